@@ -1,0 +1,97 @@
+// Internal declarations shared by the HIP translation units of libhubga.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hubga {
+
+constexpr int kMaxP = 64;          // hub lists live in LDS; p*p doubles fit easily
+constexpr int kMaxN = 8192;        // canonical kernel keeps n partial sums t_j in LDS
+constexpr int kMaxIsland = 1024;   // one island per workgroup in selection
+constexpr uint16_t kNoHub = 0xFFFF;
+constexpr int kMfmaRowsPerTile = 128;   // rows of W per batched-kernel workgroup
+constexpr int kPad = 128;               // n is padded to a multiple of this for the bf16 copies
+
+enum Precision { kFP64 = 0, kFP32 = 1, kSplitBF16 = 2 };
+
+// Device pointers of one context, carved out of the workspace.
+struct DevPtrs {
+    void *C;            // n*n, instance dtype
+    void *Ct;           // n*n transposed (== C when C is symmetric): hub rows for allocation
+    void *W;            // n*n, instance dtype
+    float *W32;         // n*n FP32 copy (FP32 mode with a binary64 instance), else null
+    uint16_t *Whi;      // n_pad*n_pad bf16 bits (split mode), else null
+    uint16_t *Wlo;
+    double *O, *D, *dsum;
+    int32_t *hubs;      // S*p current batch / children (sorted)
+    uint16_t *kidx;     // S*n_pad hub positions (kNoHub in the padding)
+    double *cost;       // S scaled cost (approximate in FP32/split modes)
+    double *parts;      // S*3 {Cc, T, Dd}
+    double *eps;        // S relative error bounds
+    int32_t *cmax;      // S largest cluster size
+    float *Ch32;        // S*p*p hub-to-hub distances (split mode)
+    double *partial;    // n_mtiles*S*p epilogue partials (split mode)
+    // GA state
+    int32_t *anc;       // R*p
+    double *anc_cost;   // R
+    double *anc_parts;  // R*3
+    int32_t *best;      // p
+    double *best_cost;  // 1 (+3 parts following)
+    int64_t *gen;       // generation counter g
+    int64_t *stats;     // 4 counters
+    int32_t *cand;      // R*m candidate child indices
+    int32_t *cand_cnt;  // R
+    double *cand_cost;  // R*m exact costs of candidates
+    double *cand_parts; // R*m*3
+    uint16_t *kidx_one; // n_pad hub positions of a single solution (best so far)
+    uint8_t *scratch;   // n bytes (middle-node selection)
+};
+
+struct Dims {
+    int n, p, S, m, R, n_pad, n_mtiles, n1, elitist, prec;
+    int c_f32, w_f32;   // instance dtypes (1 = FP32)
+    double chi, alpha, delta, scale;
+    uint64_t seed;
+};
+
+// ----------------------------------------------------------------- RNG --
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 64x64->128 multiplies with the halves crossed and xored with the round key,
+// the key bumped by two Weyl constants between rounds.
+struct U64x4 { uint64_t x[4]; };
+
+__device__ __forceinline__ U64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                               uint64_t k0, uint64_t k1)
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) { k0 += W0; k1 += W1; }
+        uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
+        uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+        uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    }
+    U64x4 o; o.x[0] = c0; o.x[1] = c1; o.x[2] = c2; o.x[3] = c3;
+    return o;
+}
+
+// Draw for (generation, index, operator, repeat) under the GA key.
+__device__ __forceinline__ U64x4 ga_draw(uint64_t seed, uint64_t g, uint64_t idx, uint64_t op, uint64_t t)
+{
+    return philox4x64_10(g, idx, op, t, seed, 0x4741ull);
+}
+
+// floor(w * m / 2^64): uniform index in [0, m).
+__device__ __forceinline__ int uindex(uint64_t w, int m) { return (int)__umul64hi(w, (uint64_t)m); }
+
+// Unit roundoffs used in the error bounds.
+constexpr double kU64 = 1.1102230246251565e-16;   // 2^-53
+constexpr double kU32 = 5.9604644775390625e-08;   // 2^-24
+constexpr double kU32Faithful = 1.1920928955078125e-07;  // 2^-23 (any faithful FP32 rounding)
+constexpr double kSplitResidual = 1.52587890625e-05;     // 2^-16: |W - hi - lo| <= 2^-16 W
+
+__host__ __device__ inline double gamma_k(double k, double u) { return k * u / (1.0 - k * u); }
+
+}  // namespace hubga

@@ -1,0 +1,294 @@
+// Per-individual fitness evaluation, one workgroup per individual (the
+// "plain" kernels; Eval of Sec. 4.3 and Sec. 5, objective (1) of Sec. 3).
+//
+// k_eval_exact: binary64 in the canonical order, bit-identical to a
+//   sequential evaluation: lane j accumulates t_j = sum_i W_ij*C[a_i][a_j]
+//   over ascending i (coalesced W rows), then T, Cc and Dd are summed in
+//   ascending order by one lane from LDS; no FMA contraction anywhere.
+//   Also used to re-evaluate selection candidates exactly.
+// k_eval_fp32: FP32 per-column sums with FMA, FP64 tree reduction of the
+//   columns; Cc and Dd come from the allocation kernel.  Returns a rigorous
+//   relative error bound with every cost.
+#include "kernels.hpp"
+
+namespace hubga {
+
+// LDS carve-up of the exact kernel: Ch (p*p doubles), buf (n doubles),
+// kid (n uint16), h (p ints).
+__host__ __device__ inline size_t exact_smem_bytes(int n, int p)
+{
+    return (size_t)p * p * 8 + (size_t)n * 8 + (((size_t)n * 2 + 15) / 16) * 16 + (size_t)kMaxP * 4;
+}
+
+// Sequential ascending sum of buf[0..n) by the calling lane.
+__device__ inline double seq_sum(const double *buf, int n)
+{
+#pragma clang fp contract(off)
+    double acc = 0.0;
+    int i = 0;
+    for (; i + 4 <= n; i += 4) {
+        double a = buf[i], b = buf[i + 1], c = buf[i + 2], d = buf[i + 3];
+        acc = acc + a;
+        acc = acc + b;
+        acc = acc + c;
+        acc = acc + d;
+    }
+    for (; i < n; ++i) acc = acc + buf[i];
+    return acc;
+}
+
+template <typename CT, typename WT>
+__device__ void eval_exact_body(const int32_t *__restrict__ hg, const uint16_t *__restrict__ krow, int n, int p,
+                                const CT *__restrict__ C, const WT *__restrict__ W, const double *__restrict__ O,
+                                const double *__restrict__ D, double chi, double alpha, double delta, double scale,
+                                double *cost_out, double *parts_out, char *smem)
+{
+#pragma clang fp contract(off)
+    double *Ch = (double *)smem;
+    double *buf = Ch + (size_t)p * p;
+    uint16_t *kid = (uint16_t *)(buf + n);
+    int *h = (int *)(smem + exact_smem_bytes(n, p) - (size_t)kMaxP * 4);
+    const int tid = threadIdx.x, nt = blockDim.x;
+    if (tid < p) h[tid] = hg[tid];
+    for (int i = tid; i < n; i += nt) kid[i] = krow[i];
+    __syncthreads();
+    for (int e = tid; e < p * p; e += nt) Ch[e] = (double)C[(size_t)h[e / p] * n + h[e % p]];
+    __syncthreads();
+    // t_j = sum over ascending i of W_ij * C[a_i][a_j], four columns per lane at a time
+    for (int j0 = tid; j0 < n; j0 += 4 * nt) {
+        int js[4], kj[4];
+        double acc[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            js[q] = j0 + q * nt;
+            kj[q] = js[q] < n ? kid[js[q]] : 0;
+            acc[q] = 0.0;
+        }
+        const bool full = js[3] < n;
+        for (int i = 0; i < n; ++i) {
+            const WT *wr = W + (size_t)i * n;
+            const double *chr = Ch + (size_t)kid[i] * p;
+            if (full) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[q] = acc[q] + (double)wr[js[q]] * chr[kj[q]];
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (js[q] < n) acc[q] = acc[q] + (double)wr[js[q]] * chr[kj[q]];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (js[q] < n) buf[js[q]] = acc[q];
+    }
+    __syncthreads();
+    double T = 0.0, Cc = 0.0, Dd = 0.0;
+    if (tid == 0) T = seq_sum(buf, n);
+    __syncthreads();
+    for (int i = tid; i < n; i += nt) buf[i] = O[i] * (double)C[(size_t)i * n + h[kid[i]]];
+    __syncthreads();
+    if (tid == 0) Cc = seq_sum(buf, n);
+    __syncthreads();
+    for (int i = tid; i < n; i += nt) buf[i] = D[i] * (double)C[(size_t)i * n + h[kid[i]]];
+    __syncthreads();
+    if (tid == 0) {
+        Dd = seq_sum(buf, n);
+        double f = ((chi * Cc) + (alpha * T)) + (delta * Dd);
+        *cost_out = f * scale;
+        if (parts_out) {
+            parts_out[0] = Cc;
+            parts_out[1] = T;
+            parts_out[2] = Dd;
+        }
+    }
+}
+
+template <typename CT, typename WT>
+__global__ __launch_bounds__(256) void k_eval_exact(const int32_t *__restrict__ hubs,
+                                                    const uint16_t *__restrict__ kidx, int count, int n, int n_pad,
+                                                    int p, const CT *__restrict__ C, const WT *__restrict__ W,
+                                                    const double *__restrict__ O, const double *__restrict__ D,
+                                                    double chi, double alpha, double delta, double scale,
+                                                    double *__restrict__ cost, double *__restrict__ parts,
+                                                    double *__restrict__ eps)
+{
+    extern __shared__ __align__(16) char smem[];
+    const int s = blockIdx.x;
+    if (s >= count) return;
+    eval_exact_body<CT, WT>(hubs + (size_t)s * p, kidx + (size_t)s * n_pad, n, p, C, W, O, D, chi, alpha, delta,
+                            scale, cost + s, parts + 3 * (size_t)s, smem);
+    if (threadIdx.x == 0 && eps) eps[s] = 0.0;
+}
+
+// Exact re-evaluation of the selection candidates of every island: block
+// (r, y) evaluates candidates y, y + gridDim.y, ... of island r.
+template <typename CT, typename WT>
+__global__ __launch_bounds__(256) void k_recheck(const int32_t *__restrict__ hubs, const uint16_t *__restrict__ kidx,
+                                                 const int32_t *__restrict__ cand, const int32_t *__restrict__ cand_cnt,
+                                                 int m, int n, int n_pad, int p, const CT *__restrict__ C,
+                                                 const WT *__restrict__ W, const double *__restrict__ O,
+                                                 const double *__restrict__ D, double chi, double alpha, double delta,
+                                                 double scale, double *__restrict__ cand_cost,
+                                                 double *__restrict__ cand_parts)
+{
+    extern __shared__ __align__(16) char smem[];
+    const int r = blockIdx.x;
+    const int cnt = cand_cnt[r];
+    for (int c = blockIdx.y; c < cnt; c += gridDim.y) {
+        const int s = cand[(size_t)r * m + c];
+        eval_exact_body<CT, WT>(hubs + (size_t)s * p, kidx + (size_t)s * n_pad, n, p, C, W, O, D, chi, alpha,
+                                delta, scale, cand_cost + (size_t)r * m + c, cand_parts + 3 * ((size_t)r * m + c),
+                                smem);
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------- FP32 --
+
+template <typename CT>
+__global__ __launch_bounds__(256) void k_eval_fp32(const int32_t *__restrict__ hubs, const uint16_t *__restrict__ kidx,
+                                                   int count, int n, int n_pad, int p, const CT *__restrict__ Ct,
+                                                   const float *__restrict__ W, double chi, double alpha,
+                                                   double delta, double scale, double eps_bound,
+                                                   double *__restrict__ cost, double *__restrict__ parts,
+                                                   double *__restrict__ eps)
+{
+#pragma clang fp contract(off)
+    extern __shared__ __align__(16) char smem[];
+    float *Ch = (float *)smem;                            // p*p
+    uint16_t *kid = (uint16_t *)(Ch + (size_t)kMaxP * kMaxP);   // n
+    __shared__ double red[256];
+    __shared__ int h[kMaxP];
+    const int s = blockIdx.x;
+    if (s >= count) return;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const uint16_t *krow = kidx + (size_t)s * n_pad;
+    if (tid < p) h[tid] = hubs[(size_t)s * p + tid];
+    for (int i = tid; i < n; i += nt) kid[i] = krow[i];
+    __syncthreads();
+    for (int e = tid; e < p * p; e += nt) Ch[e] = (float)Ct[(size_t)h[e % p] * n + h[e / p]];
+    __syncthreads();
+    double tsum = 0.0;
+    for (int j0 = tid; j0 < n; j0 += 4 * nt) {
+        int js[4], kj[4];
+        float acc[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            js[q] = j0 + q * nt;
+            kj[q] = js[q] < n ? kid[js[q]] : 0;
+            acc[q] = 0.0f;
+        }
+        const bool full = js[3] < n;
+        for (int i = 0; i < n; ++i) {
+            const float *wr = W + (size_t)i * n;
+            const float *chr = Ch + (size_t)kid[i] * p;
+            if (full) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[q] = __builtin_fmaf(wr[js[q]], chr[kj[q]], acc[q]);
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (js[q] < n) acc[q] = __builtin_fmaf(wr[js[q]], chr[kj[q]], acc[q]);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (js[q] < n) tsum = tsum + (double)acc[q];
+    }
+    red[tid] = tsum;
+    __syncthreads();
+    for (int w = nt / 2; w > 0; w >>= 1) {
+        if (tid < w) red[tid] = red[tid] + red[tid + w];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        double T = red[0];
+        double Cc = parts[3 * (size_t)s], Dd = parts[3 * (size_t)s + 2];
+        parts[3 * (size_t)s + 1] = T;
+        cost[s] = (((chi * Cc) + (alpha * T)) + (delta * Dd)) * scale;
+        if (eps) eps[s] = eps_bound;
+    }
+}
+
+// ------------------------------------------------------------ launchers --
+
+static int eval_block(int n) { return n >= 512 ? 256 : (n >= 128 ? 128 : 64); }
+
+template <typename CT, typename WT>
+static hipError_t exact_launch(const DevPtrs &P, const Dims &d, const int32_t *hubs, const uint16_t *kidx, int count,
+                               double *cost, double *parts, double *eps, hipStream_t st)
+{
+    size_t sm = exact_smem_bytes(d.n, d.p);
+    hipError_t e = hipFuncSetAttribute((const void *)k_eval_exact<CT, WT>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+    if (e != hipSuccess) return e;
+    k_eval_exact<CT, WT><<<count, eval_block(d.n), sm, st>>>(hubs, kidx, count, d.n, d.n_pad, d.p, (const CT *)P.C,
+                                                             (const WT *)P.W, P.O, P.D, d.chi, d.alpha, d.delta,
+                                                             d.scale, cost, parts, eps);
+    return hipGetLastError();
+}
+
+hipError_t launch_eval_exact(const DevPtrs &P, const Dims &d, const int32_t *hubs, const uint16_t *kidx, int count,
+                             double *cost, double *parts, double *eps, hipStream_t st)
+{
+    if (count <= 0) return hipSuccess;
+    if (d.c_f32 && d.w_f32) return exact_launch<float, float>(P, d, hubs, kidx, count, cost, parts, eps, st);
+    if (d.c_f32) return exact_launch<float, double>(P, d, hubs, kidx, count, cost, parts, eps, st);
+    if (d.w_f32) return exact_launch<double, float>(P, d, hubs, kidx, count, cost, parts, eps, st);
+    return exact_launch<double, double>(P, d, hubs, kidx, count, cost, parts, eps, st);
+}
+
+template <typename CT, typename WT>
+static hipError_t recheck_launch(const DevPtrs &P, const Dims &d, int ychunks, hipStream_t st)
+{
+    size_t sm = exact_smem_bytes(d.n, d.p);
+    hipError_t e = hipFuncSetAttribute((const void *)k_recheck<CT, WT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)sm);
+    if (e != hipSuccess) return e;
+    dim3 grid(d.R, ychunks);
+    k_recheck<CT, WT><<<grid, eval_block(d.n), sm, st>>>(P.hubs, P.kidx, P.cand, P.cand_cnt, d.m, d.n, d.n_pad, d.p,
+                                                         (const CT *)P.C, (const WT *)P.W, P.O, P.D, d.chi, d.alpha,
+                                                         d.delta, d.scale, P.cand_cost, P.cand_parts);
+    return hipGetLastError();
+}
+
+hipError_t launch_recheck(const DevPtrs &P, const Dims &d, hipStream_t st)
+{
+    int y = d.m < 4 ? d.m : 4;
+    if (d.c_f32 && d.w_f32) return recheck_launch<float, float>(P, d, y, st);
+    if (d.c_f32) return recheck_launch<float, double>(P, d, y, st);
+    if (d.w_f32) return recheck_launch<double, float>(P, d, y, st);
+    return recheck_launch<double, double>(P, d, y, st);
+}
+
+double fp32_eps_bound(int n)
+{
+    return gamma_k(n + 2.0, kU32) + gamma_k(2.0 * n + 16.0, kU64);
+}
+
+hipError_t launch_eval_fp32(const DevPtrs &P, const Dims &d, const int32_t *hubs, const uint16_t *kidx, int count,
+                            hipStream_t st)
+{
+    if (count <= 0) return hipSuccess;
+    const float *W = d.w_f32 ? (const float *)P.W : P.W32;
+    size_t sm = (size_t)kMaxP * kMaxP * 4 + (size_t)d.n * 2 + 16;
+    double eb = fp32_eps_bound(d.n);
+    hipError_t e;
+    if (d.c_f32) {
+        e = hipFuncSetAttribute((const void *)k_eval_fp32<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+        if (e != hipSuccess) return e;
+        k_eval_fp32<float><<<count, eval_block(d.n), sm, st>>>(hubs, kidx, count, d.n, d.n_pad, d.p,
+                                                                (const float *)P.Ct, W, d.chi, d.alpha, d.delta,
+                                                                d.scale, eb, P.cost, P.parts, P.eps);
+    } else {
+        e = hipFuncSetAttribute((const void *)k_eval_fp32<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)sm);
+        if (e != hipSuccess) return e;
+        k_eval_fp32<double><<<count, eval_block(d.n), sm, st>>>(hubs, kidx, count, d.n, d.n_pad, d.p,
+                                                                 (const double *)P.Ct, W, d.chi, d.alpha, d.delta,
+                                                                 d.scale, eb, P.cost, P.parts, P.eps);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace hubga

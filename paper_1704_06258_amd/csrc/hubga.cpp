@@ -1,0 +1,654 @@
+// Host side of the C ABI declared in include/hubga.h: argument validation,
+// workspace carve-up, stream-ordered kernel pipelines, state I/O.
+#include "../../include/hubga.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+
+using namespace hubga;
+
+namespace {
+
+thread_local std::string g_init_error;
+
+constexpr uint32_t kStateMagic = 0x31414748u;   // "HGA1"
+constexpr int kProfilePairs = 8192;
+
+struct Layout {
+    size_t total = 0;
+    size_t take(size_t bytes)
+    {
+        size_t off = total;
+        total += (bytes + 255) & ~(size_t)255;
+        return off;
+    }
+};
+
+bool is_valid_combo(int prec, int kern)
+{
+    return (prec == GA_PREC_FP64 && kern == GA_KERN_PLAIN) || (prec == GA_PREC_FP32 && kern == GA_KERN_PLAIN) ||
+           (prec == GA_PREC_SPLIT_BF16 && kern == GA_KERN_BATCHED);
+}
+
+bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0; }
+
+std::string check_params(const ga_params *q)
+{
+    if (!q) return "params is NULL";
+    if (q->n < 1 || q->n > kMaxN) return "n must be in [1, " + std::to_string(kMaxN) + "]";
+    if (q->p < 1 || q->p > q->n || q->p > kMaxP) return "p must be in [1, min(n, " + std::to_string(kMaxP) + ")]";
+    if (!finite_nonneg(q->chi) || !finite_nonneg(q->alpha) || !finite_nonneg(q->delta))
+        return "chi, alpha and delta must be finite and >= 0";
+    if (!std::isfinite(q->scale) || !(q->scale > 0.0)) return "scale must be finite and > 0";
+    if (q->island_size < 2 || q->island_size % 2 || q->island_size > kMaxIsland)
+        return "island_size must be even and in [2, " + std::to_string(kMaxIsland) + "]";
+    if (q->population < q->island_size || q->population % q->island_size || q->population > 65536)
+        return "population must be a multiple of island_size and <= 65536";
+    if (q->n1 < 1) return "n1 must be >= 1";
+    if (q->elitist != 0 && q->elitist != 1) return "elitist must be 0 or 1";
+    if (q->c_symmetric != 0 && q->c_symmetric != 1) return "c_symmetric must be 0 or 1";
+    if (!is_valid_combo(q->precision, q->kernel))
+        return "precision/kernel must be FP64+PLAIN, FP32+PLAIN or SPLIT_BF16+BATCHED";
+    return "";
+}
+
+Dims make_dims(const ga_params *q, ga_dtype cdt, ga_dtype wdt)
+{
+    Dims d{};
+    d.n = q->n;
+    d.p = q->p;
+    d.S = q->population;
+    d.m = q->island_size;
+    d.R = d.S / d.m;
+    d.n_pad = ((d.n + kPad - 1) / kPad) * kPad;
+    d.n_mtiles = d.n_pad / kMfmaRowsPerTile;
+    d.n1 = q->n1;
+    d.elitist = q->elitist;
+    d.prec = q->precision;
+    d.c_f32 = cdt == GA_DT_F32;
+    d.w_f32 = wdt == GA_DT_F32;
+    d.chi = q->chi;
+    d.alpha = q->alpha;
+    d.delta = q->delta;
+    d.scale = q->scale;
+    d.seed = q->seed;
+    return d;
+}
+
+// Offsets of every device buffer; the same walk sizes and carves.
+struct Carve {
+    size_t C, Ct, W, W32, Whi, Wlo, O, D, dsum, hubs, kidx, cost, parts, eps, cmax, Ch32, partial, anc, anc_cost,
+        anc_parts, best, best_cost, gen, stats, cand, cand_cnt, cand_cost, cand_parts, kidx_one, scratch;
+    size_t total;
+};
+
+Carve carve(const Dims &d, int c_symmetric)
+{
+    Layout L;
+    Carve c{};
+    const size_t n2 = (size_t)d.n * d.n, np2 = (size_t)d.n_pad * d.n_pad;
+    const size_t cs = d.c_f32 ? 4 : 8, ws = d.w_f32 ? 4 : 8;
+    const bool split = d.prec == kSplitBF16;
+    c.C = L.take(n2 * cs);
+    c.Ct = c_symmetric ? c.C : L.take(n2 * cs);
+    c.W = L.take(n2 * ws);
+    c.W32 = (d.prec == kFP32 && !d.w_f32) ? L.take(n2 * 4) : (size_t)-1;
+    c.Whi = split ? L.take(np2 * 2) : (size_t)-1;
+    c.Wlo = split ? L.take(np2 * 2) : (size_t)-1;
+    c.O = L.take((size_t)d.n * 8);
+    c.D = L.take((size_t)d.n * 8);
+    c.dsum = L.take((size_t)d.n * 8);
+    c.hubs = L.take((size_t)d.S * d.p * 4);
+    c.kidx = L.take((size_t)d.S * d.n_pad * 2);
+    c.cost = L.take((size_t)d.S * 8);
+    c.parts = L.take((size_t)d.S * 24);
+    c.eps = L.take((size_t)d.S * 8);
+    c.cmax = L.take((size_t)d.S * 4);
+    c.Ch32 = split ? L.take((size_t)d.S * d.p * d.p * 4) : (size_t)-1;
+    c.partial = split ? L.take((size_t)d.n_mtiles * d.S * d.p * 8) : (size_t)-1;
+    c.anc = L.take((size_t)d.R * d.p * 4);
+    c.anc_cost = L.take((size_t)d.R * 8);
+    c.anc_parts = L.take((size_t)d.R * 24);
+    c.best = L.take((size_t)d.p * 4);
+    c.best_cost = L.take(32);
+    c.gen = L.take(8);
+    c.stats = L.take(32);
+    c.cand = L.take((size_t)d.S * 4);
+    c.cand_cnt = L.take((size_t)d.R * 4);
+    c.cand_cost = L.take((size_t)d.S * 8);
+    c.cand_parts = L.take((size_t)d.S * 24);
+    c.kidx_one = L.take((size_t)d.n_pad * 2);
+    c.scratch = L.take((size_t)d.n);
+    c.total = L.total;
+    return c;
+}
+
+template <typename T>
+T *at(void *base, size_t off)
+{
+    return off == (size_t)-1 ? nullptr : (T *)((char *)base + off);
+}
+
+}  // namespace
+
+struct ga_ctx {
+    ga_params prm{};
+    Dims d{};
+    DevPtrs P{};
+    hipStream_t st = nullptr;
+    void *ws = nullptr;
+    bool own_ws = false;
+    bool poisoned = false;
+    std::string err;
+    // kernel timing
+    bool prof_on = false;
+    std::vector<hipEvent_t> ev;
+    int ev_used = 0;
+};
+
+namespace {
+
+ga_status fail(ga_ctx *ctx, ga_status s, const std::string &msg)
+{
+    if (ctx) {
+        ctx->err = msg;
+        if (s == GA_ERR_DEVICE) ctx->poisoned = true;
+    } else {
+        g_init_error = msg;
+    }
+    return s;
+}
+
+#define HIPCHK(expr)                                                                                      \
+    do {                                                                                                  \
+        hipError_t e_ = (expr);                                                                           \
+        if (e_ != hipSuccess) return fail(ctx, GA_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define CTXCHK(ctx)                                                     \
+    do {                                                                \
+        if (!(ctx)) return GA_ERR_INVALID;                              \
+        if ((ctx)->poisoned) return GA_ERR_STATE;                       \
+    } while (0)
+
+// Two events around the dominant evaluation kernel when profiling is on.
+void prof_events(ga_ctx *ctx, hipEvent_t *a, hipEvent_t *b)
+{
+    *a = *b = nullptr;
+    if (!ctx->prof_on || ctx->ev_used + 2 > (int)ctx->ev.size()) return;
+    *a = ctx->ev[ctx->ev_used];
+    *b = ctx->ev[ctx->ev_used + 1];
+    ctx->ev_used += 2;
+}
+
+// Evaluate `count` sorted hub sets at `hubs` (device) into P.cost / P.parts /
+// P.eps, hub positions into `kidx`.
+ga_status run_eval(ga_ctx *ctx, const int32_t *hubs, int count, uint16_t *kidx)
+{
+    const Dims &d = ctx->d;
+    const DevPtrs &P = ctx->P;
+    hipEvent_t a, b;
+    prof_events(ctx, &a, &b);
+    if (d.prec == kFP64) {
+        HIPCHK(launch_alloc(P, d, hubs, count, kidx, 0, 0, ctx->st));
+        if (a) HIPCHK(hipEventRecord(a, ctx->st));
+        HIPCHK(launch_eval_exact(P, d, hubs, kidx, count, P.cost, P.parts, P.eps, ctx->st));
+        if (b) HIPCHK(hipEventRecord(b, ctx->st));
+    } else if (d.prec == kFP32) {
+        HIPCHK(launch_alloc(P, d, hubs, count, kidx, 1, 0, ctx->st));
+        if (a) HIPCHK(hipEventRecord(a, ctx->st));
+        HIPCHK(launch_eval_fp32(P, d, hubs, kidx, count, ctx->st));
+        if (b) HIPCHK(hipEventRecord(b, ctx->st));
+    } else {
+        HIPCHK(launch_alloc(P, d, hubs, count, kidx, 1, 1, ctx->st));
+        HIPCHK(launch_eval_split(P, d, kidx, count, ctx->st, a, b));
+    }
+    return GA_OK;
+}
+
+ga_status run_generation(ga_ctx *ctx)
+{
+    const Dims &d = ctx->d;
+    const DevPtrs &P = ctx->P;
+    const int exact = d.prec == kFP64;
+    HIPCHK(launch_ga_ops(P, d, ctx->st));
+    ga_status s = run_eval(ctx, P.hubs, d.S, P.kidx);
+    if (s != GA_OK) return s;
+    HIPCHK(launch_select(P, d, exact, ctx->st));
+    HIPCHK(launch_global(P, d, exact, ctx->st));
+    return GA_OK;
+}
+
+template <typename T>
+std::string check_matrix(const void *M, int n, bool split_limit)
+{
+    const T *x = (const T *)M;
+    const size_t n2 = (size_t)n * n;
+    for (size_t k = 0; k < n2; ++k) {
+        double v = (double)x[k];
+        if (!std::isfinite(v) || v < 0.0) return "entry " + std::to_string(k) + " is negative or not finite";
+        if (split_limit && v > 3.38e38) return "entry " + std::to_string(k) + " exceeds the bf16 range";
+    }
+    return "";
+}
+
+template <typename T>
+bool symmetric(const void *M, int n)
+{
+    const T *x = (const T *)M;
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j)
+            if (x[(size_t)i * n + j] != x[(size_t)j * n + i]) return false;
+    return true;
+}
+
+std::string sort_check_hubs(const int32_t *in, int p, int n, int32_t *out)
+{
+    std::memcpy(out, in, sizeof(int32_t) * p);
+    std::sort(out, out + p);
+    if (out[0] < 0 || out[p - 1] >= n) return "hub id out of range";
+    for (int k = 1; k < p; ++k)
+        if (out[k] == out[k - 1]) return "repeated hub id";
+    return "";
+}
+
+}  // namespace
+
+extern "C" {
+
+void ga_params_default(ga_params *q, int32_t n, int32_t hubs)
+{
+    if (!q) return;
+    std::memset(q, 0, sizeof(*q));
+    q->n = n;
+    q->p = hubs;
+    q->chi = 3.0;
+    q->alpha = 0.75;
+    q->delta = 2.0;
+    q->scale = 1.0;
+    q->seed = 1;
+    q->population = 64;
+    q->island_size = 64;
+    q->n1 = 10;
+    q->elitist = 1;
+    q->precision = GA_PREC_FP64;
+    q->kernel = GA_KERN_PLAIN;
+    q->c_symmetric = 0;
+}
+
+size_t ga_workspace_bytes(const ga_params *q, ga_dtype cdt, ga_dtype wdt)
+{
+    if (!check_params(q).empty()) return 0;
+    if ((cdt != GA_DT_F64 && cdt != GA_DT_F32) || (wdt != GA_DT_F64 && wdt != GA_DT_F32)) return 0;
+    return carve(make_dims(q, cdt, wdt), q->c_symmetric).total;
+}
+
+ga_status ga_init(const ga_params *q, const void *C, ga_dtype cdt, const void *W, ga_dtype wdt, void *d_workspace,
+                  size_t ws_bytes, void *hip_stream, ga_ctx **out)
+{
+    ga_ctx *ctx = nullptr;
+    try {
+        if (!out) return fail(nullptr, GA_ERR_INVALID, "out is NULL");
+        *out = nullptr;
+        std::string e = check_params(q);
+        if (!e.empty()) return fail(nullptr, GA_ERR_INVALID, e);
+        if ((cdt != GA_DT_F64 && cdt != GA_DT_F32) || (wdt != GA_DT_F64 && wdt != GA_DT_F32))
+            return fail(nullptr, GA_ERR_INVALID, "unknown dtype");
+        if (!C || !W) return fail(nullptr, GA_ERR_INVALID, "C and W must be host arrays");
+        const bool split = q->precision == GA_PREC_SPLIT_BF16;
+        e = cdt == GA_DT_F32 ? check_matrix<float>(C, q->n, false) : check_matrix<double>(C, q->n, false);
+        if (!e.empty()) return fail(nullptr, GA_ERR_INVALID, "C: " + e);
+        e = wdt == GA_DT_F32 ? check_matrix<float>(W, q->n, split) : check_matrix<double>(W, q->n, split);
+        if (!e.empty()) return fail(nullptr, GA_ERR_INVALID, "W: " + e);
+        if (q->c_symmetric && !(cdt == GA_DT_F32 ? symmetric<float>(C, q->n) : symmetric<double>(C, q->n)))
+            return fail(nullptr, GA_ERR_INVALID, "c_symmetric is set but C is not symmetric");
+        Dims d = make_dims(q, cdt, wdt);
+        Carve c = carve(d, q->c_symmetric);
+        if (d_workspace && ws_bytes < c.total)
+            return fail(nullptr, GA_ERR_OOM,
+                        "workspace too small: " + std::to_string(ws_bytes) + " < " + std::to_string(c.total));
+        if (((uintptr_t)d_workspace) % 256)
+            return fail(nullptr, GA_ERR_INVALID, "workspace must be 256-byte aligned");
+        ctx = new (std::nothrow) ga_ctx();
+        if (!ctx) return fail(nullptr, GA_ERR_OOM, "host allocation failed");
+        ctx->prm = *q;
+        ctx->d = d;
+        ctx->st = (hipStream_t)hip_stream;
+        if (d_workspace) {
+            ctx->ws = d_workspace;
+        } else {
+            hipError_t he = hipMalloc(&ctx->ws, c.total);
+            if (he != hipSuccess) {
+                delete ctx;
+                return fail(nullptr, GA_ERR_OOM, std::string("hipMalloc: ") + hipGetErrorString(he));
+            }
+            ctx->own_ws = true;
+        }
+        void *b = ctx->ws;
+        DevPtrs &P = ctx->P;
+        P.C = at<void>(b, c.C);
+        P.Ct = at<void>(b, c.Ct);
+        P.W = at<void>(b, c.W);
+        P.W32 = at<float>(b, c.W32);
+        P.Whi = at<uint16_t>(b, c.Whi);
+        P.Wlo = at<uint16_t>(b, c.Wlo);
+        P.O = at<double>(b, c.O);
+        P.D = at<double>(b, c.D);
+        P.dsum = at<double>(b, c.dsum);
+        P.hubs = at<int32_t>(b, c.hubs);
+        P.kidx = at<uint16_t>(b, c.kidx);
+        P.cost = at<double>(b, c.cost);
+        P.parts = at<double>(b, c.parts);
+        P.eps = at<double>(b, c.eps);
+        P.cmax = at<int32_t>(b, c.cmax);
+        P.Ch32 = at<float>(b, c.Ch32);
+        P.partial = at<double>(b, c.partial);
+        P.anc = at<int32_t>(b, c.anc);
+        P.anc_cost = at<double>(b, c.anc_cost);
+        P.anc_parts = at<double>(b, c.anc_parts);
+        P.best = at<int32_t>(b, c.best);
+        P.best_cost = at<double>(b, c.best_cost);
+        P.gen = at<int64_t>(b, c.gen);
+        P.stats = at<int64_t>(b, c.stats);
+        P.cand = at<int32_t>(b, c.cand);
+        P.cand_cnt = at<int32_t>(b, c.cand_cnt);
+        P.cand_cost = at<double>(b, c.cand_cost);
+        P.cand_parts = at<double>(b, c.cand_parts);
+        P.kidx_one = at<uint16_t>(b, c.kidx_one);
+        P.scratch = at<uint8_t>(b, c.scratch);
+
+        const size_t n2 = (size_t)d.n * d.n;
+        auto dev_fail = [&](hipError_t he, const char *what) {
+            std::string m = std::string(what) + ": " + hipGetErrorString(he);
+            if (ctx->own_ws) (void)hipFree(ctx->ws);
+            delete ctx;
+            return fail(nullptr, GA_ERR_DEVICE, m);
+        };
+        hipError_t he;
+        if ((he = hipMemcpyAsync(P.C, C, n2 * (d.c_f32 ? 4 : 8), hipMemcpyHostToDevice, ctx->st)) != hipSuccess)
+            return dev_fail(he, "copy C");
+        if ((he = hipMemcpyAsync(P.W, W, n2 * (d.w_f32 ? 4 : 8), hipMemcpyHostToDevice, ctx->st)) != hipSuccess)
+            return dev_fail(he, "copy W");
+        if ((he = launch_prep(P, d, ctx->st)) != hipSuccess) return dev_fail(he, "prep");
+        // ancestor P0: middle nodes, nearest-hub allocation, exact cost (Sec. 4.1)
+        if ((he = launch_middle_nodes(P, d, P.best, P.scratch, ctx->st)) != hipSuccess)
+            return dev_fail(he, "middle nodes");
+        if ((he = launch_alloc(P, d, P.best, 1, P.kidx_one, 0, 0, ctx->st)) != hipSuccess)
+            return dev_fail(he, "alloc P0");
+        if ((he = launch_eval_exact(P, d, P.best, P.kidx_one, 1, P.best_cost, P.best_cost + 1, nullptr, ctx->st)) !=
+            hipSuccess)
+            return dev_fail(he, "eval P0");
+        if ((he = launch_init_state(P, d, ctx->st)) != hipSuccess) return dev_fail(he, "init state");
+        if ((he = hipStreamSynchronize(ctx->st)) != hipSuccess) return dev_fail(he, "sync");
+        *out = ctx;
+        return GA_OK;
+    } catch (...) {
+        if (ctx) {
+            if (ctx->own_ws) (void)hipFree(ctx->ws);
+            delete ctx;
+        }
+        return fail(nullptr, GA_ERR_OOM, "exception in ga_init");
+    }
+}
+
+ga_status ga_evaluate(ga_ctx *ctx, const int32_t *hubs, int32_t count, double *cost_out, double *parts_out,
+                      int32_t *alloc_out, double *eps_out)
+{
+    CTXCHK(ctx);
+    try {
+        const Dims &d = ctx->d;
+        if (!hubs || !cost_out || count < 0) return fail(ctx, GA_ERR_INVALID, "hubs and cost_out are required");
+        std::vector<int32_t> sorted((size_t)count * d.p);
+        for (int s = 0; s < count; ++s) {
+            std::string e = sort_check_hubs(hubs + (size_t)s * d.p, d.p, d.n, &sorted[(size_t)s * d.p]);
+            if (!e.empty()) return fail(ctx, GA_ERR_INVALID, "hub set " + std::to_string(s) + ": " + e);
+        }
+        std::vector<double> c((size_t)d.S), pr((size_t)3 * d.S), ep((size_t)d.S);
+        std::vector<uint16_t> kx;
+        if (alloc_out) kx.resize((size_t)d.S * d.n_pad);
+        for (int s0 = 0; s0 < count; s0 += d.S) {
+            const int cnt = std::min(d.S, count - s0);
+            HIPCHK(hipMemcpyAsync(ctx->P.hubs, &sorted[(size_t)s0 * d.p], sizeof(int32_t) * cnt * d.p,
+                                  hipMemcpyHostToDevice, ctx->st));
+            ga_status st = run_eval(ctx, ctx->P.hubs, cnt, ctx->P.kidx);
+            if (st != GA_OK) return st;
+            HIPCHK(hipMemcpyAsync(c.data(), ctx->P.cost, 8 * cnt, hipMemcpyDeviceToHost, ctx->st));
+            HIPCHK(hipMemcpyAsync(pr.data(), ctx->P.parts, 24 * cnt, hipMemcpyDeviceToHost, ctx->st));
+            HIPCHK(hipMemcpyAsync(ep.data(), ctx->P.eps, 8 * cnt, hipMemcpyDeviceToHost, ctx->st));
+            if (alloc_out)
+                HIPCHK(hipMemcpyAsync(kx.data(), ctx->P.kidx, 2 * (size_t)cnt * d.n_pad, hipMemcpyDeviceToHost,
+                                      ctx->st));
+            HIPCHK(hipStreamSynchronize(ctx->st));
+            for (int s = 0; s < cnt; ++s) {
+                cost_out[s0 + s] = c[s];
+                if (parts_out)
+                    for (int q = 0; q < 3; ++q) parts_out[3 * (size_t)(s0 + s) + q] = pr[3 * (size_t)s + q];
+                if (eps_out) eps_out[s0 + s] = ep[s];
+                if (alloc_out) {
+                    const int32_t *h = &sorted[(size_t)(s0 + s) * d.p];
+                    for (int i = 0; i < d.n; ++i)
+                        alloc_out[(size_t)(s0 + s) * d.n + i] = h[kx[(size_t)s * d.n_pad + i]];
+                }
+            }
+        }
+        return GA_OK;
+    } catch (...) {
+        return fail(ctx, GA_ERR_OOM, "host allocation failed in ga_evaluate");
+    }
+}
+
+ga_status ga_evaluate_dev(ga_ctx *ctx, const int32_t *d_hubs, int32_t count, uint16_t *d_kidx, double *d_cost)
+{
+    CTXCHK(ctx);
+    const Dims &d = ctx->d;
+    if (!d_hubs || !d_cost || count < 1 || count > d.S)
+        return fail(ctx, GA_ERR_INVALID, "need 1 <= count <= population and device hubs/cost");
+    HIPCHK(launch_copy_clamp(d_hubs, ctx->P.hubs, count * d.p, d.n, ctx->st));
+    ga_status s = run_eval(ctx, ctx->P.hubs, count, ctx->P.kidx);
+    if (s != GA_OK) return s;
+    HIPCHK(hipMemcpyAsync(d_cost, ctx->P.cost, 8 * (size_t)count, hipMemcpyDeviceToDevice, ctx->st));
+    if (d_kidx)
+        HIPCHK(hipMemcpy2DAsync(d_kidx, 2 * (size_t)d.n, ctx->P.kidx, 2 * (size_t)d.n_pad, 2 * (size_t)d.n, count,
+                                hipMemcpyDeviceToDevice, ctx->st));
+    return GA_OK;
+}
+
+ga_status ga_step(ga_ctx *ctx, int32_t generations)
+{
+    CTXCHK(ctx);
+    if (generations < 0) return fail(ctx, GA_ERR_INVALID, "generations must be >= 0");
+    for (int g = 0; g < generations; ++g) {
+        ga_status s = run_generation(ctx);
+        if (s != GA_OK) return s;
+    }
+    return GA_OK;
+}
+
+ga_status ga_best(ga_ctx *ctx, int32_t *hubs_out, int32_t *alloc_out, double *cost_out, double *parts_out,
+                  int64_t *generation_out)
+{
+    CTXCHK(ctx);
+    const Dims &d = ctx->d;
+    std::vector<int32_t> h(d.p);
+    double bc[4];
+    int64_t g;
+    std::vector<uint16_t> kx;
+    if (alloc_out) {
+        HIPCHK(launch_alloc(ctx->P, d, ctx->P.best, 1, ctx->P.kidx_one, 0, 0, ctx->st));
+        kx.resize(d.n_pad);
+        HIPCHK(hipMemcpyAsync(kx.data(), ctx->P.kidx_one, 2 * (size_t)d.n_pad, hipMemcpyDeviceToHost, ctx->st));
+    }
+    HIPCHK(hipMemcpyAsync(h.data(), ctx->P.best, 4 * (size_t)d.p, hipMemcpyDeviceToHost, ctx->st));
+    HIPCHK(hipMemcpyAsync(bc, ctx->P.best_cost, 32, hipMemcpyDeviceToHost, ctx->st));
+    HIPCHK(hipMemcpyAsync(&g, ctx->P.gen, 8, hipMemcpyDeviceToHost, ctx->st));
+    HIPCHK(hipStreamSynchronize(ctx->st));
+    if (hubs_out) std::memcpy(hubs_out, h.data(), 4 * (size_t)d.p);
+    if (cost_out) *cost_out = bc[0];
+    if (parts_out) std::memcpy(parts_out, bc + 1, 24);
+    if (generation_out) *generation_out = g;
+    if (alloc_out)
+        for (int i = 0; i < d.n; ++i) alloc_out[i] = h[kx[i]];
+    return GA_OK;
+}
+
+ga_status ga_solve(ga_ctx *ctx, int32_t generations, int32_t *hubs_out, int32_t *alloc_out, double *cost_out)
+{
+    ga_status s = ga_step(ctx, generations);
+    if (s != GA_OK) return s;
+    return ga_best(ctx, hubs_out, alloc_out, cost_out, nullptr, nullptr);
+}
+
+ga_status ga_population(ga_ctx *ctx, int32_t *hubs_out, double *cost_out)
+{
+    CTXCHK(ctx);
+    const Dims &d = ctx->d;
+    if (hubs_out) HIPCHK(hipMemcpyAsync(hubs_out, ctx->P.hubs, 4 * (size_t)d.S * d.p, hipMemcpyDeviceToHost, ctx->st));
+    if (cost_out) HIPCHK(hipMemcpyAsync(cost_out, ctx->P.cost, 8 * (size_t)d.S, hipMemcpyDeviceToHost, ctx->st));
+    HIPCHK(hipStreamSynchronize(ctx->st));
+    return GA_OK;
+}
+
+ga_status ga_ancestors(ga_ctx *ctx, int32_t *hubs_out, double *cost_out)
+{
+    CTXCHK(ctx);
+    const Dims &d = ctx->d;
+    if (hubs_out) HIPCHK(hipMemcpyAsync(hubs_out, ctx->P.anc, 4 * (size_t)d.R * d.p, hipMemcpyDeviceToHost, ctx->st));
+    if (cost_out) HIPCHK(hipMemcpyAsync(cost_out, ctx->P.anc_cost, 8 * (size_t)d.R, hipMemcpyDeviceToHost, ctx->st));
+    HIPCHK(hipStreamSynchronize(ctx->st));
+    return GA_OK;
+}
+
+// State blob: header {magic, n, p, S, m, seed, g} then anc (R*p int32),
+// anc_cost (R), anc_parts (3R), best (p int32), best_cost + parts (4).
+ga_status ga_get_state(ga_ctx *ctx, void *buf, size_t *bytes)
+{
+    CTXCHK(ctx);
+    if (!bytes) return fail(ctx, GA_ERR_INVALID, "bytes is NULL");
+    const Dims &d = ctx->d;
+    const size_t hdr = 64;
+    const size_t need = hdr + 4 * (size_t)d.R * d.p + 8 * (size_t)d.R + 24 * (size_t)d.R + 4 * (size_t)d.p + 32;
+    if (!buf) {
+        *bytes = need;
+        return GA_OK;
+    }
+    if (*bytes < need) return fail(ctx, GA_ERR_INVALID, "state buffer too small");
+    char *o = (char *)buf;
+    std::memset(o, 0, hdr);
+    uint32_t hv[5] = {kStateMagic, (uint32_t)d.n, (uint32_t)d.p, (uint32_t)d.S, (uint32_t)d.m};
+    std::memcpy(o, hv, sizeof(hv));
+    std::memcpy(o + 24, &ctx->prm.seed, 8);
+    char *q = o + hdr;
+    HIPCHK(hipMemcpyAsync(o + 32, ctx->P.gen, 8, hipMemcpyDeviceToHost, ctx->st));
+    HIPCHK(hipMemcpyAsync(q, ctx->P.anc, 4 * (size_t)d.R * d.p, hipMemcpyDeviceToHost, ctx->st));
+    q += 4 * (size_t)d.R * d.p;
+    HIPCHK(hipMemcpyAsync(q, ctx->P.anc_cost, 8 * (size_t)d.R, hipMemcpyDeviceToHost, ctx->st));
+    q += 8 * (size_t)d.R;
+    HIPCHK(hipMemcpyAsync(q, ctx->P.anc_parts, 24 * (size_t)d.R, hipMemcpyDeviceToHost, ctx->st));
+    q += 24 * (size_t)d.R;
+    HIPCHK(hipMemcpyAsync(q, ctx->P.best, 4 * (size_t)d.p, hipMemcpyDeviceToHost, ctx->st));
+    q += 4 * (size_t)d.p;
+    HIPCHK(hipMemcpyAsync(q, ctx->P.best_cost, 32, hipMemcpyDeviceToHost, ctx->st));
+    HIPCHK(hipStreamSynchronize(ctx->st));
+    *bytes = need;
+    return GA_OK;
+}
+
+ga_status ga_set_state(ga_ctx *ctx, const void *buf, size_t bytes)
+{
+    CTXCHK(ctx);
+    const Dims &d = ctx->d;
+    const size_t hdr = 64;
+    const size_t need = hdr + 4 * (size_t)d.R * d.p + 8 * (size_t)d.R + 24 * (size_t)d.R + 4 * (size_t)d.p + 32;
+    if (!buf || bytes != need) return fail(ctx, GA_ERR_STATE, "state blob has the wrong size");
+    const char *o = (const char *)buf;
+    uint32_t hv[5];
+    uint64_t seed;
+    std::memcpy(hv, o, sizeof(hv));
+    std::memcpy(&seed, o + 24, 8);
+    if (hv[0] != kStateMagic || hv[1] != (uint32_t)d.n || hv[2] != (uint32_t)d.p || hv[3] != (uint32_t)d.S ||
+        hv[4] != (uint32_t)d.m || seed != ctx->prm.seed)
+        return fail(ctx, GA_ERR_STATE, "state blob belongs to a different configuration");
+    const char *q = o + hdr;
+    HIPCHK(hipMemcpyAsync(ctx->P.gen, o + 32, 8, hipMemcpyHostToDevice, ctx->st));
+    HIPCHK(hipMemcpyAsync(ctx->P.anc, q, 4 * (size_t)d.R * d.p, hipMemcpyHostToDevice, ctx->st));
+    q += 4 * (size_t)d.R * d.p;
+    HIPCHK(hipMemcpyAsync(ctx->P.anc_cost, q, 8 * (size_t)d.R, hipMemcpyHostToDevice, ctx->st));
+    q += 8 * (size_t)d.R;
+    HIPCHK(hipMemcpyAsync(ctx->P.anc_parts, q, 24 * (size_t)d.R, hipMemcpyHostToDevice, ctx->st));
+    q += 24 * (size_t)d.R;
+    HIPCHK(hipMemcpyAsync(ctx->P.best, q, 4 * (size_t)d.p, hipMemcpyHostToDevice, ctx->st));
+    q += 4 * (size_t)d.p;
+    HIPCHK(hipMemcpyAsync(ctx->P.best_cost, q, 32, hipMemcpyHostToDevice, ctx->st));
+    HIPCHK(hipStreamSynchronize(ctx->st));
+    return GA_OK;
+}
+
+ga_status ga_stats(ga_ctx *ctx, int64_t stats[4])
+{
+    CTXCHK(ctx);
+    if (!stats) return fail(ctx, GA_ERR_INVALID, "stats is NULL");
+    HIPCHK(hipMemcpyAsync(stats, ctx->P.stats, 32, hipMemcpyDeviceToHost, ctx->st));
+    HIPCHK(hipStreamSynchronize(ctx->st));
+    return GA_OK;
+}
+
+ga_status ga_profile_enable(ga_ctx *ctx, int32_t enable)
+{
+    CTXCHK(ctx);
+    if (enable) {
+        HIPCHK(hipStreamSynchronize(ctx->st));
+        if (ctx->ev.empty()) {
+            ctx->ev.resize(kProfilePairs * 2);
+            for (auto &e : ctx->ev) HIPCHK(hipEventCreate(&e));
+        }
+        ctx->ev_used = 0;
+    }
+    ctx->prof_on = enable != 0;
+    return GA_OK;
+}
+
+ga_status ga_profile_read(ga_ctx *ctx, double *ms_total, int64_t *launches)
+{
+    CTXCHK(ctx);
+    HIPCHK(hipStreamSynchronize(ctx->st));
+    double tot = 0.0;
+    for (int k = 0; k + 1 < ctx->ev_used; k += 2) {
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, ctx->ev[k], ctx->ev[k + 1]));
+        tot += ms;
+    }
+    if (ms_total) *ms_total = tot;
+    if (launches) *launches = ctx->ev_used / 2;
+    return GA_OK;
+}
+
+const char *ga_status_str(ga_status s)
+{
+    switch (s) {
+    case GA_OK: return "GA_OK";
+    case GA_ERR_INVALID: return "GA_ERR_INVALID";
+    case GA_ERR_OOM: return "GA_ERR_OOM";
+    case GA_ERR_DEVICE: return "GA_ERR_DEVICE";
+    case GA_ERR_STATE: return "GA_ERR_STATE";
+    }
+    return "GA_UNKNOWN";
+}
+
+const char *ga_last_error(const ga_ctx *ctx) { return ctx ? ctx->err.c_str() : g_init_error.c_str(); }
+
+void ga_free(ga_ctx *ctx)
+{
+    if (!ctx) return;
+    (void)hipStreamSynchronize(ctx->st);
+    for (auto &e : ctx->ev) (void)hipEventDestroy(e);
+    if (ctx->own_ws) (void)hipFree(ctx->ws);
+    delete ctx;
+}
+
+}  // extern "C"

@@ -1,0 +1,35 @@
+// Launchers of the device kernels of libhubga (internal).
+#pragma once
+#include "common.hpp"
+
+namespace hubga {
+
+// instance preparation (prep.hip)
+hipError_t launch_prep(const DevPtrs &P, const Dims &d, hipStream_t st);
+hipError_t launch_middle_nodes(const DevPtrs &P, const Dims &d, int32_t *hubs_out, uint8_t *scratch, hipStream_t st);
+
+// nearest-hub allocation (alloc.hip)
+hipError_t launch_alloc(const DevPtrs &P, const Dims &d, const int32_t *hubs, int count, uint16_t *kidx,
+                        int want_sums, int want_ch, hipStream_t st);
+hipError_t launch_copy_clamp(const int32_t *src, int32_t *dst, int total, int n, hipStream_t st);
+
+// per-individual evaluation (eval_plain.hip)
+hipError_t launch_eval_exact(const DevPtrs &P, const Dims &d, const int32_t *hubs, const uint16_t *kidx, int count,
+                             double *cost, double *parts, double *eps, hipStream_t st);
+hipError_t launch_eval_fp32(const DevPtrs &P, const Dims &d, const int32_t *hubs, const uint16_t *kidx, int count,
+                            hipStream_t st);
+hipError_t launch_recheck(const DevPtrs &P, const Dims &d, hipStream_t st);
+double fp32_eps_bound(int n);
+
+// batched matrix-core evaluation (eval_mfma.hip)
+hipError_t launch_eval_split(const DevPtrs &P, const Dims &d, const uint16_t *kidx, int count, hipStream_t st,
+                             hipEvent_t ev0, hipEvent_t ev1);
+int mfma_row_tiles(const Dims &d);
+
+// GA (ga_ops.hip, select.hip)
+hipError_t launch_ga_ops(const DevPtrs &P, const Dims &d, hipStream_t st);
+hipError_t launch_select(const DevPtrs &P, const Dims &d, int exact, hipStream_t st);
+hipError_t launch_global(const DevPtrs &P, const Dims &d, int exact, hipStream_t st);
+hipError_t launch_init_state(const DevPtrs &P, const Dims &d, hipStream_t st);
+
+}  // namespace hubga

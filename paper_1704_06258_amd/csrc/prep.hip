@@ -1,0 +1,182 @@
+// Instance preparation, once per context (copy of C and W to GPU global
+// memory, Sec. 5 host steps; middle nodes of Sec. 4.1):
+//   O_i = sum_j W_ij, D_j = sum_i W_ij, d_i = sum_j C_ij in binary64, ascending;
+//   transposed C for coalesced hub-row reads;
+//   FP32 copy of W; bf16 hi/lo split of W padded with zeros to n_pad.
+#include "kernels.hpp"
+
+namespace hubga {
+
+template <typename T>
+__global__ void k_row_sums(const T *__restrict__ M, int n, double *__restrict__ out)
+{
+#pragma clang fp contract(off)
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const T *row = M + (size_t)i * n;
+    double acc = 0.0;
+    for (int j = 0; j < n; ++j) acc = acc + (double)row[j];
+    out[i] = acc;
+}
+
+template <typename T>
+__global__ void k_col_sums(const T *__restrict__ M, int n, double *__restrict__ out)
+{
+#pragma clang fp contract(off)
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    double acc = 0.0;
+    for (int i = 0; i < n; ++i) acc = acc + (double)M[(size_t)i * n + j];
+    out[j] = acc;
+}
+
+template <typename T>
+__global__ void k_transpose(const T *__restrict__ src, T *__restrict__ dst, int n)
+{
+    __shared__ T tile[32][33];
+    int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+    int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8 threads
+    for (int r = ty; r < 32; r += 8) {
+        int i = by + r, j = bx + tx;
+        if (i < n && j < n) tile[r][tx] = src[(size_t)i * n + j];
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        int i = bx + r, j = by + tx;
+        if (i < n && j < n) dst[(size_t)i * n + j] = tile[tx][r];
+    }
+}
+
+// Round-to-nearest-even of a binary64 value to bfloat16 (8 significant bits,
+// exponent range of binary32), in one rounding step: scale by the bf16
+// quantum of x's binade, round to an integer with ties to even, scale back.
+__device__ inline uint16_t bf16_rne_bits(double x)
+{
+    if (x == 0.0) return 0;
+    double ax = fabs(x);
+    int e = ilogb(ax);                 // ax in [2^e, 2^(e+1))
+    int qe = (e < -126 ? -126 : e) - 7;
+    double r = rint(ldexp(ax, -qe));   // exact scaling, RNE to integer
+    float v = (float)ldexp(r, qe);     // exactly representable in bf16, hence in binary32
+    uint32_t b = __float_as_uint(v) >> 16;
+    return (uint16_t)(b | (x < 0.0 ? 0x8000u : 0u));
+}
+
+__device__ inline double bf16_to_double(uint16_t b) { return (double)__uint_as_float(((uint32_t)b) << 16); }
+
+template <typename T>
+__global__ void k_split_bf16(const T *__restrict__ W, int n, int n_pad, uint16_t *__restrict__ hi,
+                             uint16_t *__restrict__ lo)
+{
+#pragma clang fp contract(off)
+    size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t total = (size_t)n_pad * n_pad;
+    if (idx >= total) return;
+    int i = (int)(idx / n_pad), j = (int)(idx % n_pad);
+    uint16_t h = 0, l = 0;
+    if (i < n && j < n) {
+        double x = (double)W[(size_t)i * n + j];
+        h = bf16_rne_bits(x);
+        double rem = x - bf16_to_double(h);   // exact (Sterbenz)
+        l = bf16_rne_bits(rem);
+    }
+    hi[idx] = h;
+    lo[idx] = l;
+}
+
+__global__ void k_to_f32(const double *__restrict__ src, float *__restrict__ dst, size_t count)
+{
+    size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < count) dst[idx] = (float)src[idx];
+}
+
+// The p nodes with the smallest d_i (ties to the smaller index), sorted.
+// One workgroup; p rounds of a (value, index) argmin over the untaken nodes.
+__global__ void k_middle_select(const double *__restrict__ d, int n, int p, int32_t *__restrict__ hubs,
+                                uint8_t *__restrict__ taken)
+{
+    __shared__ double sv[1024];
+    __shared__ int si[1024];
+    int tid = threadIdx.x;
+    for (int i = tid; i < n; i += blockDim.x) taken[i] = 0;
+    __syncthreads();
+    for (int k = 0; k < p; ++k) {
+        double bv = 0.0;
+        int bi = -1;
+        for (int i = tid; i < n; i += blockDim.x) {
+            if (taken[i]) continue;
+            double v = d[i];
+            if (bi < 0 || v < bv) { bv = v; bi = i; }   // ascending i: ties keep the smaller i
+        }
+        sv[tid] = bv;
+        si[tid] = bi;
+        __syncthreads();
+        for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+            if (tid < s) {
+                int oi = si[tid + s];
+                double ov = sv[tid + s];
+                int mi = si[tid];
+                if (oi >= 0 && (mi < 0 || ov < sv[tid] || (ov == sv[tid] && oi < mi))) {
+                    sv[tid] = ov;
+                    si[tid] = oi;
+                }
+            }
+            __syncthreads();
+        }
+        if (tid == 0) taken[si[0]] = 1;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        int c = 0;
+        for (int i = 0; i < n && c < p; ++i)
+            if (taken[i]) hubs[c++] = i;
+    }
+}
+
+// ------------------------------------------------------------ launchers --
+
+hipError_t launch_prep(const DevPtrs &P, const Dims &d, hipStream_t st)
+{
+    const int n = d.n;
+    const int tb = 256;
+    const int nb = (n + tb - 1) / tb;
+    if (d.w_f32) {
+        k_row_sums<float><<<nb, tb, 0, st>>>((const float *)P.W, n, P.O);
+        k_col_sums<float><<<nb, tb, 0, st>>>((const float *)P.W, n, P.D);
+    } else {
+        k_row_sums<double><<<nb, tb, 0, st>>>((const double *)P.W, n, P.O);
+        k_col_sums<double><<<nb, tb, 0, st>>>((const double *)P.W, n, P.D);
+    }
+    if (d.c_f32)
+        k_row_sums<float><<<nb, tb, 0, st>>>((const float *)P.C, n, P.dsum);
+    else
+        k_row_sums<double><<<nb, tb, 0, st>>>((const double *)P.C, n, P.dsum);
+    if (P.Ct != P.C) {
+        dim3 g((n + 31) / 32, (n + 31) / 32);
+        if (d.c_f32)
+            k_transpose<float><<<g, 256, 0, st>>>((const float *)P.C, (float *)P.Ct, n);
+        else
+            k_transpose<double><<<g, 256, 0, st>>>((const double *)P.C, (double *)P.Ct, n);
+    }
+    if (P.W32) {
+        size_t cnt = (size_t)n * n;
+        k_to_f32<<<(unsigned)((cnt + tb - 1) / tb), tb, 0, st>>>((const double *)P.W, P.W32, cnt);
+    }
+    if (P.Whi) {
+        size_t cnt = (size_t)d.n_pad * d.n_pad;
+        unsigned g = (unsigned)((cnt + tb - 1) / tb);
+        if (d.w_f32)
+            k_split_bf16<float><<<g, tb, 0, st>>>((const float *)P.W, n, d.n_pad, P.Whi, P.Wlo);
+        else
+            k_split_bf16<double><<<g, tb, 0, st>>>((const double *)P.W, n, d.n_pad, P.Whi, P.Wlo);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_middle_nodes(const DevPtrs &P, const Dims &d, int32_t *hubs_out, uint8_t *scratch, hipStream_t st)
+{
+    k_middle_select<<<1, 1024, 0, st>>>(P.dsum, d.n, d.p, hubs_out, scratch);
+    return hipGetLastError();
+}
+
+}  // namespace hubga

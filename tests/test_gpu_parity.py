@@ -1,0 +1,251 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Bars (stated per test):
+* FP64 mode: costs, parts and allocations bit-identical to the oracle;
+* FP32 / split-bf16 modes: |cost - oracle| <= eps * oracle with the returned
+  rigorous bound eps, and for split-bf16 on the clustered n=1000, p=20
+  instance a measured relative error <= 1e-6;
+* GA: hub sets, exact costs and best-so-far bit-identical to the oracle's
+  trajectory for the same seed, in every precision (certified selection).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1704_06258_amd import hubga
+from paper_1704_06258_amd import instances as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    hubga.lib()   # fails loudly if the HIP library is not built
+    yield
+
+
+def make(inst, **kw):
+    return hubga.Solver(inst.C, inst.W, inst.p, chi=inst.chi, alpha=inst.alpha, delta=inst.delta,
+                        scale=inst.scale, **kw)
+
+
+def ref_eval(inst, hubs, want_alloc=False):
+    return oracle.evaluate(inst.C64(), inst.W64(), hubs, inst.chi, inst.alpha, inst.delta, inst.scale,
+                           want_alloc=want_alloc)
+
+
+EXACT_CASES = [
+    ("small_n25_p3", lambda: I.small(), 64),
+    ("medium_n200_p10", lambda: I.medium(), 200),
+    ("asym_n77_p5_integer_ties", lambda: I.random_asymmetric(seed=3, n=77, p=5, integer=True), 96),
+    ("ragged_n129_p7", lambda: I.uniform(seed=11, n=129, p=7), 70),
+    ("n1_p1", lambda: I.uniform(seed=12, n=1, p=1), 2),
+    ("n2_p2", lambda: I.uniform(seed=13, n=2, p=2), 2),
+    ("p_equals_n_64", lambda: I.uniform(seed=14, n=64, p=64), 2),
+    ("p1_n300", lambda: I.uniform(seed=15, n=300, p=1), 40),
+    ("clustered_n1000_p20", lambda: I.clustered(), 48),
+]
+
+
+@pytest.mark.parametrize("name,mk,count", EXACT_CASES, ids=[c[0] for c in EXACT_CASES])
+def test_evaluate_fp64_bit_exact(name, mk, count):
+    inst = mk()
+    hubs = I.random_hub_sets(1, inst.n, inst.p, count)
+    ref_c, ref_p, ref_a = ref_eval(inst, hubs, want_alloc=True)
+    with make(inst, population=64 if count > 2 else 2, island_size=2 if count <= 2 else None) as s:
+        out = s.evaluate(hubs, want_alloc=True)
+    assert np.array_equal(out["alloc"], ref_a)
+    assert np.array_equal(out["cost"], ref_c), np.max(np.abs(out["cost"] - ref_c) / ref_c)
+    assert np.array_equal(out["parts"], ref_p)
+    assert np.all(out["eps"] == 0.0)
+
+
+def test_evaluate_fp64_float32_instance():
+    inst = I.large(seed=4, n=300, p=9)       # FP32 C and W
+    hubs = I.random_hub_sets(2, inst.n, inst.p, 64)
+    ref_c, ref_p, ref_a = ref_eval(inst, hubs, want_alloc=True)
+    with make(inst, population=64) as s:
+        out = s.evaluate(hubs, want_alloc=True)
+    assert np.array_equal(out["alloc"], ref_a) and np.array_equal(out["cost"], ref_c)
+
+
+def test_evaluate_unsorted_input_and_chunking():
+    inst = I.medium(seed=5, n=90, p=6)
+    hubs = I.random_hub_sets(3, inst.n, inst.p, 150)
+    shuffled = np.ascontiguousarray(hubs[:, ::-1])
+    ref_c, _ = ref_eval(inst, hubs)
+    with make(inst, population=64) as s:     # 150 sets -> chunks of 64
+        out = s.evaluate(shuffled)
+        with pytest.raises(hubga.HubGAError):
+            s.evaluate(np.array([[1, 1, 2, 3, 4, 5]], np.int32))
+        with pytest.raises(hubga.HubGAError):
+            s.evaluate(np.array([[0, 1, 2, 3, 4, 90]], np.int32))
+        out2 = s.evaluate(hubs[:3])          # the context survives invalid input
+    assert np.array_equal(out["cost"], ref_c)
+    assert np.array_equal(out2["cost"], ref_c[:3])
+
+
+@pytest.mark.parametrize("name,mk,count", [("medium", lambda: I.medium(), 256),
+                                           ("clustered", lambda: I.clustered(), 128),
+                                           ("asym_ragged", lambda: I.random_asymmetric(seed=9, n=131, p=6), 64)])
+def test_evaluate_fp32_within_bound(name, mk, count):
+    inst = mk()
+    hubs = I.random_hub_sets(4, inst.n, inst.p, count)
+    ref_c, ref_p = ref_eval(inst, hubs)
+    with make(inst, population=count, precision="fp32") as s:
+        out = s.evaluate(hubs)
+    err = np.abs(out["cost"] - ref_c) / ref_c
+    assert np.all(out["eps"] > 0) and np.all(err <= out["eps"]), (err.max(), out["eps"].min())
+
+
+SPLIT_CASES = [
+    ("clustered_n1000_p20", lambda: I.clustered(), 512),
+    ("small_n25_p3", lambda: I.small(), 64),
+    ("ragged_n129_p7_count37", lambda: I.uniform(seed=21, n=129, p=7), 37),
+    ("p1_n200", lambda: I.uniform(seed=22, n=200, p=1), 64),
+    ("p64_n300", lambda: I.uniform(seed=23, n=300, p=64), 64),
+    ("asym_n140_p9", lambda: I.random_asymmetric(seed=24, n=140, p=9), 64),
+    ("float32_n384_p50", lambda: I.large(seed=4, n=384, p=50), 64),
+]
+
+
+@pytest.mark.parametrize("name,mk,count", SPLIT_CASES, ids=[c[0] for c in SPLIT_CASES])
+def test_evaluate_split_bf16_within_bound(name, mk, count):
+    inst = mk()
+    hubs = I.random_hub_sets(5, inst.n, inst.p, count)
+    ref_c, ref_p = ref_eval(inst, hubs)
+    pop = max(2, count + (count % 2))
+    with make(inst, population=pop, island_size=2, precision="split_bf16") as s:
+        out = s.evaluate(hubs)
+    err = np.abs(out["cost"] - ref_c) / ref_c
+    assert np.all(err <= out["eps"]), (err.max(), out["eps"].min())
+    assert np.all(out["eps"] < 1e-3)
+    # collection and distribution sums are binary64 tree sums
+    assert np.allclose(out["parts"][:, [0, 2]], ref_p[:, [0, 2]], rtol=1e-12, atol=0)
+    if name.startswith("clustered"):
+        assert err.max() <= 1e-6, err.max()
+
+
+def test_split_duplicates_are_bit_identical():
+    inst = I.clustered()
+    base = I.random_hub_sets(6, inst.n, inst.p, 8)
+    hubs = np.concatenate([base, base[::-1], base[[3]] .repeat(16, axis=0)])   # 32 sets, scattered duplicates
+    with make(inst, population=32, island_size=2, precision="split_bf16") as s:
+        out = s.evaluate(hubs)
+    c = out["cost"]
+    assert np.array_equal(c[:8], c[8:16][::-1])
+    assert np.all(c[16:] == c[3])
+
+
+def test_evaluate_dev_matches_host():
+    import torch
+    inst = I.medium()
+    hubs = I.random_hub_sets(7, inst.n, inst.p, 64)
+    with make(inst, population=64, precision="split_bf16") as s:
+        host = s.evaluate(hubs)["cost"]
+        d_hubs = torch.from_numpy(hubs).to(s.device)
+        d_kidx = torch.empty((64, inst.n), dtype=torch.int16, device=s.device)
+        dev = s.evaluate_dev(d_hubs, d_kidx=d_kidx)
+        torch.cuda.synchronize()
+        kidx = d_kidx.cpu().numpy().astype(np.uint16)
+    assert np.array_equal(dev.cpu().numpy(), host)
+    _, ref_k = oracle.allocate(inst.C64(), hubs[5])
+    assert np.array_equal(kidx[5], ref_k)
+
+
+# ------------------------------------------------------------------- GA --
+
+def oracle_trajectory(inst, G, *, S, m, n1, seed, elitist=1):
+    st = oracle.ga_init(inst.C64(), inst.W64(), inst.p, S, m, inst.chi, inst.alpha, inst.delta, inst.scale)
+    oracle.ga_run(inst.C64(), inst.W64(), st, G, S=S, m=m, n1=n1, seed=seed, chi=inst.chi, alpha=inst.alpha,
+                  delta=inst.delta, scale=inst.scale, elitist=elitist)
+    return st
+
+
+def assert_same_state(s, st):
+    anc, anc_cost = s.ancestors()
+    best = s.best()
+    assert np.array_equal(anc, st.anc)
+    assert np.array_equal(anc_cost, st.anc_cost)
+    assert np.array_equal(best["hubs"], st.best) and best["cost"] == st.best_cost[0]
+    assert np.array_equal(best["parts"], st.best_parts)
+    assert best["generation"] == st.gen[0]
+
+
+def test_initial_state_is_oracle_p0():
+    inst = I.medium()
+    st = oracle.ga_init(inst.C64(), inst.W64(), inst.p, 1024, 64, inst.chi, inst.alpha, inst.delta)
+    with make(inst, population=1024, island_size=64) as s:
+        assert_same_state(s, st)
+        b = s.best()
+        a, _ = oracle.allocate(inst.C64(), st.best)
+        assert np.array_equal(b["alloc"], a)
+
+
+def test_generation0_children_match_oracle():
+    for inst, S, m in [(I.small(), 64, 16), (I.medium(), 1024, 64), (I.uniform(seed=3, n=40, p=40), 8, 4)]:
+        with make(inst, population=S, island_size=m, seed=7) as s:
+            s.step(1)
+            hubs, _ = s.population()
+        st = oracle.ga_init(inst.C64(), inst.W64(), inst.p, S, m, inst.chi, inst.alpha, inst.delta)
+        ref = oracle.ga_children(inst.n, inst.p, S, m, 7, 0, st.anc)
+        assert np.array_equal(hubs, ref)
+
+
+@pytest.mark.parametrize("m,elitist", [(64, 1), (16, 1), (16, 0)])
+def test_trajectory_small_fp64_100_generations(m, elitist):
+    inst = I.small()
+    st = oracle_trajectory(inst, 100, S=64, m=m, n1=10, seed=1, elitist=elitist)
+    with make(inst, population=64, island_size=m, n1=10, seed=1, elitist=bool(elitist)) as s:
+        s.step(100)
+        assert_same_state(s, st)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+def test_trajectory_medium_certified(precision):
+    inst = I.medium()
+    st = oracle_trajectory(inst, 25, S=1024, m=64, n1=10, seed=1)
+    with make(inst, population=1024, island_size=64, n1=10, seed=1, precision=precision) as s:
+        s.step(25)
+        assert_same_state(s, st)
+        stats = s.stats()
+    assert stats["generations"] == 25 and stats["evaluations"] == 25 * 1024
+
+
+def test_trajectory_clustered_split_bf16():
+    inst = I.clustered()
+    st = oracle_trajectory(inst, 3, S=256, m=64, n1=2, seed=1)
+    with make(inst, population=256, island_size=64, n1=2, seed=1, precision="split_bf16") as s:
+        s.step(3)
+        assert_same_state(s, st)
+
+
+def test_resume_equals_uninterrupted():
+    inst = I.medium(seed=8, n=120, p=8)
+    kw = dict(population=256, island_size=32, n1=5, seed=3, precision="fp32")
+    with make(inst, **kw) as a:
+        a.step(12)
+        blob = a.get_state()
+        a.step(13)
+        full = a.get_state()
+    with make(inst, **kw) as b:
+        b.set_state(blob)
+        b.step(13)
+        assert b.get_state() == full
+    with make(inst, **dict(kw, seed=4)) as c:
+        with pytest.raises(hubga.HubGAError):
+            c.set_state(blob)
+
+
+def test_rerun_determinism_and_solve():
+    inst = I.uniform(seed=30, n=150, p=6)
+    kw = dict(population=512, island_size=64, n1=4, seed=9, precision="split_bf16")
+    with make(inst, **kw) as a, make(inst, **kw) as b:
+        ra = a.solve(20)
+        rb = b.solve(20)
+        assert np.array_equal(ra["hubs"], rb["hubs"]) and ra["cost"] == rb["cost"]
+        assert a.get_state() == b.get_state()
+        c, _ = ref_eval(inst, ra["hubs"][None])
+        assert c[0] == ra["cost"]
