@@ -180,6 +180,16 @@ ga_status ga_stats(ga_ctx *ctx, int64_t stats[4]);
 ga_status ga_profile_enable(ga_ctx *ctx, int32_t enable);
 ga_status ga_profile_read(ga_ctx *ctx, double *ms_total, int64_t *launches);
 
+/* Tile configurations of the batched matrix-core kernel, for autotuning:
+ * ga_tile_config_count() configurations, numbered from 0; ga_tile_config_info
+ * gives rows and columns of W x [A_1..A_S] per workgroup tile and the K depth
+ * staged per step.  ga_set_tile_config selects one for the context's later
+ * batched evaluations (results agree to the returned error bounds in every
+ * configuration; the default is 0). */
+int32_t ga_tile_config_count(void);
+ga_status ga_tile_config_info(int32_t config, int32_t *rows, int32_t *cols, int32_t *ktile);
+ga_status ga_set_tile_config(ga_ctx *ctx, int32_t config);
+
 const char *ga_status_str(ga_status s);
 const char *ga_last_error(const ga_ctx *ctx);   /* also valid for ctx == NULL (last init error) */
 void ga_free(ga_ctx *ctx);                        /* waits for queued work; NULL is a no-op */

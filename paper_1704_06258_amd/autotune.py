@@ -1,0 +1,79 @@
+"""Tile autotuner for the batched split-bf16 evaluation kernel.
+
+For a live context it times every tile configuration of the batched kernel
+(ga_tile_config_count / ga_set_tile_config) on the context's own current
+population, with HIP events around each launch, keeps the fastest, and caches
+the choice in a JSON file keyed by (architecture, n bucket, p, population).
+Timing re-evaluates the population through ga_evaluate_dev, so the GA state
+(ancestors, best, generation) is left untouched.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+
+from . import hubga
+
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "hubga", "tiles.json")
+
+
+def cache_key(n, p, S, arch="gfx950"):
+    bucket = 1 << max(0, (int(n) - 1).bit_length())   # next power of two
+    return f"{arch}|n{bucket}|p{p}|S{S}"
+
+
+def _load(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def time_config(solver, cfg, d_hubs, reps=5):
+    """Mean milliseconds of one batched-kernel launch over the population."""
+    import torch
+    solver.set_tile_config(cfg)
+    solver.evaluate_dev(d_hubs)              # warm-up (code object load, caches)
+    torch.cuda.synchronize()
+    solver.profile_enable(True)
+    for _ in range(reps):
+        solver.evaluate_dev(d_hubs)
+    ms, k = solver.profile_read()
+    solver.profile_enable(False)
+    return ms / max(k, 1)
+
+
+def autotune(solver, cache_path=DEFAULT_CACHE, force=False, reps=5):
+    """Pick (and apply) the fastest tile configuration for this context.
+    Returns {"config": c, "ms": {c: ms}, "cached": bool}."""
+    import numpy as np
+    import torch
+    if solver.params.precision != hubga.GA_PREC_SPLIT_BF16:
+        return {"config": None, "ms": {}, "cached": False}
+    key = cache_key(solver.n, solver.p, solver.S)
+    cache = _load(cache_path)
+    if not force and key in cache:
+        solver.set_tile_config(int(cache[key]["config"]))
+        return {"config": int(cache[key]["config"]), "ms": cache[key].get("ms", {}), "cached": True}
+    hubs, _ = solver.population()
+    if not np.all(np.diff(hubs, axis=1) > 0):     # before the first generation: use the ancestors
+        anc, _ = solver.ancestors()
+        hubs = np.repeat(anc, solver.S // anc.shape[0], axis=0)
+    d_hubs = torch.from_numpy(np.ascontiguousarray(hubs)).to(solver.device)
+    times = {}
+    for cfg in range(len(hubga.tile_configs())):
+        times[cfg] = time_config(solver, cfg, d_hubs, reps)
+    best = min(times, key=times.get)
+    solver.set_tile_config(best)
+    cache[key] = {"config": best, "ms": times, "time": time.time()}
+    try:
+        os.makedirs(os.path.dirname(cache_path), exist_ok=True)
+        tmp = cache_path + ".tmp%d" % os.getpid()
+        with open(tmp, "w") as f:
+            json.dump(cache, f, indent=1)
+        os.replace(tmp, cache_path)
+    except OSError:
+        pass
+    return {"config": best, "ms": times, "cached": False}

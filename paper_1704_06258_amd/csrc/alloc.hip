@@ -15,7 +15,8 @@ namespace hubga {
 
 template <typename CT>
 __global__ __launch_bounds__(256) void k_alloc(const int32_t *__restrict__ hubs, int count, int n, int n_pad, int p,
-                                               const CT *__restrict__ Ct, const double *__restrict__ O,
+                                               const CT *__restrict__ Ct, const float *__restrict__ Ct32,
+                                               const double *__restrict__ O,
                                                const double *__restrict__ D, uint16_t *__restrict__ kidx,
                                                double *__restrict__ parts, int32_t *__restrict__ cmax,
                                                float *__restrict__ Ch32, int want_sums)
@@ -40,13 +41,32 @@ __global__ __launch_bounds__(256) void k_alloc(const int32_t *__restrict__ hubs,
             krow[i] = kNoHub;
             continue;
         }
+        // Scan in FP32: rounding to FP32 is monotone, so a unique FP32
+        // minimum is also the unique minimum of the instance values.  When
+        // several hubs share the FP32 minimum, rescan in the instance dtype
+        // (strict <, ties to the smaller hub id).
         int best = 0;
-        CT bd = Ct[(size_t)sh_h[0] * n + i];
+        float bd = Ct32[(size_t)sh_h[0] * n + i];
+        bool tie = false;
         for (int k = 1; k < p; ++k) {
-            CT v = Ct[(size_t)sh_h[k] * n + i];
+            float v = Ct32[(size_t)sh_h[k] * n + i];
             if (v < bd) {
                 bd = v;
                 best = k;
+                tie = false;
+            } else if (v == bd) {
+                tie = true;
+            }
+        }
+        if (tie) {
+            best = 0;
+            CT be = Ct[(size_t)sh_h[0] * n + i];
+            for (int k = 1; k < p; ++k) {
+                CT v = Ct[(size_t)sh_h[k] * n + i];
+                if (v < be) {
+                    be = v;
+                    best = k;
+                }
             }
         }
         // a hub keeps itself: binary search of i in the sorted list
@@ -127,11 +147,11 @@ hipError_t launch_alloc(const DevPtrs &P, const Dims &d, const int32_t *hubs, in
     if (count <= 0) return hipSuccess;
     float *ch = want_ch ? P.Ch32 : nullptr;
     if (d.c_f32)
-        k_alloc<float><<<count, 256, 0, st>>>(hubs, count, d.n, d.n_pad, d.p, (const float *)P.Ct, P.O, P.D, kidx,
-                                             P.parts, P.cmax, ch, want_sums);
+        k_alloc<float><<<count, 256, 0, st>>>(hubs, count, d.n, d.n_pad, d.p, (const float *)P.Ct, P.Ct32, P.O, P.D,
+                                             kidx, P.parts, P.cmax, ch, want_sums);
     else
-        k_alloc<double><<<count, 256, 0, st>>>(hubs, count, d.n, d.n_pad, d.p, (const double *)P.Ct, P.O, P.D,
-                                              kidx, P.parts, P.cmax, ch, want_sums);
+        k_alloc<double><<<count, 256, 0, st>>>(hubs, count, d.n, d.n_pad, d.p, (const double *)P.Ct, P.Ct32, P.O,
+                                              P.D, kidx, P.parts, P.cmax, ch, want_sums);
     return hipGetLastError();
 }
 

@@ -9,7 +9,7 @@ constexpr int kMaxP = 64;          // hub lists live in LDS; p*p doubles fit eas
 constexpr int kMaxN = 8192;        // canonical kernel keeps n partial sums t_j in LDS
 constexpr int kMaxIsland = 1024;   // one island per workgroup in selection
 constexpr uint16_t kNoHub = 0xFFFF;
-constexpr int kMfmaRowsPerTile = 128;   // rows of W per batched-kernel workgroup
+constexpr int kMfmaMinRows = 64;        // smallest row tile of the batched kernel (sizes its partials)
 constexpr int kPad = 128;               // n is padded to a multiple of this for the bf16 copies
 
 enum Precision { kFP64 = 0, kFP32 = 1, kSplitBF16 = 2 };
@@ -18,10 +18,13 @@ enum Precision { kFP64 = 0, kFP32 = 1, kSplitBF16 = 2 };
 struct DevPtrs {
     void *C;            // n*n, instance dtype
     void *Ct;           // n*n transposed (== C when C is symmetric): hub rows for allocation
+    float *Ct32;        // Ct rounded to FP32 (== Ct for an FP32 instance)
     void *W;            // n*n, instance dtype
     float *W32;         // n*n FP32 copy (FP32 mode with a binary64 instance), else null
     uint16_t *Whi;      // n_pad*n_pad bf16 bits (split mode), else null
     uint16_t *Wlo;
+    uint16_t *Whsw;     // W hi/lo in fragment order: 16-byte chunk (row r, k 8c..8c+7) at
+    uint16_t *Wlsw;     //   ((r/64 * n_pad/16 + k/16)*2 + (k/8)%2)*64 + r%64
     double *O, *D, *dsum;
     int32_t *hubs;      // S*p current batch / children (sorted)
     uint16_t *kidx;     // S*n_pad hub positions (kNoHub in the padding)
@@ -30,7 +33,7 @@ struct DevPtrs {
     double *eps;        // S relative error bounds
     int32_t *cmax;      // S largest cluster size
     float *Ch32;        // S*p*p hub-to-hub distances (split mode)
-    double *partial;    // n_mtiles*S*p epilogue partials (split mode)
+    double *partial;    // S*p*(n_pad/64) epilogue partials (split mode), [column][row tile]
     // GA state
     int32_t *anc;       // R*p
     double *anc_cost;   // R
@@ -45,10 +48,16 @@ struct DevPtrs {
     double *cand_parts; // R*m*3
     uint16_t *kidx_one; // n_pad hub positions of a single solution (best so far)
     uint8_t *scratch;   // n bytes (middle-node selection)
+    double *tbuf;       // tot*n column sums t_j of candidates under exact re-evaluation
+    int32_t *slot_r, *slot_c;   // tot candidate slots (island, candidate)
+    int32_t *handled;   // R: candidates of each island that got a slot
+    int32_t *total;     // 1: slots in use
 };
 
 struct Dims {
     int n, p, S, m, R, n_pad, n_mtiles, n1, elitist, prec;
+    int tot;            // candidate slots of the column-parallel exact re-evaluation
+    int mfma_cfg;       // tile configuration of the batched kernel
     int c_f32, w_f32;   // instance dtypes (1 = FP32)
     double chi, alpha, delta, scale;
     uint64_t seed;

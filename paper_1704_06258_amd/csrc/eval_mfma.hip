@@ -18,14 +18,14 @@
 // row tiles (row-tile major), keeping its row panel of W in its own L2.
 #include "kernels.hpp"
 
+#include <type_traits>
+
 namespace hubga {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int KT = 32;            // K tile staged per iteration
-constexpr int LDS_ROW = KT + 8;   // bf16 elements per LDS row (16-byte pad against bank conflicts)
 
 __device__ __forceinline__ uint32_t onehot2(uint32_t kk, uint32_t lq)
 {
@@ -34,15 +34,18 @@ __device__ __forceinline__ uint32_t onehot2(uint32_t kk, uint32_t lq)
     return lo | hi;
 }
 
-template <int ROWB, int COLB>
-__global__ __launch_bounds__(256) void k_eval_mfma(const uint16_t *__restrict__ Whi, const uint16_t *__restrict__ Wlo,
-                                                   const uint16_t *__restrict__ kidx, const float *__restrict__ Ch32,
-                                                   int n, int n_pad, int p, int NS, int n_mt, int n_nt,
-                                                   double *__restrict__ partial)
+template <int ROWB, int COLB, int KT, int OCC>
+__global__ __launch_bounds__(256, OCC) void k_eval_mfma(const uint16_t *__restrict__ Whi,
+                                                      const uint16_t *__restrict__ Wlo,
+                                                      const uint16_t *__restrict__ kidx,
+                                                      const float *__restrict__ Ch32, int n, int n_pad, int p,
+                                                      int NS, int n_mt, int n_nt, double *__restrict__ partial)
 {
     constexpr int MT = 32 * ROWB;            // rows per tile
     constexpr int NT = 4 * 32 * COLB;        // columns per tile
+    constexpr int LDS_ROW = KT + 8;          // bf16 per LDS row (16-byte pad against bank conflicts)
     constexpr int A_ELEMS = MT * LDS_ROW;    // one matrix, one stage
+    constexpr int KSTEPS = KT / 16;
     __shared__ __align__(16) uint16_t sA[2][2][A_ELEMS];   // [stage][hi/lo]
 
     // XCD-aware tile order: XCD x (= blockIdx % 8) gets the contiguous tile
@@ -58,18 +61,20 @@ __global__ __launch_bounds__(256) void k_eval_mfma(const uint16_t *__restrict__ 
     const int half = lane >> 5, l32 = lane & 31;
 
     // columns of this lane and the kidx row each one reads
-    int col[COLB], ind[COLB];
+    int col[COLB];
     uint32_t lq[COLB];
+    const uint16_t *krow[COLB];
 #pragma unroll
     for (int b = 0; b < COLB; ++b) {
         col[b] = N0 + wave * 32 * COLB + b * 32 + l32;
+        int ind = 0;
         if (col[b] < NS) {
-            ind[b] = col[b] / p;
+            ind = col[b] / p;
             lq[b] = (uint32_t)(col[b] % p);
         } else {
-            ind[b] = 0;
             lq[b] = 0xFFFFu;   // matches no hub position: zero column
         }
+        krow[b] = kidx + (size_t)ind * n_pad + half * 8;
     }
 
     f32x16 acc[ROWB][COLB];
@@ -78,30 +83,39 @@ __global__ __launch_bounds__(256) void k_eval_mfma(const uint16_t *__restrict__ 
 #pragma unroll
         for (int b = 0; b < COLB; ++b) acc[a][b] = (f32x16)(0.0f);
 
-    // global -> LDS staging: each matrix tile is MT rows x KT k = MT*4 chunks of 16 B
+    // global -> LDS staging: each matrix tile is MT rows x KT k = MT*KT/8 chunks of 16 B
     constexpr int CHUNKS = MT * (KT / 8);
     constexpr int PER_THREAD = CHUNKS / 256;   // per matrix
     static_assert(CHUNKS % 256 == 0, "tile must split evenly over 256 threads");
     u32x4 stage_hi[PER_THREAD], stage_lo[PER_THREAD];
+    u32x4 knext[KSTEPS][COLB], kcur[KSTEPS][COLB];
 
     auto gload = [&](int k0) {
 #pragma unroll
         for (int q = 0; q < PER_THREAD; ++q) {
             int c = tid + q * 256;
-            int row = c >> 2, kq = (c & 3) * 8;
+            int row = c / (KT / 8), kq = (c % (KT / 8)) * 8;
             size_t off = (size_t)(M0 + row) * n_pad + k0 + kq;
             stage_hi[q] = *(const u32x4 *)(Whi + off);
             stage_lo[q] = *(const u32x4 *)(Wlo + off);
         }
+#pragma unroll
+        for (int kk = 0; kk < KSTEPS; ++kk)
+#pragma unroll
+            for (int b = 0; b < COLB; ++b) knext[kk][b] = *(const u32x4 *)(krow[b] + k0 + kk * 16);
     };
     auto lstore = [&](int st) {
 #pragma unroll
         for (int q = 0; q < PER_THREAD; ++q) {
             int c = tid + q * 256;
-            int row = c >> 2, kq = (c & 3) * 8;
+            int row = c / (KT / 8), kq = (c % (KT / 8)) * 8;
             *(u32x4 *)(&sA[st][0][row * LDS_ROW + kq]) = stage_hi[q];
             *(u32x4 *)(&sA[st][1][row * LDS_ROW + kq]) = stage_lo[q];
         }
+#pragma unroll
+        for (int kk = 0; kk < KSTEPS; ++kk)
+#pragma unroll
+            for (int b = 0; b < COLB; ++b) kcur[kk][b] = knext[kk][b];
     };
 
     const int ktiles = n_pad / KT;
@@ -112,13 +126,12 @@ __global__ __launch_bounds__(256) void k_eval_mfma(const uint16_t *__restrict__ 
         const int cur = kt & 1;
         if (kt + 1 < ktiles) gload((kt + 1) * KT);
 #pragma unroll
-        for (int kk = 0; kk < KT / 16; ++kk) {
-            const int kbase = kt * KT + kk * 16 + half * 8;
+        for (int kk = 0; kk < KSTEPS; ++kk) {
             bf16x8 bfrag[COLB];
 #pragma unroll
             for (int b = 0; b < COLB; ++b) {
-                u32x4 kv = *(const u32x4 *)(kidx + (size_t)ind[b] * n_pad + kbase);
-                uint32_t l2 = lq[b];
+                const u32x4 kv = kcur[kk][b];
+                const uint32_t l2 = lq[b];
                 u32x4 bb;
                 bb.x = onehot2(kv.x, l2);
                 bb.y = onehot2(kv.y, l2);
@@ -126,15 +139,17 @@ __global__ __launch_bounds__(256) void k_eval_mfma(const uint16_t *__restrict__ 
                 bb.w = onehot2(kv.w, l2);
                 bfrag[b] = __builtin_bit_cast(bf16x8, bb);
             }
+            // hi pass over every accumulator, then lo pass: consecutive MFMAs
+            // never feed each other
 #pragma unroll
-            for (int a = 0; a < ROWB; ++a) {
-                const int lrow = (a * 32 + l32) * LDS_ROW + kk * 16 + half * 8;
-                bf16x8 ahi = __builtin_bit_cast(bf16x8, *(const u32x4 *)(&sA[cur][0][lrow]));
-                bf16x8 alo = __builtin_bit_cast(bf16x8, *(const u32x4 *)(&sA[cur][1][lrow]));
+            for (int part = 0; part < 2; ++part) {
 #pragma unroll
-                for (int b = 0; b < COLB; ++b) {
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bfrag[b], acc[a][b], 0, 0, 0);
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bfrag[b], acc[a][b], 0, 0, 0);
+                for (int a = 0; a < ROWB; ++a) {
+                    const int lrow = (a * 32 + l32) * LDS_ROW + kk * 16 + half * 8;
+                    bf16x8 af = __builtin_bit_cast(bf16x8, *(const u32x4 *)(&sA[cur][part][lrow]));
+#pragma unroll
+                    for (int b = 0; b < COLB; ++b)
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af, bfrag[b], acc[a][b], 0, 0, 0);
                 }
             }
         }
@@ -148,8 +163,8 @@ __global__ __launch_bounds__(256) void k_eval_mfma(const uint16_t *__restrict__ 
     for (int b = 0; b < COLB; ++b) {
         double sum = 0.0;
         if (col[b] < NS) {
-            const int s = ind[b];
-            const uint16_t *krow = kidx + (size_t)s * n_pad;
+            const int s = col[b] / p;
+            const uint16_t *kr = kidx + (size_t)s * n_pad;
             const float *ch = Ch32 + (size_t)s * p * p + lq[b];
 #pragma unroll
             for (int a = 0; a < ROWB; ++a) {
@@ -157,41 +172,250 @@ __global__ __launch_bounds__(256) void k_eval_mfma(const uint16_t *__restrict__ 
                 for (int v = 0; v < 16; ++v) {
                     const int i = M0 + a * 32 + 8 * (v >> 2) + 4 * half + (v & 3);
                     if (i < n) {
-                        const int k = krow[i];
+                        const int k = kr[i];
                         sum += (double)acc[a][b][v] * (double)ch[k * p];
                     }
                 }
             }
         }
         sum += __shfl_xor(sum, 32);
-        if (half == 0 && col[b] < NS) partial[(size_t)mt * NS + col[b]] = sum;
+        if (half == 0 && col[b] < NS) partial[(size_t)col[b] * n_mt + mt] = sum;
     }
 }
 
-// T_s = sum over l, then over row tiles, of the partials; cost assembly
-// f = ((chi*Cc) + (alpha*T)) + (delta*Dd) and its relative error bound.
-__global__ void k_finalize_split(const double *__restrict__ partial, const int32_t *__restrict__ cmax, int count,
-                                 int p, int n_mt, int n, int c_f32, double chi, double alpha, double delta,
-                                 double scale, double *__restrict__ cost, double *__restrict__ parts,
-                                 double *__restrict__ eps)
+// ---------------------------------------------------------------------------
+// Pipelined variant.  W hi/lo are read from a fragment-ordered ("swizzled")
+// copy in which every (64-row group, 16-k step, k half) is one contiguous 1 KB
+// run of 64 16-byte chunks -- exactly the lane order of one wave's operand
+// fragment.  Each K tile (32) of W and of every wave's hub positions is moved
+// global -> LDS by global_load_lds_dwordx4 (no register staging) into a ring
+// of NST stages, NST-1 tiles ahead of the matrix cores.  Waits are explicit
+// vmcnt counts (in-order completion of the wave's own loads) followed by a
+// bare workgroup barrier; the ring is read with ds_read_b128 issued as inline
+// assembly and an explicit lgkmcnt wait, so the compiler never drains the
+// whole pipeline before an LDS read.
+typedef __attribute__((address_space(3))) void lds_void;
+
+template <int N, typename F, int I = 0>
+__device__ __forceinline__ void static_for(F &&f)
 {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= count) return;
-    const int NS = count * p;
-    double T = 0.0;
-    for (int l = 0; l < p; ++l)
-        for (int mt = 0; mt < n_mt; ++mt) T += partial[(size_t)mt * NS + (size_t)s * p + l];
-    const double Cc = parts[3 * (size_t)s], Dd = parts[3 * (size_t)s + 2];
-    parts[3 * (size_t)s + 1] = T;
-    cost[s] = (((chi * Cc) + (alpha * T)) + (delta * Dd)) * scale;
-    // split residual + FP32 accumulation of at most 2*cmax non-zero addends per
-    // output (any faithful rounding) + FP32 hub distances + binary64 sums
-    double e = kSplitResidual + gamma_k(2.0 * cmax[s], kU32Faithful) + (c_f32 ? 0.0 : kU32) +
-               gamma_k((double)n + (double)p * n_mt + 4.0, kU64) + gamma_k(n + 2.0, kU64) + gamma_k(8.0, kU64) + 1e-9;
-    eps[s] = e;
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<N, F, I + 1>(static_cast<F &&>(f));
+    }
 }
 
-template <int ROWB, int COLB>
+template <int OFF>
+__device__ __forceinline__ u32x4 ds_read16(uint32_t addr)
+{
+    u32x4 v;
+    asm volatile("ds_read_b128 %0, %1 offset:%2" : "=v"(v) : "v"(addr), "i"(OFF));
+    return v;
+}
+__device__ __forceinline__ void lds_wait() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+__device__ __forceinline__ void pin(u32x4 &v) { asm volatile("" : "+v"(v)); }
+
+// s_waitcnt vmcnt(N), other counters untouched (gfx9 encoding).
+template <int N>
+__device__ __forceinline__ void vm_wait()
+{
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+
+__device__ __forceinline__ void wg_barrier()
+{
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+template <int ROWB, int COLB, int NST, int KINS, int OCC>
+__global__ __launch_bounds__(256, OCC) void k_eval_mfma_pipe(const u32x4 *__restrict__ Whsw,
+                                                              const u32x4 *__restrict__ Wlsw,
+                                                              const uint16_t *__restrict__ kidx,
+                                                              const float *__restrict__ Ch32, int n, int n_pad, int p,
+                                                              int count, int NS, int n_mt, int n_nt,
+                                                              double *__restrict__ partial)
+{
+    constexpr int MT = 32 * ROWB, NT = 128 * COLB, KTILE = 32, KSTEPS = KTILE / 16;
+    constexpr int A_CHUNKS = 2 * KSTEPS * 2 * MT;   // [hi/lo][kk][half][row] 16-byte chunks per stage
+    constexpr int K_CHUNKS = 4 * KINS * 64;         // [wave][ins][lane]
+    constexpr int STAGE = A_CHUNKS + K_CHUNKS;
+    constexpr int A_INS = A_CHUNKS / 64 / 4;        // 1 KB transfers per wave per tile for W
+    constexpr int LPT = A_INS + KINS;               // vector-memory instructions per wave per tile
+    static_assert(MT % 64 == 0 && (A_CHUNKS / 64) % 4 == 0, "tile shape");
+    __shared__ __align__(16) u32x4 ring[NST * STAGE];
+
+    const int tiles = n_mt * n_nt;
+    const int per = (tiles + 7) / 8;
+    const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (tile >= tiles) return;
+    const int mt = tile / n_nt, nt = tile % n_nt;
+    const int M0 = mt * MT, N0 = nt * NT;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int half = lane >> 5, l32 = lane & 31;
+    const int KS = n_pad / 16;
+
+    // this wave's columns and the individuals they belong to
+    const int c_first = min(N0 + wave * 32 * COLB, NS - 1);
+    const int s_first = c_first / p;
+    int col[COLB], li[COLB];
+    uint32_t lq[COLB];
+#pragma unroll
+    for (int b = 0; b < COLB; ++b) {
+        col[b] = N0 + wave * 32 * COLB + b * 32 + l32;
+        if (col[b] < NS) {
+            li[b] = col[b] / p - s_first;
+            lq[b] = (uint32_t)(col[b] % p);
+        } else {
+            li[b] = 0;
+            lq[b] = 0xFFFFu;
+        }
+    }
+
+    const uint32_t ring_addr = (uint32_t)(uintptr_t)(lds_void *)ring;
+    auto issue = [&](int kt) {
+        const int st = kt % NST;
+        u32x4 *stage = ring + st * STAGE;
+#pragma unroll
+        for (int q = 0; q < A_INS; ++q) {
+            const int ins = wave + 4 * q;                    // ((mat*KSTEPS + kk)*2 + h)*(MT/64) + gl
+            const int gl = ins % (MT / 64), t = ins / (MT / 64);
+            const int h = t & 1, kk = (t >> 1) % KSTEPS, mat = (t >> 1) / KSTEPS;
+            const size_t gchunk = (((size_t)(mt * (MT / 64) + gl) * KS + kt * KSTEPS + kk) * 2 + h) * 64;
+            const u32x4 *src = (mat ? Wlsw : Whsw) + gchunk + lane;
+            __builtin_amdgcn_global_load_lds((const void *)src, (lds_void *)(stage + ins * 64), 16, 0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < KINS; ++q) {
+            const int si = min(s_first + q * 16 + (lane >> 2), count - 1);
+            const uint16_t *src = kidx + (size_t)si * n_pad + kt * KTILE + (lane & 3) * 8;
+            __builtin_amdgcn_global_load_lds((const void *)src,
+                                             (lds_void *)(stage + A_CHUNKS + (wave * KINS + q) * 64), 16, 0, 0);
+        }
+    };
+
+    f32x16 acc[ROWB][COLB];
+#pragma unroll
+    for (int a = 0; a < ROWB; ++a)
+#pragma unroll
+        for (int b = 0; b < COLB; ++b) acc[a][b] = (f32x16)(0.0f);
+
+    const int ktiles = n_pad / KTILE;
+#pragma unroll
+    for (int t = 0; t < NST - 1; ++t)
+        if (t < ktiles) issue(t);
+    // per-lane LDS byte addresses (stage 0); per-stage offset added below
+    const uint32_t a_lane = ring_addr + (uint32_t)((half * MT + l32) * 16);
+    uint32_t k_lane[COLB];
+#pragma unroll
+    for (int b = 0; b < COLB; ++b)
+        k_lane[b] = ring_addr + (uint32_t)((A_CHUNKS + wave * KINS * 64 + li[b] * 4 + half) * 16);
+
+    for (int kt = 0; kt < ktiles; ++kt) {
+        // this wave's loads of tile kt are done once at most (younger tiles)*LPT remain
+        const int younger = min(NST - 2, ktiles - 1 - kt);
+        static_for<NST - 1>([&](auto Y) {
+            if (younger == Y.value) vm_wait<Y.value * LPT>();
+        });
+        wg_barrier();
+        if (kt + NST - 1 < ktiles) issue(kt + NST - 1);
+        const uint32_t soff = (uint32_t)((kt % NST) * STAGE * 16);
+        static_for<KSTEPS>([&](auto KK) {
+            constexpr int kk = KK.value;
+            u32x4 af[2][ROWB], kv[COLB];
+            static_for<2>([&](auto M) {
+                static_for<ROWB>([&](auto A) {
+                    af[M.value][A.value] = ds_read16<((M.value * KSTEPS + kk) * 2 * MT + A.value * 32) * 16>(a_lane + soff);
+                });
+            });
+            static_for<COLB>([&](auto B) { kv[B.value] = ds_read16<kk * 32>(k_lane[B.value] + soff); });
+            lds_wait();
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+#pragma unroll
+                for (int a = 0; a < ROWB; ++a) pin(af[m][a]);
+#pragma unroll
+            for (int b = 0; b < COLB; ++b) pin(kv[b]);
+            bf16x8 bfrag[COLB];
+#pragma unroll
+            for (int b = 0; b < COLB; ++b) {
+                u32x4 bb;
+                bb.x = onehot2(kv[b].x, lq[b]);
+                bb.y = onehot2(kv[b].y, lq[b]);
+                bb.z = onehot2(kv[b].z, lq[b]);
+                bb.w = onehot2(kv[b].w, lq[b]);
+                bfrag[b] = __builtin_bit_cast(bf16x8, bb);
+            }
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+#pragma unroll
+                for (int a = 0; a < ROWB; ++a) {
+                    const bf16x8 afr = __builtin_bit_cast(bf16x8, af[m][a]);
+#pragma unroll
+                    for (int b = 0; b < COLB; ++b)
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afr, bfrag[b], acc[a][b], 0, 0, 0);
+                }
+        });
+    }
+
+    // epilogue (as in k_eval_mfma)
+#pragma unroll
+    for (int b = 0; b < COLB; ++b) {
+        double sum = 0.0;
+        if (col[b] < NS) {
+            const int s = col[b] / p;
+            const uint16_t *kr = kidx + (size_t)s * n_pad;
+            const float *ch = Ch32 + (size_t)s * p * p + lq[b];
+#pragma unroll
+            for (int a = 0; a < ROWB; ++a) {
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    const int i = M0 + a * 32 + 8 * (v >> 2) + 4 * half + (v & 3);
+                    if (i < n) {
+                        const int k = kr[i];
+                        sum += (double)acc[a][b][v] * (double)ch[k * p];
+                    }
+                }
+            }
+        }
+        sum += __shfl_xor(sum, 32);
+        if (half == 0 && col[b] < NS) partial[(size_t)col[b] * n_mt + mt] = sum;
+    }
+}
+
+// T_s = sum of the individual's p*n_mt partials (contiguous), one wave per
+// individual with a fixed reduction order; cost assembly
+// f = ((chi*Cc) + (alpha*T)) + (delta*Dd) and its relative error bound.
+__global__ __launch_bounds__(256) void k_finalize_split(const double *__restrict__ partial,
+                                                        const int32_t *__restrict__ cmax, int count, int p, int n_mt,
+                                                        int n, int c_f32, double chi, double alpha, double delta,
+                                                        double scale, double *__restrict__ cost,
+                                                        double *__restrict__ parts, double *__restrict__ eps)
+{
+    const int s = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (s >= count) return;
+    const int len = p * n_mt;
+    const double *ps = partial + (size_t)s * len;   // [l][row tile]
+    double v = 0.0;
+    for (int e = lane; e < len; e += 64) v += ps[e];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (lane == 0) {
+        const double T = v;
+        const double Cc = parts[3 * (size_t)s], Dd = parts[3 * (size_t)s + 2];
+        parts[3 * (size_t)s + 1] = T;
+        cost[s] = (((chi * Cc) + (alpha * T)) + (delta * Dd)) * scale;
+        // split residual + FP32 accumulation of at most 2*cmax non-zero addends
+        // per output (any faithful rounding) + FP32 hub distances + binary64 sums
+        eps[s] = kSplitResidual + gamma_k(2.0 * cmax[s], kU32Faithful) + (c_f32 ? 0.0 : kU32) +
+                 gamma_k((double)n + (double)len + 8.0, kU64) + gamma_k(n + 2.0, kU64) + gamma_k(8.0, kU64) + 1e-9;
+    }
+}
+
+template <int ROWB, int COLB, int KT, int OCC>
 static hipError_t mfma_launch(const DevPtrs &P, const Dims &d, const uint16_t *kidx, int count, hipStream_t st)
 {
     const int MT = 32 * ROWB, NT = 128 * COLB;
@@ -200,12 +424,52 @@ static hipError_t mfma_launch(const DevPtrs &P, const Dims &d, const uint16_t *k
     const int n_nt = (NS + NT - 1) / NT;
     const int tiles = n_mt * n_nt;
     const int per = (tiles + 7) / 8;
-    k_eval_mfma<ROWB, COLB><<<per * 8, 256, 0, st>>>(P.Whi, P.Wlo, kidx, P.Ch32, d.n, d.n_pad, d.p, NS, n_mt, n_nt,
-                                                     P.partial);
+    k_eval_mfma<ROWB, COLB, KT, OCC><<<per * 8, 256, 0, st>>>(P.Whi, P.Wlo, kidx, P.Ch32, d.n, d.n_pad, d.p, NS,
+                                                             n_mt, n_nt, P.partial);
     return hipGetLastError();
 }
 
-int mfma_row_tiles(const Dims &d) { return d.n_pad / kMfmaRowsPerTile; }
+template <int ROWB, int COLB, int NST, int KINS, int OCC>
+static hipError_t pipe_launch(const DevPtrs &P, const Dims &d, const uint16_t *kidx, int count, hipStream_t st)
+{
+    const int MT = 32 * ROWB, NT = 128 * COLB;
+    const int NS = count * d.p;
+    const int n_mt = d.n_pad / MT;
+    const int n_nt = (NS + NT - 1) / NT;
+    const int tiles = n_mt * n_nt;
+    const int per = (tiles + 7) / 8;
+    k_eval_mfma_pipe<ROWB, COLB, NST, KINS, OCC><<<per * 8, 256, 0, st>>>(
+        (const u32x4 *)P.Whsw, (const u32x4 *)P.Wlsw, kidx, P.Ch32, d.n, d.n_pad, d.p, count, NS, n_mt, n_nt,
+        P.partial);
+    return hipGetLastError();
+}
+
+// Individuals one wave's columns can touch, in 16-individual transfers.
+static int kidx_transfers(int colb, int p) { return (((32 * colb + p - 2) / p + 2) + 15) / 16; }
+
+template <int ROWB, int COLB, int NST, int OCC>
+static hipError_t pipe_dispatch(const DevPtrs &P, const Dims &d, const uint16_t *kidx, int count, hipStream_t st)
+{
+    const int kins = kidx_transfers(COLB, d.p);
+    if (kins <= 1) return pipe_launch<ROWB, COLB, NST, 1, OCC>(P, d, kidx, count, st);
+    if (kins <= 2) return pipe_launch<ROWB, COLB, NST, 2, OCC>(P, d, kidx, count, st);
+    return mfma_launch<4, 2, 32, 2>(P, d, kidx, count, st);   // few hubs: per-lane fragment loads
+}
+
+// Tile configurations of the batched kernel: {rows/32 per wave, columns/32
+// per wave, K tile, minimum workgroups per CU, pipeline stages (0: register
+// staging, double-buffered LDS)}.
+struct MfmaCfg { int rowb, colb, kt, occ, nst; };
+static const MfmaCfg kMfmaCfgs[] = {{4, 2, 32, 2, 0}, {4, 2, 64, 1, 0}, {4, 4, 32, 1, 0}, {2, 4, 32, 2, 0},
+                                    {4, 4, 64, 1, 0}, {2, 2, 64, 2, 0}, {4, 2, 32, 1, 4}, {4, 2, 32, 2, 3},
+                                    {4, 4, 32, 1, 4}, {4, 4, 32, 1, 3}, {2, 4, 32, 2, 4}};
+constexpr int kNumMfmaCfgs = sizeof(kMfmaCfgs) / sizeof(kMfmaCfgs[0]);
+
+int mfma_num_configs() { return kNumMfmaCfgs; }
+int mfma_rows_per_tile(int cfg) { return 32 * kMfmaCfgs[cfg].rowb; }
+int mfma_pipelined(int cfg) { return kMfmaCfgs[cfg].nst > 0; }
+int mfma_cols_per_tile(int cfg) { return 128 * kMfmaCfgs[cfg].colb; }
+int mfma_k_tile(int cfg) { return kMfmaCfgs[cfg].kt; }
 
 hipError_t launch_eval_split(const DevPtrs &P, const Dims &d, const uint16_t *kidx, int count, hipStream_t st,
                              hipEvent_t ev0, hipEvent_t ev1)
@@ -213,11 +477,25 @@ hipError_t launch_eval_split(const DevPtrs &P, const Dims &d, const uint16_t *ki
     if (count <= 0) return hipSuccess;
     hipError_t e;
     if (ev0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return e;
-    e = mfma_launch<4, 2>(P, d, kidx, count, st);
+    switch (d.mfma_cfg) {
+    case 0: e = mfma_launch<4, 2, 32, 2>(P, d, kidx, count, st); break;
+    case 1: e = mfma_launch<4, 2, 64, 1>(P, d, kidx, count, st); break;
+    case 2: e = mfma_launch<4, 4, 32, 1>(P, d, kidx, count, st); break;
+    case 3: e = mfma_launch<2, 4, 32, 2>(P, d, kidx, count, st); break;
+    case 4: e = mfma_launch<4, 4, 64, 1>(P, d, kidx, count, st); break;
+    case 5: e = mfma_launch<2, 2, 64, 2>(P, d, kidx, count, st); break;
+    case 6: e = pipe_dispatch<4, 2, 4, 1>(P, d, kidx, count, st); break;
+    case 7: e = pipe_dispatch<4, 2, 3, 2>(P, d, kidx, count, st); break;
+    case 8: e = pipe_dispatch<4, 4, 4, 1>(P, d, kidx, count, st); break;
+    case 9: e = pipe_dispatch<4, 4, 3, 1>(P, d, kidx, count, st); break;
+    default: e = pipe_dispatch<2, 4, 4, 2>(P, d, kidx, count, st); break;
+    }
     if (e != hipSuccess) return e;
     if (ev1 && (e = hipEventRecord(ev1, st)) != hipSuccess) return e;
-    const int n_mt = d.n_pad / kMfmaRowsPerTile;
-    k_finalize_split<<<(count + 255) / 256, 256, 0, st>>>(P.partial, P.cmax, count, d.p, n_mt, d.n, d.c_f32, d.chi,
+    int rows = mfma_rows_per_tile(d.mfma_cfg);
+    if (mfma_pipelined(d.mfma_cfg) && kidx_transfers(kMfmaCfgs[d.mfma_cfg].colb, d.p) > 2) rows = 128;
+    const int n_mt = d.n_pad / rows;
+    k_finalize_split<<<(count + 3) / 4, 256, 0, st>>>(P.partial, P.cmax, count, d.p, n_mt, d.n, d.c_f32, d.chi,
                                                           d.alpha, d.delta, d.scale, P.cost, P.parts, P.eps);
     return hipGetLastError();
 }

@@ -120,12 +120,14 @@ __global__ __launch_bounds__(256) void k_eval_exact(const int32_t *__restrict__ 
     if (threadIdx.x == 0 && eps) eps[s] = 0.0;
 }
 
-// Exact re-evaluation of the selection candidates of every island: block
-// (r, y) evaluates candidates y, y + gridDim.y, ... of island r.
+// Exact re-evaluation of the selection candidates that got no slot in the
+// column-parallel kernels (all but the first handled[r] of island r): block
+// (r, y) evaluates candidates handled[r] + y, handled[r] + y + gridDim.y, ...
 template <typename CT, typename WT>
 __global__ __launch_bounds__(256) void k_recheck(const int32_t *__restrict__ hubs, const uint16_t *__restrict__ kidx,
                                                  const int32_t *__restrict__ cand, const int32_t *__restrict__ cand_cnt,
-                                                 int m, int n, int n_pad, int p, const CT *__restrict__ C,
+                                                 const int32_t *__restrict__ handled, int m, int n, int n_pad, int p,
+                                                 const CT *__restrict__ C,
                                                  const WT *__restrict__ W, const double *__restrict__ O,
                                                  const double *__restrict__ D, double chi, double alpha, double delta,
                                                  double scale, double *__restrict__ cand_cost,
@@ -134,12 +136,203 @@ __global__ __launch_bounds__(256) void k_recheck(const int32_t *__restrict__ hub
     extern __shared__ __align__(16) char smem[];
     const int r = blockIdx.x;
     const int cnt = cand_cnt[r];
-    for (int c = blockIdx.y; c < cnt; c += gridDim.y) {
+    for (int c = handled[r] + blockIdx.y; c < cnt; c += gridDim.y) {
         const int s = cand[(size_t)r * m + c];
         eval_exact_body<CT, WT>(hubs + (size_t)s * p, kidx + (size_t)s * n_pad, n, p, C, W, O, D, chi, alpha,
                                 delta, scale, cand_cost + (size_t)r * m + c, cand_parts + 3 * ((size_t)r * m + c),
                                 smem);
         __syncthreads();
+    }
+}
+
+
+// Column-parallel exact evaluation of selection candidates.
+//
+// k_compact (one workgroup) lists candidate slots in island order, up to
+// `tot` in all; handled[r] is how many of island r's candidates got a slot
+// (the rest go to k_recheck).
+//
+// k_canon_cols loops over (slot, 32-column chunk) items: 128-row tiles of W
+// are staged through LDS (loads issued two tiles ahead), every lane of the
+// workgroup forms products W_ij * C[a_i][a_j] for the tile -- the same binary64
+// products as the sequential definition -- and one lane per column adds them
+// in ascending row order into t_j.  k_canon_sums then sums T, Cc and Dd in
+// ascending order.
+constexpr int kCanonCols = 32;
+constexpr int kCanonRows = 128;
+
+__global__ __launch_bounds__(256) void k_compact(const int32_t *__restrict__ cand_cnt, int R, int tot,
+                                                 int32_t *__restrict__ slot_r, int32_t *__restrict__ slot_c,
+                                                 int32_t *__restrict__ handled, int32_t *__restrict__ total)
+{
+    __shared__ int part[256];
+    const int tid = threadIdx.x;
+    const int chunk = (R + 255) / 256;
+    const int r0 = tid * chunk, r1 = min(R, r0 + chunk);
+    int sum = 0;
+    for (int r = r0; r < r1; ++r) sum += cand_cnt[r];
+    part[tid] = sum;
+    __syncthreads();
+    if (tid == 0) {
+        int acc = 0;
+        for (int t = 0; t < 256; ++t) {
+            int v = part[t];
+            part[t] = acc;
+            acc += v;
+        }
+        *total = min(acc, tot);
+    }
+    __syncthreads();
+    int off = part[tid];
+    for (int r = r0; r < r1; ++r) {
+        const int cnt = cand_cnt[r];
+        const int h = max(0, min(cnt, tot - off));
+        for (int c = 0; c < h; ++c) {
+            slot_r[off + c] = r;
+            slot_c[off + c] = c;
+        }
+        handled[r] = h;
+        off += cnt;
+    }
+}
+
+__host__ __device__ inline size_t canon_cols_smem(int n, int p)
+{
+    return (size_t)p * p * 8 + (size_t)kCanonRows * kCanonCols * 8 + (((size_t)n * 2 + 15) / 16) * 16;
+}
+
+template <typename CT, typename WT>
+__global__ __launch_bounds__(256) void k_canon_cols(const int32_t *__restrict__ hubs,
+                                                    const uint16_t *__restrict__ kidx,
+                                                    const int32_t *__restrict__ cand, const int32_t *__restrict__ slot_r,
+                                                    const int32_t *__restrict__ slot_c,
+                                                    const int32_t *__restrict__ total, int m, int n, int n_pad, int p,
+                                                    const CT *__restrict__ C, const WT *__restrict__ W,
+                                                    double *__restrict__ tbuf)
+{
+#pragma clang fp contract(off)
+    extern __shared__ __align__(16) char smem[];
+    double *Ch = (double *)smem;
+    double *tile = Ch + (size_t)p * p;                        // products [row][col]
+    uint16_t *kid = (uint16_t *)(tile + kCanonRows * kCanonCols);
+    __shared__ int h[kMaxP];
+    const int tid = threadIdx.x;
+    const int nchunks = (n + kCanonCols - 1) / kCanonCols;
+    const int items = *total * nchunks;
+    constexpr int PER = kCanonRows * kCanonCols / 256;   // tile elements per thread
+    const int nb = (n + kCanonRows - 1) / kCanonRows;
+    for (int item = blockIdx.x; item < items; item += gridDim.x) {
+        const int slot = item / nchunks, chunk = item % nchunks;
+        const int r = slot_r[slot], c = slot_c[slot];
+        const int s = cand[(size_t)r * m + c];
+        const int j0 = chunk * kCanonCols;
+        const int32_t *hg = hubs + (size_t)s * p;
+        __syncthreads();   // previous item done with LDS
+        if (tid < p) h[tid] = hg[tid];
+        const uint16_t *krow = kidx + (size_t)s * n_pad;
+        for (int i = tid; i < n; i += 256) kid[i] = krow[i];
+        __syncthreads();
+        for (int e = tid; e < p * p; e += 256) Ch[e] = (double)C[(size_t)h[e / p] * n + h[e % p]];
+        // this thread's tile elements: column e % 32 (fixed), rows e / 32
+        const int col = tid % kCanonCols, j = j0 + col;
+        const bool jin = j < n;
+        WT reg0[PER], reg1[PER];
+        auto load = [&](int b, WT *dst) {
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                const int i = b * kCanonRows + (tid + q * 256) / kCanonCols;
+                dst[q] = (i < n && jin) ? W[(size_t)i * n + j] : (WT)0;
+            }
+        };
+        const bool owner = tid < kCanonCols && jin;
+        double acc = 0.0;
+        load(0, reg0);
+        if (nb > 1) load(1, reg1);
+        __syncthreads();   // Ch and kid ready
+        const int kj = jin ? kid[j] : 0;
+        auto step = [&](int b, WT *rg) {
+            const int i0 = b * kCanonRows;
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                const int e = tid + q * 256, i = i0 + e / kCanonCols;
+                tile[e] = i < n ? (double)rg[q] * Ch[(size_t)kid[i] * p + kj] : 0.0;
+            }
+            __syncthreads();
+            if (b + 2 < nb) load(b + 2, rg);
+            if (owner) {
+                const int rows = n - i0 < kCanonRows ? n - i0 : kCanonRows;
+                int ii = 0;
+                for (; ii + 8 <= rows; ii += 8) {
+                    double v0 = tile[(ii + 0) * kCanonCols + tid], v1 = tile[(ii + 1) * kCanonCols + tid];
+                    double v2 = tile[(ii + 2) * kCanonCols + tid], v3 = tile[(ii + 3) * kCanonCols + tid];
+                    double v4 = tile[(ii + 4) * kCanonCols + tid], v5 = tile[(ii + 5) * kCanonCols + tid];
+                    double v6 = tile[(ii + 6) * kCanonCols + tid], v7 = tile[(ii + 7) * kCanonCols + tid];
+                    acc = acc + v0;
+                    acc = acc + v1;
+                    acc = acc + v2;
+                    acc = acc + v3;
+                    acc = acc + v4;
+                    acc = acc + v5;
+                    acc = acc + v6;
+                    acc = acc + v7;
+                }
+                for (; ii < rows; ++ii) acc = acc + tile[ii * kCanonCols + tid];
+            }
+            __syncthreads();
+        };
+        for (int b = 0; b < nb; b += 2) {
+            step(b, reg0);
+            if (b + 1 < nb) step(b + 1, reg1);
+        }
+        if (owner) tbuf[(size_t)slot * n + j] = acc;
+    }
+}
+
+template <typename CT>
+__global__ __launch_bounds__(256) void k_canon_sums(const int32_t *__restrict__ hubs,
+                                                    const uint16_t *__restrict__ kidx,
+                                                    const int32_t *__restrict__ cand, const int32_t *__restrict__ slot_r,
+                                                    const int32_t *__restrict__ slot_c,
+                                                    const int32_t *__restrict__ total, int m, int n, int n_pad, int p,
+                                                    const CT *__restrict__ C, const double *__restrict__ O,
+                                                    const double *__restrict__ D, const double *__restrict__ tbuf,
+                                                    double chi, double alpha, double delta, double scale,
+                                                    double *__restrict__ cand_cost, double *__restrict__ cand_parts)
+{
+#pragma clang fp contract(off)
+    extern __shared__ __align__(16) char smem[];
+    double *bufA = (double *)smem, *bufB = bufA + n;
+    __shared__ int h[kMaxP];
+    __shared__ double sh_cc;
+    const int tid = threadIdx.x;
+    const int tot = *total;
+    for (int slot = blockIdx.x; slot < tot; slot += gridDim.x) {
+        const int r = slot_r[slot], c = slot_c[slot];
+        const int s = cand[(size_t)r * m + c];
+        __syncthreads();
+        if (tid < p) h[tid] = hubs[(size_t)s * p + tid];
+        const uint16_t *krow = kidx + (size_t)s * n_pad;
+        const double *t = tbuf + (size_t)slot * n;
+        __syncthreads();
+        for (int i = tid; i < n; i += 256) {
+            bufA[i] = t[i];
+            bufB[i] = O[i] * (double)C[(size_t)i * n + h[krow[i]]];
+        }
+        __syncthreads();
+        double T = 0.0;
+        if (tid == 0) T = seq_sum(bufA, n);
+        if (tid == 64) sh_cc = seq_sum(bufB, n);
+        __syncthreads();
+        for (int i = tid; i < n; i += 256) bufA[i] = D[i] * (double)C[(size_t)i * n + h[krow[i]]];
+        __syncthreads();
+        if (tid == 0) {
+            const double Cc = sh_cc, Dd = seq_sum(bufA, n);
+            const size_t o = (size_t)r * m + c;
+            cand_cost[o] = (((chi * Cc) + (alpha * T)) + (delta * Dd)) * scale;
+            cand_parts[3 * o + 0] = Cc;
+            cand_parts[3 * o + 1] = T;
+            cand_parts[3 * o + 2] = Dd;
+        }
     }
 }
 
@@ -241,14 +434,30 @@ hipError_t launch_eval_exact(const DevPtrs &P, const Dims &d, const int32_t *hub
 template <typename CT, typename WT>
 static hipError_t recheck_launch(const DevPtrs &P, const Dims &d, int ychunks, hipStream_t st)
 {
+    hipError_t e;
+    k_compact<<<1, 256, 0, st>>>(P.cand_cnt, d.R, d.tot, P.slot_r, P.slot_c, P.handled, P.total);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    size_t smA = canon_cols_smem(d.n, d.p);
+    e = hipFuncSetAttribute((const void *)k_canon_cols<CT, WT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smA);
+    if (e != hipSuccess) return e;
+    k_canon_cols<CT, WT><<<512, 256, smA, st>>>(P.hubs, P.kidx, P.cand, P.slot_r, P.slot_c, P.total, d.m, d.n,
+                                                d.n_pad, d.p, (const CT *)P.C, (const WT *)P.W, P.tbuf);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    size_t smB = (size_t)16 * d.n;
+    e = hipFuncSetAttribute((const void *)k_canon_sums<CT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smB);
+    if (e != hipSuccess) return e;
+    k_canon_sums<CT><<<256, 256, smB, st>>>(P.hubs, P.kidx, P.cand, P.slot_r, P.slot_c, P.total, d.m, d.n, d.n_pad,
+                                            d.p, (const CT *)P.C, P.O, P.D, P.tbuf, d.chi, d.alpha, d.delta, d.scale,
+                                            P.cand_cost, P.cand_parts);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     size_t sm = exact_smem_bytes(d.n, d.p);
-    hipError_t e = hipFuncSetAttribute((const void *)k_recheck<CT, WT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)sm);
+    e = hipFuncSetAttribute((const void *)k_recheck<CT, WT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
     if (e != hipSuccess) return e;
     dim3 grid(d.R, ychunks);
-    k_recheck<CT, WT><<<grid, eval_block(d.n), sm, st>>>(P.hubs, P.kidx, P.cand, P.cand_cnt, d.m, d.n, d.n_pad, d.p,
-                                                         (const CT *)P.C, (const WT *)P.W, P.O, P.D, d.chi, d.alpha,
-                                                         d.delta, d.scale, P.cand_cost, P.cand_parts);
+    k_recheck<CT, WT><<<grid, eval_block(d.n), sm, st>>>(P.hubs, P.kidx, P.cand, P.cand_cnt, P.handled, d.m, d.n,
+                                                         d.n_pad, d.p, (const CT *)P.C, (const WT *)P.W, P.O, P.D,
+                                                         d.chi, d.alpha, d.delta, d.scale, P.cand_cost,
+                                                         P.cand_parts);
     return hipGetLastError();
 }
 

@@ -67,7 +67,11 @@ Dims make_dims(const ga_params *q, ga_dtype cdt, ga_dtype wdt)
     d.m = q->island_size;
     d.R = d.S / d.m;
     d.n_pad = ((d.n + kPad - 1) / kPad) * kPad;
-    d.n_mtiles = d.n_pad / kMfmaRowsPerTile;
+    d.n_mtiles = d.n_pad / kMfmaMinRows;
+    d.mfma_cfg = 0;
+    // up to 512 candidates per generation get the column-parallel exact
+    // re-evaluation; any further ones the one-workgroup path
+    d.tot = std::min(d.S, 512);
     d.n1 = q->n1;
     d.elitist = q->elitist;
     d.prec = q->precision;
@@ -83,8 +87,8 @@ Dims make_dims(const ga_params *q, ga_dtype cdt, ga_dtype wdt)
 
 // Offsets of every device buffer; the same walk sizes and carves.
 struct Carve {
-    size_t C, Ct, W, W32, Whi, Wlo, O, D, dsum, hubs, kidx, cost, parts, eps, cmax, Ch32, partial, anc, anc_cost,
-        anc_parts, best, best_cost, gen, stats, cand, cand_cnt, cand_cost, cand_parts, kidx_one, scratch;
+    size_t C, Ct, Ct32, W, W32, Whi, Wlo, Whsw, Wlsw, O, D, dsum, hubs, kidx, cost, parts, eps, cmax, Ch32, partial, anc, anc_cost,
+        anc_parts, best, best_cost, gen, stats, cand, cand_cnt, cand_cost, cand_parts, kidx_one, scratch, tbuf, slot_r, slot_c, handled, total_slots;
     size_t total;
 };
 
@@ -97,10 +101,13 @@ Carve carve(const Dims &d, int c_symmetric)
     const bool split = d.prec == kSplitBF16;
     c.C = L.take(n2 * cs);
     c.Ct = c_symmetric ? c.C : L.take(n2 * cs);
+    c.Ct32 = d.c_f32 ? c.Ct : L.take(n2 * 4);
     c.W = L.take(n2 * ws);
     c.W32 = (d.prec == kFP32 && !d.w_f32) ? L.take(n2 * 4) : (size_t)-1;
     c.Whi = split ? L.take(np2 * 2) : (size_t)-1;
     c.Wlo = split ? L.take(np2 * 2) : (size_t)-1;
+    c.Whsw = split ? L.take(np2 * 2) : (size_t)-1;
+    c.Wlsw = split ? L.take(np2 * 2) : (size_t)-1;
     c.O = L.take((size_t)d.n * 8);
     c.D = L.take((size_t)d.n * 8);
     c.dsum = L.take((size_t)d.n * 8);
@@ -125,6 +132,11 @@ Carve carve(const Dims &d, int c_symmetric)
     c.cand_parts = L.take((size_t)d.S * 24);
     c.kidx_one = L.take((size_t)d.n_pad * 2);
     c.scratch = L.take((size_t)d.n);
+    c.tbuf = d.prec == kFP64 ? (size_t)-1 : L.take((size_t)d.tot * d.n * 8);
+    c.slot_r = L.take((size_t)d.tot * 4);
+    c.slot_c = L.take((size_t)d.tot * 4);
+    c.handled = L.take((size_t)d.R * 4);
+    c.total_slots = L.take(4);
     c.total = L.total;
     return c;
 }
@@ -334,10 +346,13 @@ ga_status ga_init(const ga_params *q, const void *C, ga_dtype cdt, const void *W
         DevPtrs &P = ctx->P;
         P.C = at<void>(b, c.C);
         P.Ct = at<void>(b, c.Ct);
+        P.Ct32 = at<float>(b, c.Ct32);
         P.W = at<void>(b, c.W);
         P.W32 = at<float>(b, c.W32);
         P.Whi = at<uint16_t>(b, c.Whi);
         P.Wlo = at<uint16_t>(b, c.Wlo);
+        P.Whsw = at<uint16_t>(b, c.Whsw);
+        P.Wlsw = at<uint16_t>(b, c.Wlsw);
         P.O = at<double>(b, c.O);
         P.D = at<double>(b, c.D);
         P.dsum = at<double>(b, c.dsum);
@@ -362,6 +377,11 @@ ga_status ga_init(const ga_params *q, const void *C, ga_dtype cdt, const void *W
         P.cand_parts = at<double>(b, c.cand_parts);
         P.kidx_one = at<uint16_t>(b, c.kidx_one);
         P.scratch = at<uint8_t>(b, c.scratch);
+        P.tbuf = at<double>(b, c.tbuf);
+        P.slot_r = at<int32_t>(b, c.slot_r);
+        P.slot_c = at<int32_t>(b, c.slot_c);
+        P.handled = at<int32_t>(b, c.handled);
+        P.total = at<int32_t>(b, c.total_slots);
 
         const size_t n2 = (size_t)d.n * d.n;
         auto dev_fail = [&](hipError_t he, const char *what) {
@@ -625,6 +645,25 @@ ga_status ga_profile_read(ga_ctx *ctx, double *ms_total, int64_t *launches)
     }
     if (ms_total) *ms_total = tot;
     if (launches) *launches = ctx->ev_used / 2;
+    return GA_OK;
+}
+
+int32_t ga_tile_config_count(void) { return mfma_num_configs(); }
+
+ga_status ga_tile_config_info(int32_t cfg, int32_t *rows, int32_t *cols, int32_t *ktile)
+{
+    if (cfg < 0 || cfg >= mfma_num_configs()) return fail(nullptr, GA_ERR_INVALID, "no such tile configuration");
+    if (rows) *rows = mfma_rows_per_tile(cfg);
+    if (cols) *cols = mfma_cols_per_tile(cfg);
+    if (ktile) *ktile = mfma_k_tile(cfg);
+    return GA_OK;
+}
+
+ga_status ga_set_tile_config(ga_ctx *ctx, int32_t cfg)
+{
+    CTXCHK(ctx);
+    if (cfg < 0 || cfg >= mfma_num_configs()) return fail(ctx, GA_ERR_INVALID, "no such tile configuration");
+    ctx->d.mfma_cfg = cfg;
     return GA_OK;
 }
 

@@ -24,7 +24,10 @@ double fp32_eps_bound(int n);
 // batched matrix-core evaluation (eval_mfma.hip)
 hipError_t launch_eval_split(const DevPtrs &P, const Dims &d, const uint16_t *kidx, int count, hipStream_t st,
                              hipEvent_t ev0, hipEvent_t ev1);
-int mfma_row_tiles(const Dims &d);
+int mfma_num_configs();
+int mfma_rows_per_tile(int cfg);
+int mfma_cols_per_tile(int cfg);
+int mfma_k_tile(int cfg);
 
 // GA (ga_ops.hip, select.hip)
 hipError_t launch_ga_ops(const DevPtrs &P, const Dims &d, hipStream_t st);

@@ -84,6 +84,44 @@ __global__ void k_split_bf16(const T *__restrict__ W, int n, int n_pad, uint16_t
     lo[idx] = l;
 }
 
+// The same split written in fragment order: one thread per 16-byte chunk of
+// 8 consecutive k of one row; chunk ((g*KS + ks)*2 + h)*64 + rl holds row
+// g*64 + rl, k = ks*16 + h*8 .. +7 (KS = n_pad/16).
+template <typename T>
+__global__ void k_split_bf16_swz(const T *__restrict__ W, int n, int n_pad, uint16_t *__restrict__ hi,
+                                 uint16_t *__restrict__ lo)
+{
+#pragma clang fp contract(off)
+    size_t chunk = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t total = (size_t)n_pad * n_pad / 8;
+    if (chunk >= total) return;
+    const int KS = n_pad / 16;
+    const int rl = (int)(chunk % 64);
+    size_t t = chunk / 64;
+    const int h = (int)(t % 2);
+    t /= 2;
+    const int ks = (int)(t % KS), g = (int)(t / KS);
+    const int r = g * 64 + rl, k0 = ks * 16 + h * 8;
+    uint16_t vh[8], vl[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int k = k0 + e;
+        uint16_t a = 0, b = 0;
+        if (r < n && k < n) {
+            double x = (double)W[(size_t)r * n + k];
+            a = bf16_rne_bits(x);
+            b = bf16_rne_bits(x - bf16_to_double(a));
+        }
+        vh[e] = a;
+        vl[e] = b;
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        hi[chunk * 8 + e] = vh[e];
+        lo[chunk * 8 + e] = vl[e];
+    }
+}
+
 __global__ void k_to_f32(const double *__restrict__ src, float *__restrict__ dst, size_t count)
 {
     size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -162,6 +200,10 @@ hipError_t launch_prep(const DevPtrs &P, const Dims &d, hipStream_t st)
         size_t cnt = (size_t)n * n;
         k_to_f32<<<(unsigned)((cnt + tb - 1) / tb), tb, 0, st>>>((const double *)P.W, P.W32, cnt);
     }
+    if (!d.c_f32) {
+        size_t cnt = (size_t)n * n;
+        k_to_f32<<<(unsigned)((cnt + tb - 1) / tb), tb, 0, st>>>((const double *)P.Ct, P.Ct32, cnt);
+    }
     if (P.Whi) {
         size_t cnt = (size_t)d.n_pad * d.n_pad;
         unsigned g = (unsigned)((cnt + tb - 1) / tb);
@@ -169,6 +211,11 @@ hipError_t launch_prep(const DevPtrs &P, const Dims &d, hipStream_t st)
             k_split_bf16<float><<<g, tb, 0, st>>>((const float *)P.W, n, d.n_pad, P.Whi, P.Wlo);
         else
             k_split_bf16<double><<<g, tb, 0, st>>>((const double *)P.W, n, d.n_pad, P.Whi, P.Wlo);
+        unsigned gs = (unsigned)((cnt / 8 + tb - 1) / tb);
+        if (d.w_f32)
+            k_split_bf16_swz<float><<<gs, tb, 0, st>>>((const float *)P.W, n, d.n_pad, P.Whsw, P.Wlsw);
+        else
+            k_split_bf16_swz<double><<<gs, tb, 0, st>>>((const double *)P.W, n, d.n_pad, P.Whsw, P.Wlsw);
     }
     return hipGetLastError();
 }

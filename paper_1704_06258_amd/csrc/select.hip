@@ -31,12 +31,22 @@ __global__ __launch_bounds__(1024) void k_select1(const double *__restrict__ cos
     const int r = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
     const int s = r * m + tid;
     const bool live = tid < m;
+    const double fa = anc_cost[r];
     double f = live ? cost[s] : 0.0;
     double lb = f, ub = f;
+    bool same_as_anc = false;
     if (!exact && live) {
         double e = 2.0 * eps[s] + 8.881784197001252e-16;   // + 2^-50 for the interval arithmetic itself
         lb = f * (1.0 - e);
         ub = f * (1.0 + e);
+        // a child identical to the ancestor has the ancestor's exact cost
+        same_as_anc = true;
+        for (int k = 0; k < p; ++k)
+            if (children[(size_t)s * p + k] != anc[(size_t)r * p + k]) {
+                same_as_anc = false;
+                break;
+            }
+        if (same_as_anc) lb = ub = fa;
     }
     // (min ub, index) over the island; exact mode: (min f, lowest j)
     sv[tid] = ub;
@@ -50,7 +60,6 @@ __global__ __launch_bounds__(1024) void k_select1(const double *__restrict__ cos
         __syncthreads();
     }
     const double U = sv[0];
-    const double fa = anc_cost[r];
     if (exact) {
         if (tid == 0) {
             const int j = si[0];
@@ -69,7 +78,7 @@ __global__ __launch_bounds__(1024) void k_select1(const double *__restrict__ cos
         }
         return;
     }
-    const bool is_cand = live && lb <= U && (!elitist || lb < fa);
+    const bool is_cand = live && lb <= U && (!elitist || lb < fa) && !(elitist && same_as_anc);
     // compact candidates in ascending child order: wave ballots + per-wave offsets
     const unsigned long long mask = __ballot(is_cand);
     const int lane = tid & 63, wave = tid >> 6;

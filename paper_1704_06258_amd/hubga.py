@@ -27,7 +27,8 @@ DEFAULT_KERNEL = {GA_PREC_FP64: GA_KERN_PLAIN, GA_PREC_FP32: GA_KERN_PLAIN, GA_P
 # Every symbol declared in include/hubga.h.
 EXPORTS = ("ga_params_default", "ga_workspace_bytes", "ga_init", "ga_evaluate", "ga_evaluate_dev", "ga_step",
            "ga_best", "ga_solve", "ga_population", "ga_ancestors", "ga_get_state", "ga_set_state", "ga_stats",
-           "ga_profile_enable", "ga_profile_read", "ga_status_str", "ga_last_error", "ga_free")
+           "ga_profile_enable", "ga_profile_read", "ga_tile_config_count", "ga_tile_config_info",
+           "ga_set_tile_config", "ga_status_str", "ga_last_error", "ga_free")
 
 
 class ga_params(ct.Structure):
@@ -80,6 +81,12 @@ def lib():
                   "ga_ancestors", "ga_get_state", "ga_set_state", "ga_stats", "ga_profile_enable",
                   "ga_profile_read"):
             getattr(L, f).restype = ct.c_int
+        L.ga_tile_config_count.argtypes = []
+        L.ga_tile_config_count.restype = i32
+        L.ga_tile_config_info.argtypes = [i32, ct.POINTER(i32), ct.POINTER(i32), ct.POINTER(i32)]
+        L.ga_tile_config_info.restype = ct.c_int
+        L.ga_set_tile_config.argtypes = [vp, i32]
+        L.ga_set_tile_config.restype = ct.c_int
         L.ga_status_str.argtypes = [ct.c_int]
         L.ga_status_str.restype = ct.c_char_p
         L.ga_last_error.argtypes = [vp]
@@ -104,6 +111,16 @@ def _check(status, ctx=None):
 
 def _ptr(a) -> int:
     return a.ctypes.data if isinstance(a, np.ndarray) else int(a.data_ptr())
+
+
+def tile_configs():
+    """[(rows, cols, ktile)] of every tile configuration of the batched kernel."""
+    out = []
+    for c in range(lib().ga_tile_config_count()):
+        r, k, kt = ct.c_int32(), ct.c_int32(), ct.c_int32()
+        _check(lib().ga_tile_config_info(c, ct.byref(r), ct.byref(k), ct.byref(kt)))
+        out.append((r.value, k.value, kt.value))
+    return out
 
 
 def ga_params_default(n, p) -> ga_params:
@@ -245,6 +262,9 @@ class Solver:
         s = np.zeros(4, np.int64)
         _check(lib().ga_stats(self.ctx, s.ctypes.data), self.ctx)
         return dict(generations=int(s[0]), rechecks=int(s[1]), islands_rechecked=int(s[2]), evaluations=int(s[3]))
+
+    def set_tile_config(self, config: int):
+        _check(lib().ga_set_tile_config(self.ctx, int(config)), self.ctx)
 
     def profile_enable(self, on=True):
         _check(lib().ga_profile_enable(self.ctx, int(bool(on))), self.ctx)

@@ -36,7 +36,18 @@ def ref_eval(inst, hubs, want_alloc=False):
                            want_alloc=want_alloc)
 
 
+def fp32_tie_instance(seed=50, n=100, p=8):
+    """Integer distances plus perturbations of 1e-9: rounding to FP32 makes
+    many hub distances equal that differ in binary64 (allocation tie path)."""
+    rng = np.random.default_rng(seed)
+    C = rng.integers(100, 120, size=(n, n)).astype(np.float64) + 1e-9 * rng.random((n, n))
+    np.fill_diagonal(C, 0.0)
+    W = rng.uniform(0.0, 10.0, size=(n, n))
+    return I.Instance("fp32ties", C, W, p, 2.0, 0.75, 1.5)
+
+
 EXACT_CASES = [
+    ("fp32_ties_n100_p8", lambda: fp32_tie_instance(), 64),
     ("small_n25_p3", lambda: I.small(), 64),
     ("medium_n200_p10", lambda: I.medium(), 200),
     ("asym_n77_p5_integer_ties", lambda: I.random_asymmetric(seed=3, n=77, p=5, integer=True), 96),
@@ -249,3 +260,68 @@ def test_rerun_determinism_and_solve():
         assert a.get_state() == b.get_state()
         c, _ = ref_eval(inst, ra["hubs"][None])
         assert c[0] == ra["cost"]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+@pytest.mark.parametrize("elitist", [1, 0])
+@pytest.mark.parametrize("n,p", [(3, 1), (6, 5)])
+def test_certified_selection_with_planted_ties(precision, elitist, n, p):
+    """Tiny hub-set spaces make most children exact duplicates: islands carry
+    many candidates within the error bound (more than the column-parallel
+    re-evaluation slots), and ties must resolve to the lowest child index."""
+    inst = I.uniform(seed=40 + n, n=n, p=p)
+    st = oracle_trajectory(inst, 12, S=256, m=64, n1=3, seed=5, elitist=elitist)
+    with make(inst, population=256, island_size=64, n1=3, seed=5, precision=precision, elitist=bool(elitist)) as s:
+        s.step(12)
+        assert_same_state(s, st)
+        stats = s.stats()
+    if not elitist:
+        assert stats["rechecks"] > 0
+    if not elitist and n == 3:
+        assert stats["rechecks"] > 12 * 4 * 16   # beyond the 16 column-parallel slots per island
+
+
+def test_every_tile_config_within_bound_and_same_trajectory():
+    inst = I.uniform(seed=60, n=333, p=11)
+    hubs = I.random_hub_sets(8, inst.n, inst.p, 200)
+    ref_c, _ = ref_eval(inst, hubs)
+    st = oracle_trajectory(inst, 6, S=256, m=32, n1=3, seed=2)
+    for cfg in range(len(hubga.tile_configs())):
+        with make(inst, population=256, island_size=32, n1=3, seed=2, precision="split_bf16") as s:
+            s.set_tile_config(cfg)
+            out = s.evaluate(hubs)
+            err = np.abs(out["cost"] - ref_c) / ref_c
+            assert np.all(err <= out["eps"]), (cfg, err.max())
+            s.step(6)
+            assert_same_state(s, st)
+    with pytest.raises(hubga.HubGAError):
+        with make(inst, population=256, island_size=32, precision="split_bf16") as s:
+            s.set_tile_config(len(hubga.tile_configs()))
+
+
+def test_autotuner_picks_a_config(tmp_path):
+    from paper_1704_06258_amd import autotune
+    inst = I.medium()
+    with make(inst, population=512, island_size=64, precision="split_bf16") as s:
+        s.step(1)
+        res = autotune.autotune(s, cache_path=str(tmp_path / "tiles.json"), reps=2)
+        assert res["config"] in res["ms"] and not res["cached"]
+        again = autotune.autotune(s, cache_path=str(tmp_path / "tiles.json"))
+        assert again["cached"] and again["config"] == res["config"]
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 5, 50])
+def test_pipelined_configs_all_hub_counts(p):
+    """The pipelined tile configurations stage every wave's hub positions in
+    LDS; few hubs per individual mean many individuals per wave (p <= 2 falls
+    back to per-lane fragment loads)."""
+    inst = I.uniform(seed=70 + p, n=260, p=p)
+    hubs = I.random_hub_sets(9, inst.n, inst.p, 96)
+    ref_c, _ = ref_eval(inst, hubs)
+    n_cfg = len(hubga.tile_configs())
+    for cfg in range(6, n_cfg):
+        with make(inst, population=96, island_size=32, precision="split_bf16") as s:
+            s.set_tile_config(cfg)
+            out = s.evaluate(hubs)
+        err = np.abs(out["cost"] - ref_c) / ref_c
+        assert np.all(err <= out["eps"]), (cfg, err.max())
