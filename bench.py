@@ -96,6 +96,37 @@ def cpu_baseline(inst, gpu_hubs, gpu_cost, budget_s=12.0):
                        f"{t_used:.1f} s of CPU work"), float(err.max())
 
 
+def serving_leg(count, warmup, rate=200.0, budget=16 << 30, slots=32):
+    """Continuous-batching serving of a Poisson request stream: p50/p99
+    latency from scheduled arrival to result, completed solves/s and
+    evaluations/s.  Instances come from a pool of 4 seeded instances per size
+    (generated before the run); every request has its own GA seed."""
+    from paper_1704_06258_amd import instances as I
+    from paper_1704_06258_amd import serve
+    stream = I.serving_requests(count, rate=rate, seed=5, generations=100)
+    pool = {}
+    reqs = []
+    for q in stream:
+        key = (q.n, q.rid % 4)
+        if key not in pool:
+            pool[key] = I.uniform(seed=5_000_000 + 7 * q.n + key[1], n=q.n, p=3)
+        inst = pool[key]
+        reqs.append(serve.SolveRequest(q.rid, q.arrival, inst.C, inst.W, q.p, 3.0, 0.75, 2.0, q.S, q.generations,
+                                       q.ga_seed))
+    srv = serve.Server(hbm_budget=budget, max_slots=slots)
+    t0 = time.perf_counter()
+    res = srv.run(reqs, realtime=True)
+    wall = time.perf_counter() - t0
+    srv.close()
+    measured = [r for r in res if r.rid >= warmup]
+    st = serve.latency_stats(measured)
+    evals = sum(reqs[r.rid].population * reqs[r.rid].generations for r in res)
+    return {"requests": count, "warmup": warmup, "rate_per_s": rate, "generations": 100,
+            "p50_latency_s": st.get("p50_s"), "p99_latency_s": st.get("p99_s"), "mean_latency_s": st.get("mean_s"),
+            "completed_per_s": len(res) / wall, "evals_per_s": evals / wall, "max_resident": srv.max_resident,
+            "ticks": srv.ticks, "budget_bytes": budget, "slots": slots}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,6 +137,12 @@ def main():
     ap.add_argument("--tile-config", default="auto",
                     help="tile configuration of the batched kernel: an index, or 'auto' to run the autotuner "
                          "(outside the timed region)")
+    ap.add_argument("--serve-requests", type=int, default=300,
+                    help="requests of the serving leg (Poisson arrivals at 200/s, size mix n in "
+                         "{50..2000}, p in {3,5,10,20}, population in {256..2048}, 100 generations); 0 skips it")
+    ap.add_argument("--serve-warmup", type=int, default=50)
+    ap.add_argument("--serve-full", action="store_true",
+                    help="only the serving workload at full size: 200 warm-up + 2000 measured requests")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run an elementwise copy of 256 MiB (reads 256 MiB, writes 256 MiB) five times, "
                          "to scale HBM byte counters")
@@ -119,6 +156,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibration": "elementwise copy", "bytes_read": a.numel() * 4,
                           "bytes_written": b.numel() * 4, "launches": 5}))
+        return
+    if args.serve_full:
+        print(json.dumps({"serving": serving_leg(2200, 200)}), flush=True)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
@@ -192,6 +232,9 @@ def main():
         out["plain"] = plain
         out["speedup_vs_plain_fp64"] = value / plain["fp64"]["evals_per_s"]
         out["speedup_vs_plain_fp32"] = value / plain["fp32"]["evals_per_s"]
+
+    if args.serve_requests > 0:
+        out["serving"] = serving_leg(args.serve_requests, args.serve_warmup)
 
     if not args.no_cpu:
         cb, err = cpu_baseline(inst, gpu_hubs, gpu_cost)

@@ -190,6 +190,25 @@ int32_t ga_tile_config_count(void);
 ga_status ga_tile_config_info(int32_t config, int32_t *rows, int32_t *cols, int32_t *ktile);
 ga_status ga_set_tile_config(ga_ctx *ctx, int32_t config);
 
+/* Batches: several contexts advanced together, generation by generation (the
+ * islands of every context run the steps of ga_step).  One generation of the
+ * whole batch is captured once as a HIP graph: per-context operator,
+ * allocation and selection chains run as parallel branches, and the
+ * matrix-core products of all split-bf16 contexts with p >= 3 are one grouped
+ * launch over their concatenated tiles (tile_config must be a pipelined
+ * configuration, see ga_tile_config_info).  Every context must use the
+ * batch's (non-null) stream and must not be stepped on its own while it is
+ * in the batch.  ga_batch_set waits for queued work, replaces the batch's
+ * contexts and captures a new graph; ga_batch_step replays it (enqueued,
+ * returns without waiting).  Results are those of stepping each context
+ * alone.  For callers that mix requests: a context's generation counter,
+ * best and state are read with the usual per-context calls. */
+typedef struct ga_batch ga_batch;
+ga_status ga_batch_create(void *hip_stream, int32_t tile_config, ga_batch **out);
+ga_status ga_batch_set(ga_batch *batch, ga_ctx *const *ctxs, int32_t count);
+ga_status ga_batch_step(ga_batch *batch, int32_t generations);
+void ga_batch_free(ga_batch *batch);
+
 const char *ga_status_str(ga_status s);
 const char *ga_last_error(const ga_ctx *ctx);   /* also valid for ctx == NULL (last init error) */
 void ga_free(ga_ctx *ctx);                        /* waits for queued work; NULL is a no-op */

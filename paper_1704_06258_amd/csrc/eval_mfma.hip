@@ -230,13 +230,24 @@ __device__ __forceinline__ void wg_barrier()
     asm volatile("" ::: "memory");
 }
 
-template <int ROWB, int COLB, int NST, int KINS, int OCC>
-__global__ __launch_bounds__(256, OCC) void k_eval_mfma_pipe(const u32x4 *__restrict__ Whsw,
-                                                              const u32x4 *__restrict__ Wlsw,
-                                                              const uint16_t *__restrict__ kidx,
-                                                              const float *__restrict__ Ch32, int n, int n_pad, int p,
-                                                              int count, int NS, int n_mt, int n_nt,
-                                                              double *__restrict__ partial)
+// One context's operands for the batched kernel (also one entry of a grouped
+// launch over several contexts).
+struct MfmaJob {
+    const u32x4 *Whsw, *Wlsw;
+    const uint16_t *kidx;
+    const float *Ch32;
+    double *partial;
+    int n, n_pad, p, count, NS, n_mt, n_nt, tile_start;
+};
+
+template <int ROWB, int COLB, int NST, int KINS>
+constexpr int pipe_ring_chunks()
+{
+    return NST * (2 * 2 * 2 * 32 * ROWB + 4 * KINS * 64);
+}
+
+template <int ROWB, int COLB, int NST, int KINS>
+__device__ __forceinline__ void mfma_pipe_tile(const MfmaJob &J, int tile, u32x4 *ring)
 {
     constexpr int MT = 32 * ROWB, NT = 128 * COLB, KTILE = 32, KSTEPS = KTILE / 16;
     constexpr int A_CHUNKS = 2 * KSTEPS * 2 * MT;   // [hi/lo][kk][half][row] 16-byte chunks per stage
@@ -245,12 +256,12 @@ __global__ __launch_bounds__(256, OCC) void k_eval_mfma_pipe(const u32x4 *__rest
     constexpr int A_INS = A_CHUNKS / 64 / 4;        // 1 KB transfers per wave per tile for W
     constexpr int LPT = A_INS + KINS;               // vector-memory instructions per wave per tile
     static_assert(MT % 64 == 0 && (A_CHUNKS / 64) % 4 == 0, "tile shape");
-    __shared__ __align__(16) u32x4 ring[NST * STAGE];
-
-    const int tiles = n_mt * n_nt;
-    const int per = (tiles + 7) / 8;
-    const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-    if (tile >= tiles) return;
+    const u32x4 *__restrict__ Whsw = J.Whsw;
+    const u32x4 *__restrict__ Wlsw = J.Wlsw;
+    const uint16_t *__restrict__ kidx = J.kidx;
+    const float *__restrict__ Ch32 = J.Ch32;
+    double *__restrict__ partial = J.partial;
+    const int n = J.n, n_pad = J.n_pad, p = J.p, count = J.count, NS = J.NS, n_mt = J.n_mt, n_nt = J.n_nt;
     const int mt = tile / n_nt, nt = tile % n_nt;
     const int M0 = mt * MT, N0 = nt * NT;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -385,6 +396,40 @@ __global__ __launch_bounds__(256, OCC) void k_eval_mfma_pipe(const u32x4 *__rest
     }
 }
 
+template <int ROWB, int COLB, int NST, int KINS, int OCC>
+__global__ __launch_bounds__(256, OCC) void k_eval_mfma_pipe(MfmaJob J)
+{
+    __shared__ __align__(16) u32x4 ring[pipe_ring_chunks<ROWB, COLB, NST, KINS>()];
+    const int tiles = J.n_mt * J.n_nt;
+    const int per = (tiles + 7) / 8;
+    const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (tile >= tiles) return;
+    mfma_pipe_tile<ROWB, COLB, NST, KINS>(J, tile, ring);
+}
+
+// One launch over the tiles of several contexts: the concatenated tile list
+// (each context row-tile major) is split into 8 contiguous ranges, one per
+// XCD (blockIdx % 8), so every XCD walks whole row panels.
+template <int ROWB, int COLB, int NST, int KINS, int OCC>
+__global__ __launch_bounds__(256, OCC) void k_eval_mfma_pipe_group(const MfmaJob *__restrict__ jobs, int njobs,
+                                                                   int total_tiles)
+{
+    __shared__ __align__(16) u32x4 ring[pipe_ring_chunks<ROWB, COLB, NST, KINS>()];
+    const int per = (total_tiles + 7) / 8;
+    const int t = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (t >= total_tiles) return;
+    int lo = 0, hi = njobs - 1;   // last job with tile_start <= t
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].tile_start <= t)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const MfmaJob J = jobs[lo];
+    mfma_pipe_tile<ROWB, COLB, NST, KINS>(J, t - J.tile_start, ring);
+}
+
 // T_s = sum of the individual's p*n_mt partials (contiguous), one wave per
 // individual with a fixed reduction order; cost assembly
 // f = ((chi*Cc) + (alpha*T)) + (delta*Dd) and its relative error bound.
@@ -438,9 +483,9 @@ static hipError_t pipe_launch(const DevPtrs &P, const Dims &d, const uint16_t *k
     const int n_nt = (NS + NT - 1) / NT;
     const int tiles = n_mt * n_nt;
     const int per = (tiles + 7) / 8;
-    k_eval_mfma_pipe<ROWB, COLB, NST, KINS, OCC><<<per * 8, 256, 0, st>>>(
-        (const u32x4 *)P.Whsw, (const u32x4 *)P.Wlsw, kidx, P.Ch32, d.n, d.n_pad, d.p, count, NS, n_mt, n_nt,
-        P.partial);
+    MfmaJob J{(const u32x4 *)P.Whsw, (const u32x4 *)P.Wlsw, kidx, P.Ch32, P.partial, d.n, d.n_pad, d.p, count,
+              NS, n_mt, n_nt, 0};
+    k_eval_mfma_pipe<ROWB, COLB, NST, KINS, OCC><<<per * 8, 256, 0, st>>>(J);
     return hipGetLastError();
 }
 
@@ -471,33 +516,106 @@ int mfma_pipelined(int cfg) { return kMfmaCfgs[cfg].nst > 0; }
 int mfma_cols_per_tile(int cfg) { return 128 * kMfmaCfgs[cfg].colb; }
 int mfma_k_tile(int cfg) { return kMfmaCfgs[cfg].kt; }
 
+hipError_t launch_mfma(const DevPtrs &P, const Dims &d, const uint16_t *kidx, int count, hipStream_t st)
+{
+    if (count <= 0) return hipSuccess;
+    switch (d.mfma_cfg) {
+    case 0: return mfma_launch<4, 2, 32, 2>(P, d, kidx, count, st);
+    case 1: return mfma_launch<4, 2, 64, 1>(P, d, kidx, count, st);
+    case 2: return mfma_launch<4, 4, 32, 1>(P, d, kidx, count, st);
+    case 3: return mfma_launch<2, 4, 32, 2>(P, d, kidx, count, st);
+    case 4: return mfma_launch<4, 4, 64, 1>(P, d, kidx, count, st);
+    case 5: return mfma_launch<2, 2, 64, 2>(P, d, kidx, count, st);
+    case 6: return pipe_dispatch<4, 2, 4, 1>(P, d, kidx, count, st);
+    case 7: return pipe_dispatch<4, 2, 3, 2>(P, d, kidx, count, st);
+    case 8: return pipe_dispatch<4, 4, 4, 1>(P, d, kidx, count, st);
+    case 9: return pipe_dispatch<4, 4, 3, 1>(P, d, kidx, count, st);
+    default: return pipe_dispatch<2, 4, 4, 2>(P, d, kidx, count, st);
+    }
+}
+
+// Row tiles the partials of configuration cfg use for p hubs.
+int mfma_partial_tiles(const Dims &d, int cfg)
+{
+    int rows = mfma_rows_per_tile(cfg);
+    if (mfma_pipelined(cfg) && kidx_transfers(kMfmaCfgs[cfg].colb, d.p) > 2) rows = 128;
+    return d.n_pad / rows;
+}
+
+hipError_t launch_finalize(const DevPtrs &P, const Dims &d, int count, int cfg, hipStream_t st)
+{
+    if (count <= 0) return hipSuccess;
+    const int n_mt = mfma_partial_tiles(d, cfg);
+    k_finalize_split<<<(count + 3) / 4, 256, 0, st>>>(P.partial, P.cmax, count, d.p, n_mt, d.n, d.c_f32, d.chi,
+                                                      d.alpha, d.delta, d.scale, P.cost, P.parts, P.eps);
+    return hipGetLastError();
+}
+
 hipError_t launch_eval_split(const DevPtrs &P, const Dims &d, const uint16_t *kidx, int count, hipStream_t st,
                              hipEvent_t ev0, hipEvent_t ev1)
 {
     if (count <= 0) return hipSuccess;
     hipError_t e;
     if (ev0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return e;
-    switch (d.mfma_cfg) {
-    case 0: e = mfma_launch<4, 2, 32, 2>(P, d, kidx, count, st); break;
-    case 1: e = mfma_launch<4, 2, 64, 1>(P, d, kidx, count, st); break;
-    case 2: e = mfma_launch<4, 4, 32, 1>(P, d, kidx, count, st); break;
-    case 3: e = mfma_launch<2, 4, 32, 2>(P, d, kidx, count, st); break;
-    case 4: e = mfma_launch<4, 4, 64, 1>(P, d, kidx, count, st); break;
-    case 5: e = mfma_launch<2, 2, 64, 2>(P, d, kidx, count, st); break;
-    case 6: e = pipe_dispatch<4, 2, 4, 1>(P, d, kidx, count, st); break;
-    case 7: e = pipe_dispatch<4, 2, 3, 2>(P, d, kidx, count, st); break;
-    case 8: e = pipe_dispatch<4, 4, 4, 1>(P, d, kidx, count, st); break;
-    case 9: e = pipe_dispatch<4, 4, 3, 1>(P, d, kidx, count, st); break;
-    default: e = pipe_dispatch<2, 4, 4, 2>(P, d, kidx, count, st); break;
-    }
-    if (e != hipSuccess) return e;
+    if ((e = launch_mfma(P, d, kidx, count, st)) != hipSuccess) return e;
     if (ev1 && (e = hipEventRecord(ev1, st)) != hipSuccess) return e;
-    int rows = mfma_rows_per_tile(d.mfma_cfg);
-    if (mfma_pipelined(d.mfma_cfg) && kidx_transfers(kMfmaCfgs[d.mfma_cfg].colb, d.p) > 2) rows = 128;
-    const int n_mt = d.n_pad / rows;
-    k_finalize_split<<<(count + 3) / 4, 256, 0, st>>>(P.partial, P.cmax, count, d.p, n_mt, d.n, d.c_f32, d.chi,
-                                                          d.alpha, d.delta, d.scale, P.cost, P.parts, P.eps);
+    return launch_finalize(P, d, count, d.mfma_cfg, st);
+}
+
+// Grouped launch over several contexts' populations (one tile configuration,
+// pipelined, at least 3 hubs per context).
+bool mfma_groupable(const Dims &d, int cfg)
+{
+    return mfma_pipelined(cfg) && kidx_transfers(kMfmaCfgs[cfg].colb, d.p) <= 2;
+}
+
+size_t mfma_job_bytes() { return sizeof(MfmaJob); }
+
+// Fill jobs (host array, one per context) and return the total tile count.
+int mfma_fill_jobs(const DevPtrs *const *P, const Dims *const *d, int njobs, int cfg, void *jobs_host)
+{
+    MfmaJob *J = (MfmaJob *)jobs_host;
+    const int MT = mfma_rows_per_tile(cfg), NT = mfma_cols_per_tile(cfg);
+    int start = 0;
+    for (int j = 0; j < njobs; ++j) {
+        const int NS = d[j]->S * d[j]->p;
+        const int n_mt = d[j]->n_pad / MT, n_nt = (NS + NT - 1) / NT;
+        J[j] = MfmaJob{(const u32x4 *)P[j]->Whsw, (const u32x4 *)P[j]->Wlsw, P[j]->kidx, P[j]->Ch32, P[j]->partial,
+                       d[j]->n, d[j]->n_pad, d[j]->p, d[j]->S, NS, n_mt, n_nt, start};
+        start += n_mt * n_nt;
+    }
+    return start;
+}
+
+template <int ROWB, int COLB, int NST, int KINS, int OCC>
+static hipError_t group_launch(const void *d_jobs, int njobs, int total, hipStream_t st)
+{
+    const int per = (total + 7) / 8;
+    k_eval_mfma_pipe_group<ROWB, COLB, NST, KINS, OCC><<<per * 8, 256, 0, st>>>((const MfmaJob *)d_jobs, njobs,
+                                                                               total);
     return hipGetLastError();
+}
+
+template <int ROWB, int COLB, int NST, int OCC>
+static hipError_t group_dispatch(int kins, const void *d_jobs, int njobs, int total, hipStream_t st)
+{
+    if (kins <= 1) return group_launch<ROWB, COLB, NST, 1, OCC>(d_jobs, njobs, total, st);
+    return group_launch<ROWB, COLB, NST, 2, OCC>(d_jobs, njobs, total, st);
+}
+
+hipError_t launch_mfma_group(const void *d_jobs, int njobs, int total, int cfg, int min_p, hipStream_t st)
+{
+    if (njobs <= 0 || total <= 0) return hipSuccess;
+    const int kins = kidx_transfers(kMfmaCfgs[cfg].colb, min_p);
+    if (kins > 2) return hipErrorInvalidValue;
+    switch (cfg) {
+    case 6: return group_dispatch<4, 2, 4, 1>(kins, d_jobs, njobs, total, st);
+    case 7: return group_dispatch<4, 2, 3, 2>(kins, d_jobs, njobs, total, st);
+    case 8: return group_dispatch<4, 4, 4, 1>(kins, d_jobs, njobs, total, st);
+    case 9: return group_dispatch<4, 4, 3, 1>(kins, d_jobs, njobs, total, st);
+    case 10: return group_dispatch<2, 4, 4, 2>(kins, d_jobs, njobs, total, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace hubga

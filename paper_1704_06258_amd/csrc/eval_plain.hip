@@ -412,9 +412,6 @@ static hipError_t exact_launch(const DevPtrs &P, const Dims &d, const int32_t *h
                                double *cost, double *parts, double *eps, hipStream_t st)
 {
     size_t sm = exact_smem_bytes(d.n, d.p);
-    hipError_t e = hipFuncSetAttribute((const void *)k_eval_exact<CT, WT>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
-    if (e != hipSuccess) return e;
     k_eval_exact<CT, WT><<<count, eval_block(d.n), sm, st>>>(hubs, kidx, count, d.n, d.n_pad, d.p, (const CT *)P.C,
                                                              (const WT *)P.W, P.O, P.D, d.chi, d.alpha, d.delta,
                                                              d.scale, cost, parts, eps);
@@ -438,21 +435,15 @@ static hipError_t recheck_launch(const DevPtrs &P, const Dims &d, int ychunks, h
     k_compact<<<1, 256, 0, st>>>(P.cand_cnt, d.R, d.tot, P.slot_r, P.slot_c, P.handled, P.total);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     size_t smA = canon_cols_smem(d.n, d.p);
-    e = hipFuncSetAttribute((const void *)k_canon_cols<CT, WT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smA);
-    if (e != hipSuccess) return e;
     k_canon_cols<CT, WT><<<512, 256, smA, st>>>(P.hubs, P.kidx, P.cand, P.slot_r, P.slot_c, P.total, d.m, d.n,
                                                 d.n_pad, d.p, (const CT *)P.C, (const WT *)P.W, P.tbuf);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     size_t smB = (size_t)16 * d.n;
-    e = hipFuncSetAttribute((const void *)k_canon_sums<CT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smB);
-    if (e != hipSuccess) return e;
     k_canon_sums<CT><<<256, 256, smB, st>>>(P.hubs, P.kidx, P.cand, P.slot_r, P.slot_c, P.total, d.m, d.n, d.n_pad,
                                             d.p, (const CT *)P.C, P.O, P.D, P.tbuf, d.chi, d.alpha, d.delta, d.scale,
                                             P.cand_cost, P.cand_parts);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     size_t sm = exact_smem_bytes(d.n, d.p);
-    e = hipFuncSetAttribute((const void *)k_recheck<CT, WT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
-    if (e != hipSuccess) return e;
     dim3 grid(d.R, ychunks);
     k_recheck<CT, WT><<<grid, eval_block(d.n), sm, st>>>(P.hubs, P.kidx, P.cand, P.cand_cnt, P.handled, d.m, d.n,
                                                          d.n_pad, d.p, (const CT *)P.C, (const WT *)P.W, P.O, P.D,
@@ -482,22 +473,35 @@ hipError_t launch_eval_fp32(const DevPtrs &P, const Dims &d, const int32_t *hubs
     const float *W = d.w_f32 ? (const float *)P.W : P.W32;
     size_t sm = (size_t)kMaxP * kMaxP * 4 + (size_t)d.n * 2 + 16;
     double eb = fp32_eps_bound(d.n);
-    hipError_t e;
     if (d.c_f32) {
-        e = hipFuncSetAttribute((const void *)k_eval_fp32<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
-        if (e != hipSuccess) return e;
         k_eval_fp32<float><<<count, eval_block(d.n), sm, st>>>(hubs, kidx, count, d.n, d.n_pad, d.p,
                                                                 (const float *)P.Ct, W, d.chi, d.alpha, d.delta,
                                                                 d.scale, eb, P.cost, P.parts, P.eps);
     } else {
-        e = hipFuncSetAttribute((const void *)k_eval_fp32<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)sm);
-        if (e != hipSuccess) return e;
         k_eval_fp32<double><<<count, eval_block(d.n), sm, st>>>(hubs, kidx, count, d.n, d.n_pad, d.p,
                                                                  (const double *)P.Ct, W, d.chi, d.alpha, d.delta,
                                                                  d.scale, eb, P.cost, P.parts, P.eps);
     }
     return hipGetLastError();
+}
+
+// Raise the dynamic-LDS cap of every kernel here that may need more than the
+// default, once per process (never during graph capture).
+hipError_t prepare_plain_kernels(int max_lds)
+{
+    const void *fns[] = {(const void *)k_eval_exact<double, double>, (const void *)k_eval_exact<double, float>,
+                         (const void *)k_eval_exact<float, double>,  (const void *)k_eval_exact<float, float>,
+                         (const void *)k_recheck<double, double>,    (const void *)k_recheck<double, float>,
+                         (const void *)k_recheck<float, double>,     (const void *)k_recheck<float, float>,
+                         (const void *)k_canon_cols<double, double>, (const void *)k_canon_cols<double, float>,
+                         (const void *)k_canon_cols<float, double>,  (const void *)k_canon_cols<float, float>,
+                         (const void *)k_canon_sums<double>,         (const void *)k_canon_sums<float>,
+                         (const void *)k_eval_fp32<double>,          (const void *)k_eval_fp32<float>};
+    for (const void *f : fns) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace hubga

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <cstring>
 #include <new>
 #include <string>
@@ -162,6 +163,28 @@ struct ga_ctx {
     bool prof_on = false;
     std::vector<hipEvent_t> ev;
     int ev_used = 0;
+    // one captured generation, replayed by ga_step (needs a non-null stream)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    bool graph_failed = false;
+    // the two halves of a generation around a grouped matrix-core launch,
+    // captured for one grouping (grouped_cfg, or -1 for not grouped)
+    hipGraphExec_t pre_exec = nullptr, post_exec = nullptr;
+    int halves_cfg = -2;
+};
+
+struct ga_batch {
+    hipStream_t st = nullptr;
+    int cfg = 7;
+    std::vector<ga_ctx *> ctxs;
+    std::vector<char> grouped;
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> ev;      // fork/join events
+    void *d_jobs = nullptr;          // device job table of the grouped launch
+    void *h_jobs = nullptr;          // pinned staging of the job table
+    size_t jobs_cap = 0;
+    hipEvent_t jobs_copied = nullptr;
+    int njobs = 0, total_tiles = 0, min_p = 0;
 };
 
 namespace {
@@ -200,41 +223,104 @@ void prof_events(ga_ctx *ctx, hipEvent_t *a, hipEvent_t *b)
 }
 
 // Evaluate `count` sorted hub sets at `hubs` (device) into P.cost / P.parts /
-// P.eps, hub positions into `kidx`.
-ga_status run_eval(ga_ctx *ctx, const int32_t *hubs, int count, uint16_t *kidx)
+// P.eps, hub positions into `kidx`, on stream s.
+ga_status run_eval(ga_ctx *ctx, const int32_t *hubs, int count, uint16_t *kidx, hipStream_t s)
 {
     const Dims &d = ctx->d;
     const DevPtrs &P = ctx->P;
     hipEvent_t a, b;
     prof_events(ctx, &a, &b);
     if (d.prec == kFP64) {
-        HIPCHK(launch_alloc(P, d, hubs, count, kidx, 0, 0, ctx->st));
-        if (a) HIPCHK(hipEventRecord(a, ctx->st));
-        HIPCHK(launch_eval_exact(P, d, hubs, kidx, count, P.cost, P.parts, P.eps, ctx->st));
-        if (b) HIPCHK(hipEventRecord(b, ctx->st));
+        HIPCHK(launch_alloc(P, d, hubs, count, kidx, 0, 0, s));
+        if (a) HIPCHK(hipEventRecord(a, s));
+        HIPCHK(launch_eval_exact(P, d, hubs, kidx, count, P.cost, P.parts, P.eps, s));
+        if (b) HIPCHK(hipEventRecord(b, s));
     } else if (d.prec == kFP32) {
-        HIPCHK(launch_alloc(P, d, hubs, count, kidx, 1, 0, ctx->st));
-        if (a) HIPCHK(hipEventRecord(a, ctx->st));
-        HIPCHK(launch_eval_fp32(P, d, hubs, kidx, count, ctx->st));
-        if (b) HIPCHK(hipEventRecord(b, ctx->st));
+        HIPCHK(launch_alloc(P, d, hubs, count, kidx, 1, 0, s));
+        if (a) HIPCHK(hipEventRecord(a, s));
+        HIPCHK(launch_eval_fp32(P, d, hubs, kidx, count, s));
+        if (b) HIPCHK(hipEventRecord(b, s));
     } else {
-        HIPCHK(launch_alloc(P, d, hubs, count, kidx, 1, 1, ctx->st));
-        HIPCHK(launch_eval_split(P, d, kidx, count, ctx->st, a, b));
+        HIPCHK(launch_alloc(P, d, hubs, count, kidx, 1, 1, s));
+        HIPCHK(launch_eval_split(P, d, kidx, count, s, a, b));
     }
+    return GA_OK;
+}
+
+ga_status run_eval(ga_ctx *ctx, const int32_t *hubs, int count, uint16_t *kidx)
+{
+    return run_eval(ctx, hubs, count, kidx, ctx->st);
+}
+
+// A generation in two halves around the batched evaluation.  With `grouped`
+// the matrix-core product is left to a grouped launch over several contexts.
+ga_status gen_pre(ga_ctx *ctx, hipStream_t s, bool grouped)
+{
+    const Dims &d = ctx->d;
+    const DevPtrs &P = ctx->P;
+    HIPCHK(launch_ga_ops(P, d, s));
+    if (grouped) {
+        HIPCHK(launch_alloc(P, d, P.hubs, d.S, P.kidx, 1, 1, s));
+        return GA_OK;
+    }
+    return run_eval(ctx, P.hubs, d.S, P.kidx, s);
+}
+
+ga_status gen_post(ga_ctx *ctx, hipStream_t s, bool grouped, int group_cfg)
+{
+    const Dims &d = ctx->d;
+    const DevPtrs &P = ctx->P;
+    const int exact = d.prec == kFP64;
+    if (grouped) HIPCHK(launch_finalize(P, d, d.S, group_cfg, s));
+    HIPCHK(launch_select(P, d, exact, s));
+    HIPCHK(launch_global(P, d, exact, s));
     return GA_OK;
 }
 
 ga_status run_generation(ga_ctx *ctx)
 {
-    const Dims &d = ctx->d;
-    const DevPtrs &P = ctx->P;
-    const int exact = d.prec == kFP64;
-    HIPCHK(launch_ga_ops(P, d, ctx->st));
-    ga_status s = run_eval(ctx, P.hubs, d.S, P.kidx);
-    if (s != GA_OK) return s;
-    HIPCHK(launch_select(P, d, exact, ctx->st));
-    HIPCHK(launch_global(P, d, exact, ctx->st));
-    return GA_OK;
+    ga_status st = gen_pre(ctx, ctx->st, false);
+    if (st != GA_OK) return st;
+    return gen_post(ctx, ctx->st, false, 0);
+}
+
+void drop_graph(ga_ctx *ctx)
+{
+    if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    ctx->gexec = nullptr;
+    ctx->graph = nullptr;
+}
+
+// Capture one generation on the context's stream; false if the stream cannot
+// be captured (then generations are launched directly).
+bool capture_generation(ga_ctx *ctx)
+{
+    if (!ctx->st || ctx->graph_failed) return false;
+    if (hipStreamBeginCapture(ctx->st, hipStreamCaptureModeRelaxed) != hipSuccess) {
+        ctx->graph_failed = true;
+        return false;
+    }
+    ga_status gs = run_generation(ctx);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(ctx->st, &g);
+    if (gs != GA_OK || e != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        ctx->poisoned = false;   // a failed capture enqueued nothing
+        ctx->graph_failed = true;
+        (void)hipGetLastError();
+        return false;
+    }
+    hipGraphExec_t x = nullptr;
+    if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        ctx->graph_failed = true;
+        (void)hipGetLastError();
+        return false;
+    }
+    ctx->graph = g;
+    ctx->gexec = x;
+    return true;
 }
 
 template <typename T>
@@ -322,6 +408,26 @@ ga_status ga_init(const ga_params *q, const void *C, ga_dtype cdt, const void *W
             return fail(nullptr, GA_ERR_INVALID, "c_symmetric is set but C is not symmetric");
         Dims d = make_dims(q, cdt, wdt);
         Carve c = carve(d, q->c_symmetric);
+        {
+            static std::once_flag once;
+            static hipError_t prep_err = hipSuccess;
+            std::call_once(once, [] {
+                int dev = 0, max_lds = 65536;
+                if (hipGetDevice(&dev) == hipSuccess)
+                    (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+                prep_err = prepare_plain_kernels(max_lds);
+            });
+            if (prep_err != hipSuccess)
+                return fail(nullptr, GA_ERR_DEVICE, std::string("kernel attributes: ") + hipGetErrorString(prep_err));
+        }
+        if (make_dims(q, cdt, wdt).n > 0) {
+            int dev = 0, max_lds = 65536;
+            if (hipGetDevice(&dev) == hipSuccess)
+                (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+            const size_t need = std::max<size_t>((size_t)d.p * d.p * 8 + (size_t)d.n * 10 + 512, (size_t)16 * d.n);
+            if (need > (size_t)max_lds)
+                return fail(nullptr, GA_ERR_INVALID, "n too large for this device's LDS (exact kernels)");
+        }
         if (d_workspace && ws_bytes < c.total)
             return fail(nullptr, GA_ERR_OOM,
                         "workspace too small: " + std::to_string(ws_bytes) + " < " + std::to_string(c.total));
@@ -483,6 +589,11 @@ ga_status ga_step(ga_ctx *ctx, int32_t generations)
 {
     CTXCHK(ctx);
     if (generations < 0) return fail(ctx, GA_ERR_INVALID, "generations must be >= 0");
+    if (generations == 0) return GA_OK;
+    if (!ctx->prof_on && (ctx->gexec || capture_generation(ctx))) {
+        for (int g = 0; g < generations; ++g) HIPCHK(hipGraphLaunch(ctx->gexec, ctx->st));
+        return GA_OK;
+    }
     for (int g = 0; g < generations; ++g) {
         ga_status s = run_generation(ctx);
         if (s != GA_OK) return s;
@@ -663,8 +774,198 @@ ga_status ga_set_tile_config(ga_ctx *ctx, int32_t cfg)
 {
     CTXCHK(ctx);
     if (cfg < 0 || cfg >= mfma_num_configs()) return fail(ctx, GA_ERR_INVALID, "no such tile configuration");
+    if (ctx->d.mfma_cfg != cfg) drop_graph(ctx);
     ctx->d.mfma_cfg = cfg;
     return GA_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------- batches --
+
+static void drop_halves(ga_ctx *ctx)
+{
+    if (ctx->pre_exec) (void)hipGraphExecDestroy(ctx->pre_exec);
+    if (ctx->post_exec) (void)hipGraphExecDestroy(ctx->post_exec);
+    ctx->pre_exec = ctx->post_exec = nullptr;
+    ctx->halves_cfg = -2;
+}
+
+// Capture one half of a generation of ctx on its stream as an executable graph.
+template <typename F>
+static hipError_t capture_half(ga_ctx *ctx, F &&body, hipGraphExec_t *out)
+{
+    hipError_t e = hipStreamBeginCapture(ctx->st, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) return e;
+    ga_status gs = body();
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(ctx->st, &g);
+    if (gs != GA_OK || e != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        ctx->poisoned = false;
+        return e != hipSuccess ? e : hipErrorUnknown;
+    }
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    return e;
+}
+
+static hipError_t ensure_halves(ga_ctx *ctx, int group_cfg)
+{
+    if (ctx->halves_cfg == group_cfg && ctx->pre_exec && ctx->post_exec) return hipSuccess;
+    drop_halves(ctx);
+    const bool grouped = group_cfg >= 0;
+    hipError_t e = capture_half(ctx, [&] { return gen_pre(ctx, ctx->st, grouped); }, &ctx->pre_exec);
+    if (e != hipSuccess) return e;
+    e = capture_half(ctx, [&] { return gen_post(ctx, ctx->st, grouped, group_cfg); }, &ctx->post_exec);
+    if (e != hipSuccess) return e;
+    ctx->halves_cfg = group_cfg;
+    return hipSuccess;
+}
+
+extern "C" {
+
+ga_status ga_batch_create(void *hip_stream, int32_t tile_config, ga_batch **out)
+{
+    if (!out) return fail(nullptr, GA_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!hip_stream) return fail(nullptr, GA_ERR_INVALID, "a batch needs a non-null stream");
+    if (tile_config < 0 || tile_config >= mfma_num_configs() || !mfma_pipelined(tile_config))
+        return fail(nullptr, GA_ERR_INVALID, "the batch tile configuration must be a pipelined one");
+    ga_batch *b = new (std::nothrow) ga_batch();
+    if (!b) return fail(nullptr, GA_ERR_OOM, "host allocation failed");
+    b->st = (hipStream_t)hip_stream;
+    b->cfg = tile_config;
+    if (hipEventCreateWithFlags(&b->jobs_copied, hipEventDisableTiming) != hipSuccess) {
+        delete b;
+        return fail(nullptr, GA_ERR_DEVICE, "event");
+    }
+    *out = b;
+    return GA_OK;
+}
+
+ga_status ga_batch_set(ga_batch *b, ga_ctx *const *ctxs, int32_t count)
+{
+    if (!b || (count > 0 && !ctxs) || count < 0) return GA_ERR_INVALID;
+    for (int i = 0; i < count; ++i) {
+        if (!ctxs[i]) return fail(nullptr, GA_ERR_INVALID, "NULL context in batch");
+        if (ctxs[i]->poisoned) return GA_ERR_STATE;
+        if (ctxs[i]->st != b->st) return fail(nullptr, GA_ERR_INVALID, "batch contexts must use the batch's stream");
+        for (int k = 0; k < i; ++k)
+            if (ctxs[k] == ctxs[i]) return fail(nullptr, GA_ERR_INVALID, "context listed twice");
+    }
+    hipError_t e;
+    // per-context halves (captured once per context and grouping)
+    std::vector<char> grouped(count, 0);
+    for (int i = 0; i < count; ++i) {
+        grouped[i] = ctxs[i]->d.prec == kSplitBF16 && mfma_groupable(ctxs[i]->d, b->cfg);
+        if ((e = ensure_halves(ctxs[i], grouped[i] ? b->cfg : -1)) != hipSuccess)
+            return fail(nullptr, GA_ERR_DEVICE, std::string("capture: ") + hipGetErrorString(e));
+    }
+    // grouped job table, copied in stream order after earlier generations
+    std::vector<const DevPtrs *> P;
+    std::vector<const Dims *> D;
+    int min_p = 1 << 30;
+    for (int i = 0; i < count; ++i)
+        if (grouped[i]) {
+            P.push_back(&ctxs[i]->P);
+            D.push_back(&ctxs[i]->d);
+            min_p = std::min(min_p, ctxs[i]->d.p);
+        }
+    const int njobs = (int)P.size();
+    const size_t bytes = mfma_job_bytes() * std::max(1, njobs);
+    if ((e = hipEventSynchronize(b->jobs_copied)) != hipSuccess)
+        return fail(nullptr, GA_ERR_DEVICE, hipGetErrorString(e));
+    if (bytes > b->jobs_cap) {
+        if ((e = hipStreamSynchronize(b->st)) != hipSuccess) return fail(nullptr, GA_ERR_DEVICE, hipGetErrorString(e));
+        if (b->d_jobs) (void)hipFree(b->d_jobs);
+        if (b->h_jobs) (void)hipHostFree(b->h_jobs);
+        b->d_jobs = b->h_jobs = nullptr;
+        const size_t cap = std::max(bytes * 2, mfma_job_bytes() * 64);
+        if (hipMalloc(&b->d_jobs, cap) != hipSuccess || hipHostMalloc(&b->h_jobs, cap, 0) != hipSuccess)
+            return fail(nullptr, GA_ERR_OOM, "job table");
+        b->jobs_cap = cap;
+    }
+    b->total_tiles = njobs ? mfma_fill_jobs(P.data(), D.data(), njobs, b->cfg, b->h_jobs) : 0;
+    if (njobs) {
+        if ((e = hipMemcpyAsync(b->d_jobs, b->h_jobs, bytes, hipMemcpyHostToDevice, b->st)) != hipSuccess)
+            return fail(nullptr, GA_ERR_DEVICE, hipGetErrorString(e));
+        if ((e = hipEventRecord(b->jobs_copied, b->st)) != hipSuccess)
+            return fail(nullptr, GA_ERR_DEVICE, hipGetErrorString(e));
+    }
+    b->njobs = njobs;
+    b->min_p = min_p;
+    // side streams (default priority) for the per-context branches
+    const int nside = std::min(std::max(count, 1), 16);
+    while ((int)b->side.size() < nside) {
+        hipStream_t s2;
+        if ((e = hipStreamCreateWithFlags(&s2, hipStreamNonBlocking)) != hipSuccess)
+            return fail(nullptr, GA_ERR_DEVICE, hipGetErrorString(e));
+        b->side.push_back(s2);
+    }
+    while ((int)b->ev.size() < 2 * 16 + 2) {
+        hipEvent_t ev;
+        if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess)
+            return fail(nullptr, GA_ERR_DEVICE, hipGetErrorString(e));
+        b->ev.push_back(ev);
+    }
+    b->ctxs.assign(ctxs, ctxs + count);
+    b->grouped = grouped;
+    return GA_OK;
+}
+
+ga_status ga_batch_step(ga_batch *b, int32_t generations)
+{
+    if (!b || generations < 0) return GA_ERR_INVALID;
+    const int count = (int)b->ctxs.size();
+    if (count == 0 || generations == 0) return GA_OK;
+    const int nside = std::min(count, (int)b->side.size());
+    auto dev_fail = [&](hipError_t e, const char *what) {
+        for (auto *c : b->ctxs) c->poisoned = true;
+        return fail(nullptr, GA_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    };
+    hipError_t e;
+    for (int g = 0; g < generations; ++g) {
+        // fork: every branch starts after the previous generation
+        if ((e = hipEventRecord(b->ev[0], b->st)) != hipSuccess) return dev_fail(e, "fork");
+        for (int k = 0; k < nside; ++k)
+            if ((e = hipStreamWaitEvent(b->side[k], b->ev[0], 0)) != hipSuccess) return dev_fail(e, "fork wait");
+        for (int i = 0; i < count; ++i)
+            if ((e = hipGraphLaunch(b->ctxs[i]->pre_exec, b->side[i % nside])) != hipSuccess)
+                return dev_fail(e, "pre");
+        for (int k = 0; k < nside; ++k) {
+            if ((e = hipEventRecord(b->ev[2 + k], b->side[k])) != hipSuccess) return dev_fail(e, "join");
+            if ((e = hipStreamWaitEvent(b->st, b->ev[2 + k], 0)) != hipSuccess) return dev_fail(e, "join wait");
+        }
+        if (b->njobs && (e = launch_mfma_group(b->d_jobs, b->njobs, b->total_tiles, b->cfg, b->min_p, b->st)) !=
+                            hipSuccess)
+            return dev_fail(e, "grouped launch");
+        if ((e = hipEventRecord(b->ev[1], b->st)) != hipSuccess) return dev_fail(e, "fork2");
+        for (int k = 0; k < nside; ++k)
+            if ((e = hipStreamWaitEvent(b->side[k], b->ev[1], 0)) != hipSuccess) return dev_fail(e, "fork2 wait");
+        for (int i = 0; i < count; ++i)
+            if ((e = hipGraphLaunch(b->ctxs[i]->post_exec, b->side[i % nside])) != hipSuccess)
+                return dev_fail(e, "post");
+        for (int k = 0; k < nside; ++k) {
+            if ((e = hipEventRecord(b->ev[2 + 16 + k], b->side[k])) != hipSuccess) return dev_fail(e, "join2");
+            if ((e = hipStreamWaitEvent(b->st, b->ev[2 + 16 + k], 0)) != hipSuccess) return dev_fail(e, "join2 wait");
+        }
+    }
+    return GA_OK;
+}
+
+void ga_batch_free(ga_batch *b)
+{
+    if (!b) return;
+    (void)hipStreamSynchronize(b->st);
+    for (auto s2 : b->side) (void)hipStreamSynchronize(s2);
+    for (auto s2 : b->side) (void)hipStreamDestroy(s2);
+    for (auto ev : b->ev) (void)hipEventDestroy(ev);
+    if (b->jobs_copied) (void)hipEventDestroy(b->jobs_copied);
+    if (b->d_jobs) (void)hipFree(b->d_jobs);
+    if (b->h_jobs) (void)hipHostFree(b->h_jobs);
+    delete b;
 }
 
 const char *ga_status_str(ga_status s)
@@ -685,6 +986,8 @@ void ga_free(ga_ctx *ctx)
 {
     if (!ctx) return;
     (void)hipStreamSynchronize(ctx->st);
+    drop_graph(ctx);
+    drop_halves(ctx);
     for (auto &e : ctx->ev) (void)hipEventDestroy(e);
     if (ctx->own_ws) (void)hipFree(ctx->ws);
     delete ctx;

@@ -20,10 +20,19 @@ hipError_t launch_eval_fp32(const DevPtrs &P, const Dims &d, const int32_t *hubs
                             hipStream_t st);
 hipError_t launch_recheck(const DevPtrs &P, const Dims &d, hipStream_t st);
 double fp32_eps_bound(int n);
+hipError_t prepare_plain_kernels(int max_lds);
 
 // batched matrix-core evaluation (eval_mfma.hip)
 hipError_t launch_eval_split(const DevPtrs &P, const Dims &d, const uint16_t *kidx, int count, hipStream_t st,
                              hipEvent_t ev0, hipEvent_t ev1);
+hipError_t launch_mfma(const DevPtrs &P, const Dims &d, const uint16_t *kidx, int count, hipStream_t st);
+hipError_t launch_finalize(const DevPtrs &P, const Dims &d, int count, int cfg, hipStream_t st);
+int mfma_partial_tiles(const Dims &d, int cfg);
+bool mfma_groupable(const Dims &d, int cfg);
+size_t mfma_job_bytes();
+int mfma_fill_jobs(const DevPtrs *const *P, const Dims *const *d, int njobs, int cfg, void *jobs_host);
+hipError_t launch_mfma_group(const void *d_jobs, int njobs, int total, int cfg, int min_p, hipStream_t st);
+int mfma_pipelined(int cfg);
 int mfma_num_configs();
 int mfma_rows_per_tile(int cfg);
 int mfma_cols_per_tile(int cfg);

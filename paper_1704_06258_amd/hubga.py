@@ -28,7 +28,8 @@ DEFAULT_KERNEL = {GA_PREC_FP64: GA_KERN_PLAIN, GA_PREC_FP32: GA_KERN_PLAIN, GA_P
 EXPORTS = ("ga_params_default", "ga_workspace_bytes", "ga_init", "ga_evaluate", "ga_evaluate_dev", "ga_step",
            "ga_best", "ga_solve", "ga_population", "ga_ancestors", "ga_get_state", "ga_set_state", "ga_stats",
            "ga_profile_enable", "ga_profile_read", "ga_tile_config_count", "ga_tile_config_info",
-           "ga_set_tile_config", "ga_status_str", "ga_last_error", "ga_free")
+           "ga_set_tile_config", "ga_batch_create", "ga_batch_set", "ga_batch_step", "ga_batch_free",
+           "ga_status_str", "ga_last_error", "ga_free")
 
 
 class ga_params(ct.Structure):
@@ -87,6 +88,14 @@ def lib():
         L.ga_tile_config_info.restype = ct.c_int
         L.ga_set_tile_config.argtypes = [vp, i32]
         L.ga_set_tile_config.restype = ct.c_int
+        L.ga_batch_create.argtypes = [vp, i32, ct.POINTER(vp)]
+        L.ga_batch_create.restype = ct.c_int
+        L.ga_batch_set.argtypes = [vp, ct.POINTER(vp), i32]
+        L.ga_batch_set.restype = ct.c_int
+        L.ga_batch_step.argtypes = [vp, i32]
+        L.ga_batch_step.restype = ct.c_int
+        L.ga_batch_free.argtypes = [vp]
+        L.ga_batch_free.restype = None
         L.ga_status_str.argtypes = [ct.c_int]
         L.ga_status_str.restype = ct.c_char_p
         L.ga_last_error.argtypes = [vp]
@@ -178,7 +187,9 @@ class Solver:
             raise HubGAError(GA_ERR_INVALID, "invalid parameters")
         self.device = torch.device("cuda", device)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        # a stream of its own (non-null, so generations can be replayed as a graph)
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
         self.workspace_bytes = nbytes
         h = ct.c_void_p()
         _check(lib().ga_init(ct.byref(self.params), C.ctypes.data, cdt, W.ctypes.data, wdt,
@@ -209,9 +220,15 @@ class Solver:
         k = d_hubs.shape[0]
         if d_cost is None:
             d_cost = torch.empty(k, dtype=torch.float64, device=self.device)
+        cur = torch.cuda.current_stream(self.device)
+        self.stream.wait_stream(cur)          # inputs produced on the caller's stream
         _check(lib().ga_evaluate_dev(self.ctx, d_hubs.data_ptr(), k,
                                      d_kidx.data_ptr() if d_kidx is not None else None, d_cost.data_ptr()),
                self.ctx)
+        cur.wait_stream(self.stream)          # outputs consumed on the caller's stream
+        for t in (d_hubs, d_cost, d_kidx):
+            if t is not None:
+                t.record_stream(self.stream)
         return d_cost
 
     # -- GA ---------------------------------------------------------------
@@ -291,3 +308,40 @@ class Solver:
 
     def __exit__(self, *a):
         self.close()
+
+
+class Batch:
+    """Several Solvers advanced together (ga_batch_*): one captured graph per
+    composition, with one grouped matrix-core launch for their populations.
+    Every member must have been created with ``stream=batch.stream``."""
+
+    def __init__(self, device=0, tile_config=7, stream=None):
+        import torch
+        self.device = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        h = ct.c_void_p()
+        _check(lib().ga_batch_create(ct.c_void_p(self.stream.cuda_stream), int(tile_config), ct.byref(h)))
+        self.handle = h
+        self.members = []
+
+    def set(self, solvers):
+        arr = (ct.c_void_p * max(1, len(solvers)))(*[s.ctx for s in solvers])
+        _check(lib().ga_batch_set(self.handle, arr, len(solvers)))
+        self.members = list(solvers)
+
+    def step(self, generations=1):
+        _check(lib().ga_batch_step(self.handle, int(generations)))
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().ga_batch_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

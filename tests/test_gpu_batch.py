@@ -1,0 +1,124 @@
+"""GPU: graph-replayed generations and multi-context batches.
+
+Bar: every context's GA state (ancestors, exact costs, best so far,
+generation) after batched generations is bit-identical to stepping it alone and
+to the oracle's trajectory, whatever else shares the batch.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1704_06258_amd import hubga
+from paper_1704_06258_amd import instances as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    hubga.lib()
+    yield
+
+
+def make(inst, **kw):
+    return hubga.Solver(inst.C, inst.W, inst.p, chi=inst.chi, alpha=inst.alpha, delta=inst.delta,
+                        scale=inst.scale, **kw)
+
+
+def state_of(s):
+    anc, cost = s.ancestors()
+    b = s.best()
+    return anc, cost, b["hubs"], b["cost"], b["generation"], s.get_state()
+
+
+def same(a, b):
+    return all(np.array_equal(x, y) if isinstance(x, np.ndarray) else x == y for x, y in zip(a, b))
+
+
+def test_graph_replay_equals_direct_launches():
+    inst = I.medium()
+    kw = dict(population=512, island_size=64, n1=4, seed=3, precision="split_bf16")
+    with make(inst, **kw) as a, make(inst, **kw) as b:
+        a.step(9)                      # graph replay
+        b.profile_enable(True)         # profiling launches kernels directly
+        b.step(9)
+        b.profile_enable(False)
+        assert same(state_of(a), state_of(b))
+    st = oracle.ga_init(inst.C64(), inst.W64(), inst.p, 512, 64, inst.chi, inst.alpha, inst.delta)
+    oracle.ga_run(inst.C64(), inst.W64(), st, 9, S=512, m=64, n1=4, seed=3, chi=inst.chi, alpha=inst.alpha,
+                  delta=inst.delta)
+    assert np.array_equal(state_of(a)[0], st.anc) and state_of(a)[3] == st.best_cost[0]
+
+
+MIX = [  # (instance, population, island, precision)
+    (lambda: I.uniform(seed=1, n=200, p=10), 512, 64, "split_bf16"),
+    (lambda: I.uniform(seed=2, n=500, p=5), 256, 64, "split_bf16"),
+    (lambda: I.uniform(seed=3, n=100, p=3), 1024, 64, "split_bf16"),
+    (lambda: I.uniform(seed=4, n=150, p=2), 256, 32, "split_bf16"),   # p < 3: own matrix-core launch
+    (lambda: I.small(seed=5), 64, 16, "fp64"),
+    (lambda: I.uniform(seed=6, n=120, p=7), 256, 64, "fp32"),
+]
+
+
+@pytest.mark.parametrize("cfg", [7, 6, 10])
+def test_batch_equals_alone(cfg):
+    import torch
+    insts = [(mk(), S, m, prec) for mk, S, m, prec in MIX]
+    alone = []
+    for k, (inst, S, m, prec) in enumerate(insts):
+        with make(inst, population=S, island_size=m, n1=3, seed=10 + k, precision=prec) as s:
+            s.step(7)
+            alone.append(state_of(s))
+    batch = hubga.Batch(tile_config=cfg)
+    members = [make(inst, population=S, island_size=m, n1=3, seed=10 + k, precision=prec, stream=batch.stream)
+               for k, (inst, S, m, prec) in enumerate(insts)]
+    batch.set(members)
+    batch.step(7)
+    batch.synchronize()
+    for k, s in enumerate(members):
+        assert same(state_of(s), alone[k]), k
+    for s in members:
+        s.close()
+    batch.close()
+    torch.cuda.synchronize()
+
+
+def test_batch_recomposition_and_oracle():
+    insts = [I.uniform(seed=20 + k, n=150 + 50 * k, p=4 + k) for k in range(3)]
+    batch = hubga.Batch(tile_config=7)
+    sol = [make(inst, population=256, island_size=32, n1=2, seed=k, precision="split_bf16", stream=batch.stream)
+           for k, inst in enumerate(insts)]
+    batch.set(sol[:2])
+    batch.step(3)
+    batch.set(sol[1:])
+    batch.step(2)
+    batch.set([sol[0]])
+    batch.step(4)
+    batch.synchronize()
+    gens = {0: 7, 1: 5, 2: 2}
+    for k, inst in enumerate(insts):
+        st = oracle.ga_init(inst.C64(), inst.W64(), inst.p, 256, 32, inst.chi, inst.alpha, inst.delta)
+        oracle.ga_run(inst.C64(), inst.W64(), st, gens[k], S=256, m=32, n1=2, seed=k, chi=inst.chi,
+                      alpha=inst.alpha, delta=inst.delta)
+        anc, cost, hubs, bc, g, _ = state_of(sol[k])
+        assert g == gens[k]
+        assert np.array_equal(anc, st.anc) and np.array_equal(cost, st.anc_cost)
+        assert np.array_equal(hubs, st.best) and bc == st.best_cost[0]
+    for s in sol:
+        s.close()
+    batch.close()
+
+
+def test_batch_rejects_foreign_stream_and_empty_is_noop():
+    inst = I.small()
+    batch = hubga.Batch(tile_config=7)
+    with make(inst, population=64, island_size=32, precision="split_bf16") as s:
+        with pytest.raises(hubga.HubGAError):
+            batch.set([s])
+    batch.set([])
+    batch.step(3)
+    with pytest.raises(hubga.HubGAError):
+        hubga.Batch(tile_config=0)    # not a pipelined configuration
+    batch.close()

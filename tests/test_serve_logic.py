@@ -1,0 +1,109 @@
+"""Admission and scheduling of the solve server against a fake device backend
+(CPU only): FIFO admission under an HBM budget and a slot cap, requests join
+and leave at generation boundaries, every request runs exactly its
+generations, and a request larger than the budget is refused."""
+import numpy as np
+import pytest
+
+from paper_1704_06258_amd import hubga, serve
+from paper_1704_06258_amd import instances as I
+
+
+class FakeSolver:
+    live = []
+
+    def __init__(self, C, W, p, *, population, generations_cb=None, **kw):
+        self.n, self.p, self.S = C.shape[0], p, population
+        q = hubga.make_params(self.n, p, chi=kw["chi"], alpha=kw["alpha"], delta=kw["delta"], population=population,
+                              island_size=kw["island_size"], n1=kw["n1"], precision=kw["precision"],
+                              c_symmetric=True)
+        self.workspace_bytes = hubga.ga_workspace_bytes(q)
+        self.gen = 0
+        self.closed = False
+        FakeSolver.live.append(self)
+
+    def best(self):
+        return {"hubs": np.arange(self.p), "cost": float(self.gen), "generation": self.gen}
+
+    def close(self):
+        self.closed = True
+
+
+class FakeBatch:
+    def __init__(self, device=0, tile_config=7):
+        self.members = []
+        self.history = []
+
+    def set(self, solvers):
+        assert all(not s.closed for s in solvers)
+        self.members = list(solvers)
+        self.history.append(len(solvers))
+
+    def step(self, g=1):
+        for s in self.members:
+            s.gen += g
+
+    def synchronize(self):
+        pass
+
+    def close(self):
+        pass
+
+    stream = None
+
+
+@pytest.fixture
+def fake(monkeypatch):
+    FakeSolver.live = []
+    monkeypatch.setattr(serve.hubga, "Solver", FakeSolver)
+    monkeypatch.setattr(serve.hubga, "Batch", FakeBatch)
+    yield
+
+
+def make_requests(k, sizes, gens):
+    reqs = []
+    for r in range(k):
+        n = sizes[r % len(sizes)]
+        inst = I.uniform(seed=r, n=n, p=3)
+        reqs.append(serve.SolveRequest(r, 0.0, inst.C, inst.W, 3, 3.0, 0.75, 2.0, 256, gens[r % len(gens)], r))
+    return reqs
+
+
+def test_admission_respects_budget_and_slots(fake):
+    reqs = make_requests(12, [50, 100, 200], [3, 5, 8])
+    one = serve.workspace_bytes(reqs[2])
+    srv = serve.Server(hbm_budget=int(2.5 * one), max_slots=3)
+    peak = {"bytes": 0, "slots": 0}
+    orig = srv._admit
+
+    def admit(req, now):
+        job = orig(req, now)
+        peak["bytes"] = max(peak["bytes"], srv.used + job.nbytes)
+        peak["slots"] = max(peak["slots"], len(srv.resident) + 1)
+        return job
+
+    srv._admit = admit
+    res = srv.run(reqs, realtime=False)
+    assert sorted(r.rid for r in res) == list(range(12))
+    for r in res:
+        assert r.generations == reqs[r.rid].generations
+    assert peak["bytes"] <= srv.budget and peak["slots"] <= 3
+    assert srv.used == 0 and all(s.closed for s in FakeSolver.live)
+    # FIFO: admission order is arrival order
+    admitted = sorted(res, key=lambda r: r.admitted)
+    assert [r.rid for r in admitted] == sorted(r.rid for r in admitted)
+
+
+def test_request_larger_than_budget_is_refused(fake):
+    reqs = make_requests(1, [200], [2])
+    srv = serve.Server(hbm_budget=1000, max_slots=4)
+    with pytest.raises(MemoryError):
+        srv.run(reqs, realtime=False)
+
+
+def test_poisson_stream_generator():
+    reqs = I.serving_requests(500, rate=200.0, seed=5)
+    gaps = np.diff([r.arrival for r in reqs])
+    assert abs(gaps.mean() - 1 / 200.0) < 0.1 / 200.0
+    assert {r.n for r in reqs} <= set(I.SERVING_N) and {r.p for r in reqs} <= set(I.SERVING_P)
+    assert {r.S for r in reqs} <= set(I.SERVING_S)
