@@ -29,7 +29,15 @@ sys.path.insert(0, ROOT)
 
 PEAK_BF16_TFLOPS = 2500.0        # MI355X dense bf16 matrix peak
 PEAK_HBM_GBS = 8000.0
-N, P, S, M, N1 = 1000, 20, 4096, 64, 10
+WORKLOADS = {
+    # name: (instance factory, n, p, population, island size, n1, description)
+    "clustered": ("clustered", 1000, 20, 4096, 64, 10,
+                  "clustered n=1000 p=20 population=4096 (64 islands x 64), one GA generation per step, split-bf16 "
+                  "batched matrix-core evaluation"),
+    "large": ("large", 6000, 50, 2048, 64, 10,
+              "large n=6000 p=50 population=2048 (32 islands x 64), FP32 instance, one GA generation per step, "
+              "split-bf16 batched matrix-core evaluation"),
+}
 MFMA_SRC = os.path.join(ROOT, "paper_1704_06258_amd", "csrc", "eval_mfma.hip")
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "eval_mfma_clustered_n1000_p20_traffic.md")
 
@@ -71,14 +79,14 @@ def time_steps(solver, steps, warmup, kernel_steps=20):
     return dt, kms, launches
 
 
-def cpu_baseline(inst, gpu_hubs, gpu_cost, budget_s=12.0):
+def cpu_baseline(inst, gpu_hubs, gpu_cost, budget_s=12.0, label="n=1000, p=20"):
     """The FP64 oracle (OpenMP over individuals) on the GPU's last population:
     evaluations per second over a bounded sample, plus the measured error of
     the GPU's split-bf16 costs on that sample."""
     import oracle
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     C, W = inst.C64(), inst.W64()
-    done, t_used, k = 0, 0.0, 64
+    done, t_used, k = 0, 0.0, 16
     errs = []
     pos = 0
     while t_used < budget_s:
@@ -92,7 +100,7 @@ def cpu_baseline(inst, gpu_hubs, gpu_cost, budget_s=12.0):
         k = min(k * 2, 1024)
     err = np.concatenate(errs)
     return dict(value=done / t_used, unit="evals/s", cores=cores, kind="oracle",
-                sample=f"{done} children of the last GPU generation (n=1000, p=20), FP64 oracle, "
+                sample=f"{done} children of the last GPU generation ({label}), FP64 oracle, "
                        f"{t_used:.1f} s of CPU work"), float(err.max())
 
 
@@ -134,6 +142,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-kernel comparison")
+    ap.add_argument("--workload", default="clustered", choices=sorted(WORKLOADS))
     ap.add_argument("--tile-config", default="auto",
                     help="tile configuration of the batched kernel: an index, or 'auto' to run the autotuner "
                          "(outside the timed region)")
@@ -170,7 +179,8 @@ def main():
     from paper_1704_06258_amd import instances as I
 
     hubga.lib()
-    inst = I.clustered()
+    factory, N, P, S, M, N1, wdesc = WORKLOADS[args.workload]
+    inst = getattr(I, factory)()
     kw = dict(chi=inst.chi, alpha=inst.alpha, delta=inst.delta, scale=inst.scale, seed=1, population=S,
               island_size=M, n1=N1)
     solver = hubga.Solver(inst.C, inst.W, inst.p, precision="split_bf16", **kw)
@@ -204,8 +214,7 @@ def main():
         "vs_baseline": None,
         "dtype": "bf16",
         "data": "synthetic",
-        "config": {"workload": "clustered n=1000 p=20 population=4096 (64 islands x 64), one GA generation per "
-                               "step, split-bf16 batched matrix-core evaluation",
+        "config": {"workload": wdesc,
                    "n": N, "p": P, "population": S, "islands": S // M, "n1": N1,
                    "precision": "W = bf16 hi + lo, FP32 accumulate, FP64 epilogue and selection",
                    "instance_sha256": inst.sha256()},
@@ -224,7 +233,7 @@ def main():
         plain = {}
         for prec in ("fp64", "fp32"):
             s2 = hubga.Solver(inst.C, inst.W, inst.p, precision=prec, **kw)
-            steps = 10
+            steps = 10 if N <= 2000 else 2
             dt2, kms2, l2 = time_steps(s2, steps, 2, kernel_steps=3)
             s2.close()
             plain[prec] = {"evals_per_s": S * steps / dt2, "ms_per_step": 1e3 * dt2 / steps,
@@ -233,11 +242,11 @@ def main():
         out["speedup_vs_plain_fp64"] = value / plain["fp64"]["evals_per_s"]
         out["speedup_vs_plain_fp32"] = value / plain["fp32"]["evals_per_s"]
 
-    if args.serve_requests > 0:
+    if args.serve_requests > 0 and args.workload == "clustered":
         out["serving"] = serving_leg(args.serve_requests, args.serve_warmup)
 
     if not args.no_cpu:
-        cb, err = cpu_baseline(inst, gpu_hubs, gpu_cost)
+        cb, err = cpu_baseline(inst, gpu_hubs, gpu_cost, label=f"n={N}, p={P}")
         out["cpu_baseline"] = cb
         out["max_rel_err_vs_oracle"] = err
     print(json.dumps(out), flush=True)

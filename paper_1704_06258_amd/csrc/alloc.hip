@@ -13,112 +13,133 @@
 
 namespace hubga {
 
+constexpr int kAllocPer = 4;   // individuals per workgroup
+
 template <typename CT>
 __global__ __launch_bounds__(256) void k_alloc(const int32_t *__restrict__ hubs, int count, int n, int n_pad, int p,
                                                const CT *__restrict__ Ct, const float *__restrict__ Ct32,
-                                               const double *__restrict__ O,
-                                               const double *__restrict__ D, uint16_t *__restrict__ kidx,
-                                               double *__restrict__ parts, int32_t *__restrict__ cmax,
-                                               float *__restrict__ Ch32, int want_sums)
+                                               const double *__restrict__ O, const double *__restrict__ D,
+                                               uint16_t *__restrict__ kidx, double *__restrict__ parts,
+                                               int32_t *__restrict__ cmax, float *__restrict__ Ch32, int want_sums)
 {
 #pragma clang fp contract(off)
-    __shared__ int sh_h[kMaxP];
-    __shared__ int sh_cnt[kMaxP];
-    __shared__ double red_c[256], red_d[256];
-    const int s = blockIdx.x;
-    if (s >= count) return;
+    __shared__ int sh_h[kAllocPer][kMaxP];
+    __shared__ int sh_cnt[kAllocPer][kMaxP];
+    __shared__ double red_c[kAllocPer][256], red_d[kAllocPer][256];
+    // XCD-major group order: consecutive groups (children of one island) run
+    // on the same XCD (blockIdx % 8) and share its L2.
+    const int groups = (count + kAllocPer - 1) / kAllocPer;
+    const int per = (groups + 7) / 8;
+    const int grp = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (grp >= groups) return;
+    const int s0 = grp * kAllocPer;
+    const int nind = min(kAllocPer, count - s0);
     const int tid = threadIdx.x;
-    const int32_t *h = hubs + (size_t)s * p;
-    if (tid < p) {
-        sh_h[tid] = h[tid];
-        sh_cnt[tid] = 0;
+    for (int e = tid; e < kAllocPer * kMaxP; e += 256) {
+        const int c = e / kMaxP, k = e % kMaxP;
+        sh_cnt[c][k] = 0;
+        if (c < nind && k < p) sh_h[c][k] = hubs[(size_t)(s0 + c) * p + k];
     }
     __syncthreads();
-    double pc = 0.0, pd = 0.0;
-    uint16_t *krow = kidx + (size_t)s * n_pad;
-    for (int i = tid; i < n_pad; i += blockDim.x) {
-        if (i >= n) {
-            krow[i] = kNoHub;
-            continue;
-        }
-        // Scan in FP32: rounding to FP32 is monotone, so a unique FP32
-        // minimum is also the unique minimum of the instance values.  When
-        // several hubs share the FP32 minimum, rescan in the instance dtype
-        // (strict <, ties to the smaller hub id).
-        int best = 0;
-        float bd = Ct32[(size_t)sh_h[0] * n + i];
-        bool tie = false;
-        for (int k = 1; k < p; ++k) {
-            float v = Ct32[(size_t)sh_h[k] * n + i];
-            if (v < bd) {
-                bd = v;
-                best = k;
-                tie = false;
-            } else if (v == bd) {
-                tie = true;
+    double pc[kAllocPer], pd[kAllocPer];
+#pragma unroll
+    for (int c = 0; c < kAllocPer; ++c) pc[c] = pd[c] = 0.0;
+    for (int i = tid; i < n_pad; i += 256) {
+#pragma unroll
+        for (int c = 0; c < kAllocPer; ++c) {
+            if (c >= nind) break;
+            uint16_t *krow = kidx + (size_t)(s0 + c) * n_pad;
+            if (i >= n) {
+                krow[i] = kNoHub;
+                continue;
             }
-        }
-        if (tie) {
-            best = 0;
-            CT be = Ct[(size_t)sh_h[0] * n + i];
+            const int *h = sh_h[c];
+            // Scan in FP32: rounding to FP32 is monotone, so a unique FP32
+            // minimum is also the unique minimum of the instance values.  When
+            // several hubs share the FP32 minimum, rescan in the instance
+            // dtype (strict <, ties to the smaller hub id).
+            int best = 0;
+            float bd = Ct32[(size_t)h[0] * n + i];
+            bool tie = false;
             for (int k = 1; k < p; ++k) {
-                CT v = Ct[(size_t)sh_h[k] * n + i];
-                if (v < be) {
-                    be = v;
+                const float v = Ct32[(size_t)h[k] * n + i];
+                if (v < bd) {
+                    bd = v;
                     best = k;
+                    tie = false;
+                } else if (v == bd) {
+                    tie = true;
                 }
             }
-        }
-        // a hub keeps itself: binary search of i in the sorted list
-        int lo = 0, hi = p - 1;
-        while (lo <= hi) {
-            int mid = (lo + hi) >> 1;
-            int hv = sh_h[mid];
-            if (hv == i) {
-                best = mid;
-                break;
+            if (tie) {
+                best = 0;
+                CT be = Ct[(size_t)h[0] * n + i];
+                for (int k = 1; k < p; ++k) {
+                    const CT v = Ct[(size_t)h[k] * n + i];
+                    if (v < be) {
+                        be = v;
+                        best = k;
+                    }
+                }
             }
-            if (hv < i)
-                lo = mid + 1;
-            else
-                hi = mid - 1;
-        }
-        krow[i] = (uint16_t)best;
-        atomicAdd(&sh_cnt[best], 1);
-        if (want_sums) {
-            double ci = (double)Ct[(size_t)sh_h[best] * n + i];
-            pc = pc + O[i] * ci;
-            pd = pd + D[i] * ci;
+            // a hub keeps itself: binary search of i in the sorted list
+            int lo = 0, hi = p - 1;
+            while (lo <= hi) {
+                const int mid = (lo + hi) >> 1;
+                const int hv = h[mid];
+                if (hv == i) {
+                    best = mid;
+                    break;
+                }
+                if (hv < i)
+                    lo = mid + 1;
+                else
+                    hi = mid - 1;
+            }
+            krow[i] = (uint16_t)best;
+            atomicAdd(&sh_cnt[c][best], 1);
+            if (want_sums) {
+                const double ci = (double)Ct[(size_t)h[best] * n + i];
+                pc[c] = pc[c] + O[i] * ci;
+                pd[c] = pd[c] + D[i] * ci;
+            }
         }
     }
     if (Ch32) {
-        float *ch = Ch32 + (size_t)s * p * p;
-        for (int e = tid; e < p * p; e += blockDim.x) {
-            int k = e / p, l = e % p;
-            ch[e] = (float)Ct[(size_t)sh_h[l] * n + sh_h[k]];   // C[h_k][h_l]
+        for (int e = tid; e < nind * p * p; e += 256) {
+            const int c = e / (p * p), kl = e % (p * p);
+            const int k = kl / p, l = kl % p;
+            Ch32[(size_t)(s0 + c) * p * p + kl] = (float)Ct[(size_t)sh_h[c][l] * n + sh_h[c][k]];   // C[h_k][h_l]
         }
     }
     if (want_sums) {
-        red_c[tid] = pc;
-        red_d[tid] = pd;
+#pragma unroll
+        for (int c = 0; c < kAllocPer; ++c) {
+            red_c[c][tid] = pc[c];
+            red_d[c][tid] = pd[c];
+        }
     }
     __syncthreads();
     if (want_sums) {
-        for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        for (int w = 128; w > 0; w >>= 1) {
             if (tid < w) {
-                red_c[tid] = red_c[tid] + red_c[tid + w];
-                red_d[tid] = red_d[tid] + red_d[tid + w];
+#pragma unroll
+                for (int c = 0; c < kAllocPer; ++c) {
+                    red_c[c][tid] = red_c[c][tid] + red_c[c][tid + w];
+                    red_d[c][tid] = red_d[c][tid] + red_d[c][tid + w];
+                }
             }
             __syncthreads();
         }
     }
-    if (tid == 0) {
-        int m = 0;
-        for (int k = 0; k < p; ++k) m = sh_cnt[k] > m ? sh_cnt[k] : m;
-        cmax[s] = m;
+    if (tid < nind) {
+        const int c = tid;
+        int mx = 0;
+        for (int k = 0; k < p; ++k) mx = sh_cnt[c][k] > mx ? sh_cnt[c][k] : mx;
+        cmax[s0 + c] = mx;
         if (want_sums) {
-            parts[3 * (size_t)s + 0] = red_c[0];
-            parts[3 * (size_t)s + 2] = red_d[0];
+            parts[3 * (size_t)(s0 + c) + 0] = red_c[c][0];
+            parts[3 * (size_t)(s0 + c) + 2] = red_d[c][0];
         }
     }
 }
@@ -146,11 +167,13 @@ hipError_t launch_alloc(const DevPtrs &P, const Dims &d, const int32_t *hubs, in
 {
     if (count <= 0) return hipSuccess;
     float *ch = want_ch ? P.Ch32 : nullptr;
+    const int groups = (count + kAllocPer - 1) / kAllocPer;
+    const unsigned grid = (unsigned)(((groups + 7) / 8) * 8);
     if (d.c_f32)
-        k_alloc<float><<<count, 256, 0, st>>>(hubs, count, d.n, d.n_pad, d.p, (const float *)P.Ct, P.Ct32, P.O, P.D,
+        k_alloc<float><<<grid, 256, 0, st>>>(hubs, count, d.n, d.n_pad, d.p, (const float *)P.Ct, P.Ct32, P.O, P.D,
                                              kidx, P.parts, P.cmax, ch, want_sums);
     else
-        k_alloc<double><<<count, 256, 0, st>>>(hubs, count, d.n, d.n_pad, d.p, (const double *)P.Ct, P.Ct32, P.O,
+        k_alloc<double><<<grid, 256, 0, st>>>(hubs, count, d.n, d.n_pad, d.p, (const double *)P.Ct, P.Ct32, P.O,
                                               P.D, kidx, P.parts, P.cmax, ch, want_sums);
     return hipGetLastError();
 }

@@ -52,6 +52,9 @@ struct DevPtrs {
     int32_t *slot_r, *slot_c;   // tot candidate slots (island, candidate)
     int32_t *handled;   // R: candidates of each island that got a slot
     int32_t *total;     // 1: slots in use
+    int32_t *extra_r, *extra_c;   // S: candidates beyond the slots
+    int32_t *nextra;    // 1
+    int *sync;          // 2 grid counters (last-workgroup detection), zero between launches
 };
 
 struct Dims {

@@ -10,6 +10,9 @@
 //   columns; Cc and Dd come from the allocation kernel.  Returns a rigorous
 //   relative error bound with every cost.
 #include "kernels.hpp"
+#include "select_dev.hpp"
+
+#include <algorithm>
 
 namespace hubga {
 
@@ -120,81 +123,20 @@ __global__ __launch_bounds__(256) void k_eval_exact(const int32_t *__restrict__ 
     if (threadIdx.x == 0 && eps) eps[s] = 0.0;
 }
 
-// Exact re-evaluation of the selection candidates that got no slot in the
-// column-parallel kernels (all but the first handled[r] of island r): block
-// (r, y) evaluates candidates handled[r] + y, handled[r] + y + gridDim.y, ...
-template <typename CT, typename WT>
-__global__ __launch_bounds__(256) void k_recheck(const int32_t *__restrict__ hubs, const uint16_t *__restrict__ kidx,
-                                                 const int32_t *__restrict__ cand, const int32_t *__restrict__ cand_cnt,
-                                                 const int32_t *__restrict__ handled, int m, int n, int n_pad, int p,
-                                                 const CT *__restrict__ C,
-                                                 const WT *__restrict__ W, const double *__restrict__ O,
-                                                 const double *__restrict__ D, double chi, double alpha, double delta,
-                                                 double scale, double *__restrict__ cand_cost,
-                                                 double *__restrict__ cand_parts)
-{
-    extern __shared__ __align__(16) char smem[];
-    const int r = blockIdx.x;
-    const int cnt = cand_cnt[r];
-    for (int c = handled[r] + blockIdx.y; c < cnt; c += gridDim.y) {
-        const int s = cand[(size_t)r * m + c];
-        eval_exact_body<CT, WT>(hubs + (size_t)s * p, kidx + (size_t)s * n_pad, n, p, C, W, O, D, chi, alpha,
-                                delta, scale, cand_cost + (size_t)r * m + c, cand_parts + 3 * ((size_t)r * m + c),
-                                smem);
-        __syncthreads();
-    }
-}
-
-
 // Column-parallel exact evaluation of selection candidates.
 //
-// k_compact (one workgroup) lists candidate slots in island order, up to
-// `tot` in all; handled[r] is how many of island r's candidates got a slot
-// (the rest go to k_recheck).
+// The last workgroup of the selection kernel lists candidate slots in island
+// order, up to `tot` in all; the rest form an extra list.
 //
 // k_canon_cols loops over (slot, 32-column chunk) items: 128-row tiles of W
 // are staged through LDS (loads issued two tiles ahead), every lane of the
 // workgroup forms products W_ij * C[a_i][a_j] for the tile -- the same binary64
 // products as the sequential definition -- and one lane per column adds them
 // in ascending row order into t_j.  k_canon_sums then sums T, Cc and Dd in
-// ascending order.
+// ascending order, evaluates the extra candidates whole (one workgroup each),
+// and its last workgroup decides every island and ends the generation.
 constexpr int kCanonCols = 32;
 constexpr int kCanonRows = 128;
-
-__global__ __launch_bounds__(256) void k_compact(const int32_t *__restrict__ cand_cnt, int R, int tot,
-                                                 int32_t *__restrict__ slot_r, int32_t *__restrict__ slot_c,
-                                                 int32_t *__restrict__ handled, int32_t *__restrict__ total)
-{
-    __shared__ int part[256];
-    const int tid = threadIdx.x;
-    const int chunk = (R + 255) / 256;
-    const int r0 = tid * chunk, r1 = min(R, r0 + chunk);
-    int sum = 0;
-    for (int r = r0; r < r1; ++r) sum += cand_cnt[r];
-    part[tid] = sum;
-    __syncthreads();
-    if (tid == 0) {
-        int acc = 0;
-        for (int t = 0; t < 256; ++t) {
-            int v = part[t];
-            part[t] = acc;
-            acc += v;
-        }
-        *total = min(acc, tot);
-    }
-    __syncthreads();
-    int off = part[tid];
-    for (int r = r0; r < r1; ++r) {
-        const int cnt = cand_cnt[r];
-        const int h = max(0, min(cnt, tot - off));
-        for (int c = 0; c < h; ++c) {
-            slot_r[off + c] = r;
-            slot_c[off + c] = c;
-        }
-        handled[r] = h;
-        off += cnt;
-    }
-}
 
 __host__ __device__ inline size_t canon_cols_smem(int n, int p)
 {
@@ -288,16 +230,19 @@ __global__ __launch_bounds__(256) void k_canon_cols(const int32_t *__restrict__ 
     }
 }
 
-template <typename CT>
-__global__ __launch_bounds__(256) void k_canon_sums(const int32_t *__restrict__ hubs,
-                                                    const uint16_t *__restrict__ kidx,
-                                                    const int32_t *__restrict__ cand, const int32_t *__restrict__ slot_r,
+template <typename CT, typename WT>
+__global__ __launch_bounds__(256) void k_canon_sums(SelState S, const int32_t *__restrict__ kidx,
+                                                    const int32_t *__restrict__ slot_r,
                                                     const int32_t *__restrict__ slot_c,
-                                                    const int32_t *__restrict__ total, int m, int n, int n_pad, int p,
-                                                    const CT *__restrict__ C, const double *__restrict__ O,
-                                                    const double *__restrict__ D, const double *__restrict__ tbuf,
-                                                    double chi, double alpha, double delta, double scale,
-                                                    double *__restrict__ cand_cost, double *__restrict__ cand_parts)
+                                                    const int32_t *__restrict__ total,
+                                                    const int32_t *__restrict__ extra_r,
+                                                    const int32_t *__restrict__ extra_c,
+                                                    const int32_t *__restrict__ nextra, int n, int n_pad,
+                                                    const CT *__restrict__ C, const WT *__restrict__ W,
+                                                    const double *__restrict__ O, const double *__restrict__ D,
+                                                    const double *__restrict__ tbuf, double chi, double alpha,
+                                                    double delta, double scale, double *__restrict__ cand_cost,
+                                                    double *__restrict__ cand_parts, int *__restrict__ sync)
 {
 #pragma clang fp contract(off)
     extern __shared__ __align__(16) char smem[];
@@ -305,13 +250,15 @@ __global__ __launch_bounds__(256) void k_canon_sums(const int32_t *__restrict__ 
     __shared__ int h[kMaxP];
     __shared__ double sh_cc;
     const int tid = threadIdx.x;
+    const int p = S.p, m = S.m;
+    const uint16_t *kid16 = (const uint16_t *)kidx;
     const int tot = *total;
     for (int slot = blockIdx.x; slot < tot; slot += gridDim.x) {
         const int r = slot_r[slot], c = slot_c[slot];
-        const int s = cand[(size_t)r * m + c];
+        const int s = S.cand[(size_t)r * m + c];
         __syncthreads();
-        if (tid < p) h[tid] = hubs[(size_t)s * p + tid];
-        const uint16_t *krow = kidx + (size_t)s * n_pad;
+        if (tid < p) h[tid] = S.children[(size_t)s * p + tid];
+        const uint16_t *krow = kid16 + (size_t)s * n_pad;
         const double *t = tbuf + (size_t)slot * n;
         __syncthreads();
         for (int i = tid; i < n; i += 256) {
@@ -334,6 +281,19 @@ __global__ __launch_bounds__(256) void k_canon_sums(const int32_t *__restrict__ 
             cand_parts[3 * o + 2] = Dd;
         }
     }
+    // candidates beyond the slots: evaluated whole, one workgroup each
+    const int ne = *nextra;
+    for (int e = blockIdx.x; e < ne; e += gridDim.x) {
+        const int r = extra_r[e], c = extra_c[e];
+        const int s = S.cand[(size_t)r * m + c];
+        __syncthreads();
+        const size_t o = (size_t)r * m + c;
+        eval_exact_body<CT, WT>(S.children + (size_t)s * p, kid16 + (size_t)s * n_pad, n, p, C, W, O, D, chi,
+                                alpha, delta, scale, cand_cost + o, cand_parts + 3 * o, smem);
+    }
+    if (!last_block(sync, gridDim.x)) return;
+    for (int r = 0; r < S.R; ++r) select_island_exact(S, r);
+    global_step(S);
 }
 
 // ------------------------------------------------------------- FP32 --
@@ -429,36 +389,27 @@ hipError_t launch_eval_exact(const DevPtrs &P, const Dims &d, const int32_t *hub
 }
 
 template <typename CT, typename WT>
-static hipError_t recheck_launch(const DevPtrs &P, const Dims &d, int ychunks, hipStream_t st)
+static hipError_t recheck_launch(const DevPtrs &P, const Dims &d, const SelState &S, hipStream_t st)
 {
     hipError_t e;
-    k_compact<<<1, 256, 0, st>>>(P.cand_cnt, d.R, d.tot, P.slot_r, P.slot_c, P.handled, P.total);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    size_t smA = canon_cols_smem(d.n, d.p);
+    const size_t smA = canon_cols_smem(d.n, d.p);
     k_canon_cols<CT, WT><<<512, 256, smA, st>>>(P.hubs, P.kidx, P.cand, P.slot_r, P.slot_c, P.total, d.m, d.n,
                                                 d.n_pad, d.p, (const CT *)P.C, (const WT *)P.W, P.tbuf);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    size_t smB = (size_t)16 * d.n;
-    k_canon_sums<CT><<<256, 256, smB, st>>>(P.hubs, P.kidx, P.cand, P.slot_r, P.slot_c, P.total, d.m, d.n, d.n_pad,
-                                            d.p, (const CT *)P.C, P.O, P.D, P.tbuf, d.chi, d.alpha, d.delta, d.scale,
-                                            P.cand_cost, P.cand_parts);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    size_t sm = exact_smem_bytes(d.n, d.p);
-    dim3 grid(d.R, ychunks);
-    k_recheck<CT, WT><<<grid, eval_block(d.n), sm, st>>>(P.hubs, P.kidx, P.cand, P.cand_cnt, P.handled, d.m, d.n,
-                                                         d.n_pad, d.p, (const CT *)P.C, (const WT *)P.W, P.O, P.D,
-                                                         d.chi, d.alpha, d.delta, d.scale, P.cand_cost,
-                                                         P.cand_parts);
+    const size_t smB = std::max((size_t)16 * d.n, exact_smem_bytes(d.n, d.p));
+    k_canon_sums<CT, WT><<<256, 256, smB, st>>>(S, (const int32_t *)P.kidx, P.slot_r, P.slot_c, P.total, P.extra_r,
+                                                P.extra_c, P.nextra, d.n, d.n_pad, (const CT *)P.C, (const WT *)P.W,
+                                                P.O, P.D, P.tbuf, d.chi, d.alpha, d.delta, d.scale, P.cand_cost,
+                                                P.cand_parts, P.sync + 1);
     return hipGetLastError();
 }
 
-hipError_t launch_recheck(const DevPtrs &P, const Dims &d, hipStream_t st)
+hipError_t launch_recheck(const DevPtrs &P, const Dims &d, const SelState &S, hipStream_t st)
 {
-    int y = d.m < 4 ? d.m : 4;
-    if (d.c_f32 && d.w_f32) return recheck_launch<float, float>(P, d, y, st);
-    if (d.c_f32) return recheck_launch<float, double>(P, d, y, st);
-    if (d.w_f32) return recheck_launch<double, float>(P, d, y, st);
-    return recheck_launch<double, double>(P, d, y, st);
+    if (d.c_f32 && d.w_f32) return recheck_launch<float, float>(P, d, S, st);
+    if (d.c_f32) return recheck_launch<float, double>(P, d, S, st);
+    if (d.w_f32) return recheck_launch<double, float>(P, d, S, st);
+    return recheck_launch<double, double>(P, d, S, st);
 }
 
 double fp32_eps_bound(int n)
@@ -491,11 +442,10 @@ hipError_t prepare_plain_kernels(int max_lds)
 {
     const void *fns[] = {(const void *)k_eval_exact<double, double>, (const void *)k_eval_exact<double, float>,
                          (const void *)k_eval_exact<float, double>,  (const void *)k_eval_exact<float, float>,
-                         (const void *)k_recheck<double, double>,    (const void *)k_recheck<double, float>,
-                         (const void *)k_recheck<float, double>,     (const void *)k_recheck<float, float>,
                          (const void *)k_canon_cols<double, double>, (const void *)k_canon_cols<double, float>,
                          (const void *)k_canon_cols<float, double>,  (const void *)k_canon_cols<float, float>,
-                         (const void *)k_canon_sums<double>,         (const void *)k_canon_sums<float>,
+                         (const void *)k_canon_sums<double, double>, (const void *)k_canon_sums<double, float>,
+                         (const void *)k_canon_sums<float, double>,  (const void *)k_canon_sums<float, float>,
                          (const void *)k_eval_fp32<double>,          (const void *)k_eval_fp32<float>};
     for (const void *f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);

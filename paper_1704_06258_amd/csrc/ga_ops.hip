@@ -13,117 +13,119 @@
 // removal.  Draws are Philox4x64-10 words addressed by (g, index, operator,
 // t), so an operator that does nothing never shifts later draws.
 //
-// One lane per child; hub lists are kept sorted in LDS, strided by the block
-// size so that lanes touch distinct banks.
+// One wave per child.  A sorted hub list lives in LDS with element k owned by
+// lane k (and lane k-64 for k >= 64).  With x sorted and distinct, x[k] - k
+// is the number of spokes below x[k] and is non-decreasing in k, so the spoke
+// of rank r is r + #{k : x[k] - k <= r}: one ballot.  Removing position pos
+// and inserting v moves element k to k - [k > pos] + [x[k] > v].
 #include "kernels.hpp"
 
 namespace hubga {
 
 namespace {
 
-struct List {
-    uint16_t *a;   // element k at a[k * stride]
-    int stride;
-    __device__ int get(int k) const { return a[k * stride]; }
-    __device__ void set(int k, int v) { a[k * stride] = (uint16_t)v; }
+// Sorted list of up to 128 node ids; slots k and k+64 belong to lane k.
+struct WList {
+    int *a;
+    __device__ int lo(int lane) const { return a[lane]; }
+    __device__ int hi(int lane) const { return a[lane + 64]; }
 };
 
-__device__ int nth_spoke(const List &x, int cnt, int r)
+__device__ __forceinline__ int popc(unsigned long long m) { return __popcll(m); }
+
+// Spoke of rank r for the list x[0..cnt).
+__device__ __forceinline__ int wave_nth_spoke(const WList &x, int cnt, int r, int lane)
 {
-    int v = r;
-    for (int k = 0; k < cnt; ++k) {
-        if (x.get(k) <= v)
-            ++v;
-        else
-            break;
-    }
-    return v;
+    const int e0 = lane < cnt ? x.lo(lane) - lane : 0x7FFFFFFF;
+    const int e1 = lane + 64 < cnt ? x.hi(lane) - (lane + 64) : 0x7FFFFFFF;
+    return r + popc(__ballot(e0 <= r)) + popc(__ballot(e1 <= r));
 }
 
-__device__ void remove_at(List &x, int &cnt, int pos)
+// Remove position pos (or none when pos < 0) and insert v (or none when v < 0).
+__device__ __forceinline__ void wave_edit(WList &x, int &cnt, int pos, int v, int lane)
 {
-    for (int k = pos; k + 1 < cnt; ++k) x.set(k, x.get(k + 1));
-    --cnt;
+    const bool in0 = lane < cnt, in1 = lane + 64 < cnt;
+    const int x0 = in0 ? x.lo(lane) : 0, x1 = in1 ? x.hi(lane) : 0;
+    const bool keep0 = in0 && lane != pos, keep1 = in1 && lane + 64 != pos;
+    int ins = 0;
+    if (v >= 0) ins = popc(__ballot(keep0 && x0 < v)) + popc(__ballot(keep1 && x1 < v));
+    const int d0 = lane - (pos >= 0 && lane > pos ? 1 : 0) + (v >= 0 && x0 > v ? 1 : 0);
+    const int d1 = lane + 64 - (pos >= 0 && lane + 64 > pos ? 1 : 0) + (v >= 0 && x1 > v ? 1 : 0);
+    __builtin_amdgcn_wave_barrier();
+    if (keep0) x.a[d0] = x0;
+    if (keep1) x.a[d1] = x1;
+    if (v >= 0 && lane == 0) x.a[ins] = v;
+    __builtin_amdgcn_wave_barrier();
+    cnt += (v >= 0 ? 1 : 0) - (pos >= 0 ? 1 : 0);
 }
 
-__device__ void insert_sorted(List &x, int &cnt, int v)
+// Hub<->spoke swap with the spoke ranked before the removal.
+__device__ __forceinline__ void wave_swap(int n, WList &x, int &cnt, uint64_t w_pos, uint64_t w_rank, int lane)
 {
-    int k = cnt;
-    while (k > 0 && x.get(k - 1) > v) {
-        x.set(k, x.get(k - 1));
-        --k;
-    }
-    x.set(k, v);
-    ++cnt;
-}
-
-__device__ void swap_move(int n, List &x, int &cnt, uint64_t w_pos, uint64_t w_rank)
-{
-    int pos = uindex(w_pos, cnt);
-    int v = nth_spoke(x, cnt, uindex(w_rank, n - cnt));
-    remove_at(x, cnt, pos);
-    insert_sorted(x, cnt, v);
+    const int pos = uindex(w_pos, cnt);
+    const int v = wave_nth_spoke(x, cnt, uindex(w_rank, n - cnt), lane);
+    wave_edit(x, cnt, pos, v, lane);
 }
 
 }  // namespace
 
-__global__ __launch_bounds__(64) void k_ga_ops(const int32_t *__restrict__ anc, int32_t *__restrict__ children,
-                                               const int64_t *__restrict__ gen, int n, int p, int S, int m,
-                                               uint64_t seed)
+__global__ __launch_bounds__(256) void k_ga_ops(const int32_t *__restrict__ anc, int32_t *__restrict__ children,
+                                                const int64_t *__restrict__ gen, int n, int p, int S, int m,
+                                                uint64_t seed)
 {
-    extern __shared__ uint16_t lds[];
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ int lists[4][3][128];   // per wave: parent a, parent b, child
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int s = blockIdx.x * 4 + wave;
     if (s >= S) return;
-    const int B = blockDim.x, tid = threadIdx.x;
     const uint64_t g = (uint64_t)*gen;
-    List pa{lds + tid, B}, pb{lds + (size_t)p * B + tid, B}, cx{lds + (size_t)2 * p * B + tid, B};
+    WList pa{lists[wave][0]}, pb{lists[wave][1]}, cx{lists[wave][2]};
     const int r = s / m, q = s / 2;
     const int32_t *a = anc + (size_t)r * p;
-    for (int k = 0; k < p; ++k) {
-        pa.set(k, a[k]);
-        pb.set(k, a[k]);
+    if (lane < p) {
+        pa.a[lane] = a[lane];
+        pb.a[lane] = a[lane];
     }
+    __builtin_amdgcn_wave_barrier();
     int ca = p, cb = p;
     if (p < n) {
         U64x4 w = ga_draw(seed, g, (uint64_t)(2 * q), 0, 0);
-        swap_move(n, pa, ca, w.x[0], w.x[1]);
+        wave_swap(n, pa, ca, w.x[0], w.x[1], lane);
         w = ga_draw(seed, g, (uint64_t)(2 * q + 1), 0, 0);
-        swap_move(n, pb, cb, w.x[0], w.x[1]);
+        wave_swap(n, pb, cb, w.x[0], w.x[1], lane);
     }
+    // crossover: first parent's hubs below the cut, second parent's from it on
     U64x4 w = ga_draw(seed, g, (uint64_t)q, 1, 0);
     const int cut = 1 + uindex(w.x[0], n - 1);
-    const List &first = (s & 1) ? pb : pa;
-    const List &second = (s & 1) ? pa : pb;
-    const int cf = (s & 1) ? cb : ca, cs = (s & 1) ? ca : cb;
-    int cnt = 0;
-    for (int k = 0; k < cf; ++k) {
-        int v = first.get(k);
-        if (v < cut) cx.set(cnt++, v);
-    }
-    for (int k = 0; k < cs; ++k) {
-        int v = second.get(k);
-        if (v >= cut) cx.set(cnt++, v);
-    }
+    const WList &first = (s & 1) ? pb : pa;
+    const WList &second = (s & 1) ? pa : pb;
+    const int f = lane < p ? first.lo(lane) : 0x7FFFFFFF;
+    const int sc = lane < p ? second.lo(lane) : -1;
+    const int nf = popc(__ballot(lane < p && f < cut));
+    const int ns_below = popc(__ballot(lane < p && sc < cut));
+    __builtin_amdgcn_wave_barrier();
+    if (lane < p && f < cut) cx.a[lane] = f;
+    if (lane < p && sc >= cut) cx.a[nf + lane - ns_below] = sc;
+    __builtin_amdgcn_wave_barrier();
+    int cnt = nf + (p - ns_below);
+    // mutation
     w = ga_draw(seed, g, (uint64_t)s, 2, 0);
-    if (cnt > 0 && cnt < n) swap_move(n, cx, cnt, w.x[0], w.x[1]);
+    if (cnt > 0 && cnt < n) wave_swap(n, cx, cnt, w.x[0], w.x[1], lane);
+    // correction
     uint64_t t = 0;
     while (cnt > p) {
         w = ga_draw(seed, g, (uint64_t)s, 3, t++);
-        remove_at(cx, cnt, uindex(w.x[0], cnt));
+        wave_edit(cx, cnt, uindex(w.x[0], cnt), -1, lane);
     }
     while (cnt < p) {
         w = ga_draw(seed, g, (uint64_t)s, 3, t++);
-        insert_sorted(cx, cnt, nth_spoke(cx, cnt, uindex(w.x[0], n - cnt)));
+        wave_edit(cx, cnt, -1, wave_nth_spoke(cx, cnt, uindex(w.x[0], n - cnt), lane), lane);
     }
-    int32_t *out = children + (size_t)s * p;
-    for (int k = 0; k < p; ++k) out[k] = cx.get(k);
+    if (lane < p) children[(size_t)s * p + lane] = cx.a[lane];
 }
 
 hipError_t launch_ga_ops(const DevPtrs &P, const Dims &d, hipStream_t st)
 {
-    const int B = 64;
-    size_t sm = (size_t)(4 * d.p + 2) * B * sizeof(uint16_t);
-    k_ga_ops<<<(d.S + B - 1) / B, B, sm, st>>>(P.anc, P.hubs, P.gen, d.n, d.p, d.S, d.m, d.seed);
+    k_ga_ops<<<(d.S + 3) / 4, 256, 0, st>>>(P.anc, P.hubs, P.gen, d.n, d.p, d.S, d.m, d.seed);
     return hipGetLastError();
 }
 

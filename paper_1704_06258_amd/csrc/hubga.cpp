@@ -89,7 +89,7 @@ Dims make_dims(const ga_params *q, ga_dtype cdt, ga_dtype wdt)
 // Offsets of every device buffer; the same walk sizes and carves.
 struct Carve {
     size_t C, Ct, Ct32, W, W32, Whi, Wlo, Whsw, Wlsw, O, D, dsum, hubs, kidx, cost, parts, eps, cmax, Ch32, partial, anc, anc_cost,
-        anc_parts, best, best_cost, gen, stats, cand, cand_cnt, cand_cost, cand_parts, kidx_one, scratch, tbuf, slot_r, slot_c, handled, total_slots;
+        anc_parts, best, best_cost, gen, stats, cand, cand_cnt, cand_cost, cand_parts, kidx_one, scratch, tbuf, slot_r, slot_c, handled, total_slots, extra_r, extra_c, nextra, sync;
     size_t total;
 };
 
@@ -138,6 +138,10 @@ Carve carve(const Dims &d, int c_symmetric)
     c.slot_c = L.take((size_t)d.tot * 4);
     c.handled = L.take((size_t)d.R * 4);
     c.total_slots = L.take(4);
+    c.extra_r = L.take((size_t)d.S * 4);
+    c.extra_c = L.take((size_t)d.S * 4);
+    c.nextra = L.take(4);
+    c.sync = L.take(8);
     c.total = L.total;
     return c;
 }
@@ -273,7 +277,6 @@ ga_status gen_post(ga_ctx *ctx, hipStream_t s, bool grouped, int group_cfg)
     const int exact = d.prec == kFP64;
     if (grouped) HIPCHK(launch_finalize(P, d, d.S, group_cfg, s));
     HIPCHK(launch_select(P, d, exact, s));
-    HIPCHK(launch_global(P, d, exact, s));
     return GA_OK;
 }
 
@@ -488,6 +491,10 @@ ga_status ga_init(const ga_params *q, const void *C, ga_dtype cdt, const void *W
         P.slot_c = at<int32_t>(b, c.slot_c);
         P.handled = at<int32_t>(b, c.handled);
         P.total = at<int32_t>(b, c.total_slots);
+        P.extra_r = at<int32_t>(b, c.extra_r);
+        P.extra_c = at<int32_t>(b, c.extra_c);
+        P.nextra = at<int32_t>(b, c.nextra);
+        P.sync = at<int>(b, c.sync);
 
         const size_t n2 = (size_t)d.n * d.n;
         auto dev_fail = [&](hipError_t he, const char *what) {

@@ -1,6 +1,7 @@
 // Launchers of the device kernels of libhubga (internal).
 #pragma once
 #include "common.hpp"
+#include "select_dev.hpp"
 
 namespace hubga {
 
@@ -18,7 +19,7 @@ hipError_t launch_eval_exact(const DevPtrs &P, const Dims &d, const int32_t *hub
                              double *cost, double *parts, double *eps, hipStream_t st);
 hipError_t launch_eval_fp32(const DevPtrs &P, const Dims &d, const int32_t *hubs, const uint16_t *kidx, int count,
                             hipStream_t st);
-hipError_t launch_recheck(const DevPtrs &P, const Dims &d, hipStream_t st);
+hipError_t launch_recheck(const DevPtrs &P, const Dims &d, const SelState &S, hipStream_t st);
 double fp32_eps_bound(int n);
 hipError_t prepare_plain_kernels(int max_lds);
 
@@ -41,7 +42,6 @@ int mfma_k_tile(int cfg);
 // GA (ga_ops.hip, select.hip)
 hipError_t launch_ga_ops(const DevPtrs &P, const Dims &d, hipStream_t st);
 hipError_t launch_select(const DevPtrs &P, const Dims &d, int exact, hipStream_t st);
-hipError_t launch_global(const DevPtrs &P, const Dims &d, int exact, hipStream_t st);
 hipError_t launch_init_state(const DevPtrs &P, const Dims &d, hipStream_t st);
 
 }  // namespace hubga

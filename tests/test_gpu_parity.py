@@ -325,3 +325,44 @@ def test_pipelined_configs_all_hub_counts(p):
             out = s.evaluate(hubs)
         err = np.abs(out["cost"] - ref_c) / ref_c
         assert np.all(err <= out["eps"]), (cfg, err.max())
+
+
+# ---------------------------------------------------- full-size workloads --
+
+def test_headline_workload_full_population_two_generations():
+    """n=1000, p=20, population 4096 in 64 islands, split-bf16 in the
+    benchmark's configuration: the trajectory equals the oracle's."""
+    inst = I.clustered()
+    st = oracle_trajectory(inst, 2, S=4096, m=64, n1=10, seed=1)
+    for cfg in (0, 7):
+        with make(inst, population=4096, island_size=64, n1=10, seed=1, precision="split_bf16") as s:
+            s.set_tile_config(cfg)
+            s.step(2)
+            assert_same_state(s, st)
+            hubs, cost = s.population()
+        ref, _ = ref_eval(inst, hubs[::64])
+        err = np.abs(cost[::64] - ref) / ref
+        assert err.max() <= 1e-6
+
+
+def test_large_workload_sampled():
+    """n=6000, p=50, population 2048 (FP32 instance): generation-0 children
+    equal the oracle's, sampled costs are within their bounds, and the new
+    ancestors carry their exact costs."""
+    inst = I.large()
+    C64, W64 = inst.C64(), inst.W64()
+    with make(inst, population=2048, island_size=64, n1=10, seed=1, precision="split_bf16") as s:
+        anc0, _ = s.ancestors()
+        s.step(1)
+        hubs, cost = s.population()
+        anc, anc_cost = s.ancestors()
+        out = s.evaluate(hubs[::128])
+    ref_children = oracle.ga_children(inst.n, inst.p, 2048, 64, 1, 0, anc0)
+    assert np.array_equal(hubs, ref_children)
+    ref, _ = oracle.evaluate(C64, W64, hubs[::128], inst.chi, inst.alpha, inst.delta)
+    assert np.all(np.abs(out["cost"] - ref) <= out["eps"] * ref)
+    assert np.all(np.abs(cost[::128] - ref) <= out["eps"] * ref)
+    uniq = np.unique(anc, axis=0)
+    exact, _ = oracle.evaluate(C64, W64, uniq, inst.chi, inst.alpha, inst.delta)
+    for row, c in zip(uniq, exact):
+        assert np.all(anc_cost[np.all(anc == row, axis=1)] == c)
