@@ -67,18 +67,34 @@ __device__ void eval_exact_body(const int32_t *__restrict__ hg, const uint16_t *
             kj[q] = js[q] < n ? kid[js[q]] : 0;
             acc[q] = 0.0;
         }
-        const bool full = js[3] < n;
-        for (int i = 0; i < n; ++i) {
+        // rows in groups of 8: 32 loads in flight per lane, then the adds in
+        // ascending row order (absent columns read 0 and are discarded)
+        int jc[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) jc[q] = js[q] < n ? js[q] : 0;
+        int i = 0;
+        for (; i + 8 <= n; i += 8) {
+            double w[8][4];
+            int ki[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const WT *wr = W + (size_t)(i + u) * n;
+                ki[u] = kid[i + u];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) w[u][q] = (double)wr[jc[q]];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const double *chr = Ch + (size_t)ki[u] * p;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[q] = acc[q] + w[u][q] * chr[kj[q]];
+            }
+        }
+        for (; i < n; ++i) {
             const WT *wr = W + (size_t)i * n;
             const double *chr = Ch + (size_t)kid[i] * p;
-            if (full) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) acc[q] = acc[q] + (double)wr[js[q]] * chr[kj[q]];
-            } else {
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    if (js[q] < n) acc[q] = acc[q] + (double)wr[js[q]] * chr[kj[q]];
-            }
+            for (int q = 0; q < 4; ++q) acc[q] = acc[q] + (double)wr[jc[q]] * chr[kj[q]];
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q)
