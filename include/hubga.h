@@ -180,6 +180,12 @@ ga_status ga_stats(ga_ctx *ctx, int64_t stats[4]);
 ga_status ga_profile_enable(ga_ctx *ctx, int32_t enable);
 ga_status ga_profile_read(ga_ctx *ctx, double *ms_total, int64_t *launches);
 
+/* Move the context to another stream (hipStream_t, non-null or NULL): work
+ * already queued on the old stream stays ordered before everything issued
+ * afterwards on the new one (an event, no host wait).  The context must not
+ * be in a batch whose stream differs from the new one when the batch steps. */
+ga_status ga_set_stream(ga_ctx *ctx, void *hip_stream);
+
 /* Tile configurations of the batched matrix-core kernel, for autotuning:
  * ga_tile_config_count() configurations, numbered from 0; ga_tile_config_info
  * gives rows and columns of W x [A_1..A_S] per workgroup tile and the K depth

@@ -13,7 +13,7 @@
 
 namespace hubga {
 
-constexpr int kAllocPer = 4;   // individuals per workgroup
+constexpr int kAllocPer = 1;   // individuals per workgroup
 
 template <typename CT>
 __global__ __launch_bounds__(256) void k_alloc(const int32_t *__restrict__ hubs, int count, int n, int n_pad, int p,

@@ -371,26 +371,44 @@ __device__ __forceinline__ void mfma_pipe_tile(const MfmaJob &J, int tile, u32x4
         });
     }
 
-    // epilogue (as in k_eval_mfma)
+    // Epilogue: sum_i G[i][(s,l)] * C[h_k(i)][h_l] over this tile's rows in
+    // binary64.  The ring is free once every wave has left the K loop: it
+    // takes the hub positions of the tile's rows and the FP32 hub-distance
+    // tables of the workgroup's individuals, so the gathers hit LDS.
+    // Accumulator v of a 32x32 block holds row 8*(v/4) + 4*half + (v%4).
+    wg_barrier();
+    const int s_lo = min(N0, NS - 1) / p, s_hi = min(N0 + NT - 1, NS - 1) / p;
+    const int nind = s_hi - s_lo + 1;
+    const size_t need = (size_t)nind * MT * 2 + (size_t)nind * p * p * 4;
+    const bool staged = need <= sizeof(u32x4) * NST * STAGE;
+    uint16_t *lk = (uint16_t *)ring;                                     // [ind][row]
+    float *lch = (float *)((char *)ring + (((size_t)nind * MT * 2 + 15) & ~(size_t)15));   // [ind][k][l]
+    if (staged) {
+        for (int e = tid; e < nind * MT; e += 256) {
+            const int ind = e / MT, row = e % MT;
+            lk[e] = kidx[(size_t)(s_lo + ind) * n_pad + M0 + row];
+        }
+        const int pp = p * p;
+        for (int e = tid; e < nind * pp; e += 256) lch[e] = Ch32[(size_t)s_lo * pp + e];
+        __syncthreads();
+    }
 #pragma unroll
     for (int b = 0; b < COLB; ++b) {
-        double sum = 0.0;
+        double part[4] = {0.0, 0.0, 0.0, 0.0};
         if (col[b] < NS) {
             const int s = col[b] / p;
-            const uint16_t *kr = kidx + (size_t)s * n_pad;
-            const float *ch = Ch32 + (size_t)s * p * p + lq[b];
+            const uint16_t *kr = staged ? lk + (size_t)(s - s_lo) * MT - M0 : kidx + (size_t)s * n_pad;
+            const float *ch = (staged ? lch + (size_t)(s - s_lo) * p * p : Ch32 + (size_t)s * p * p) + lq[b];
 #pragma unroll
             for (int a = 0; a < ROWB; ++a) {
 #pragma unroll
                 for (int v = 0; v < 16; ++v) {
                     const int i = M0 + a * 32 + 8 * (v >> 2) + 4 * half + (v & 3);
-                    if (i < n) {
-                        const int k = kr[i];
-                        sum += (double)acc[a][b][v] * (double)ch[k * p];
-                    }
+                    if (i < n) part[v & 3] += (double)acc[a][b][v] * (double)ch[kr[i] * p];
                 }
             }
         }
+        double sum = (part[0] + part[1]) + (part[2] + part[3]);
         sum += __shfl_xor(sum, 32);
         if (half == 0 && col[b] < NS) partial[(size_t)col[b] * n_mt + mt] = sum;
     }

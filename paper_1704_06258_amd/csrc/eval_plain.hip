@@ -149,8 +149,8 @@ __global__ __launch_bounds__(256) void k_eval_exact(const int32_t *__restrict__ 
 // workgroup forms products W_ij * C[a_i][a_j] for the tile -- the same binary64
 // products as the sequential definition -- and one lane per column adds them
 // in ascending row order into t_j.  k_canon_sums then sums T, Cc and Dd in
-// ascending order, evaluates the extra candidates whole (one workgroup each),
-// and its last workgroup decides every island and ends the generation.
+// ascending order and evaluates the extra candidates whole (one workgroup
+// each); k_select2 decides every island on exact costs.
 constexpr int kCanonCols = 32;
 constexpr int kCanonRows = 128;
 
@@ -258,7 +258,7 @@ __global__ __launch_bounds__(256) void k_canon_sums(SelState S, const int32_t *_
                                                     const double *__restrict__ O, const double *__restrict__ D,
                                                     const double *__restrict__ tbuf, double chi, double alpha,
                                                     double delta, double scale, double *__restrict__ cand_cost,
-                                                    double *__restrict__ cand_parts, int *__restrict__ sync)
+                                                    double *__restrict__ cand_parts)
 {
 #pragma clang fp contract(off)
     extern __shared__ __align__(16) char smem[];
@@ -307,8 +307,14 @@ __global__ __launch_bounds__(256) void k_canon_sums(SelState S, const int32_t *_
         eval_exact_body<CT, WT>(S.children + (size_t)s * p, kid16 + (size_t)s * n_pad, n, p, C, W, O, D, chi,
                                 alpha, delta, scale, cand_cost + o, cand_parts + 3 * o, smem);
     }
+}
+
+// Island decisions on exact costs, one workgroup per island; the last
+// workgroup ends the generation (global step, best so far, g + 1).
+__global__ __launch_bounds__(256) void k_select2(SelState S, int *__restrict__ sync)
+{
+    select_island_exact(S, blockIdx.x);
     if (!last_block(sync, gridDim.x)) return;
-    for (int r = 0; r < S.R; ++r) select_island_exact(S, r);
     global_step(S);
 }
 
@@ -416,7 +422,9 @@ static hipError_t recheck_launch(const DevPtrs &P, const Dims &d, const SelState
     k_canon_sums<CT, WT><<<256, 256, smB, st>>>(S, (const int32_t *)P.kidx, P.slot_r, P.slot_c, P.total, P.extra_r,
                                                 P.extra_c, P.nextra, d.n, d.n_pad, (const CT *)P.C, (const WT *)P.W,
                                                 P.O, P.D, P.tbuf, d.chi, d.alpha, d.delta, d.scale, P.cand_cost,
-                                                P.cand_parts, P.sync + 1);
+                                                P.cand_parts);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_select2<<<d.R, 256, 0, st>>>(S, P.sync + 1);
     return hipGetLastError();
 }
 
@@ -464,7 +472,11 @@ hipError_t prepare_plain_kernels(int max_lds)
                          (const void *)k_canon_sums<float, double>,  (const void *)k_canon_sums<float, float>,
                          (const void *)k_eval_fp32<double>,          (const void *)k_eval_fp32<float>};
     for (const void *f : fns) {
-        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+        hipFuncAttributes fa;
+        hipError_t e = hipFuncGetAttributes(&fa, f);
+        if (e != hipSuccess) return e;
+        const int dyn = max_lds - (int)fa.sharedSizeBytes;   // the cap excludes the kernel's static LDS
+        e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -415,18 +415,28 @@ ga_status ga_init(const ga_params *q, const void *C, ga_dtype cdt, const void *W
             static std::once_flag once;
             static hipError_t prep_err = hipSuccess;
             std::call_once(once, [] {
-                int dev = 0, max_lds = 65536;
-                if (hipGetDevice(&dev) == hipSuccess)
+                int dev = 0, max_lds = 65536, optin = 0;
+                if (hipGetDevice(&dev) == hipSuccess) {
                     (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+                    if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, dev) == hipSuccess &&
+                        optin > max_lds)
+                        max_lds = optin;
+                }
+                (void)hipGetLastError();
                 prep_err = prepare_plain_kernels(max_lds);
             });
             if (prep_err != hipSuccess)
                 return fail(nullptr, GA_ERR_DEVICE, std::string("kernel attributes: ") + hipGetErrorString(prep_err));
         }
         if (make_dims(q, cdt, wdt).n > 0) {
-            int dev = 0, max_lds = 65536;
-            if (hipGetDevice(&dev) == hipSuccess)
+            int dev = 0, max_lds = 65536, optin = 0;
+            if (hipGetDevice(&dev) == hipSuccess) {
                 (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+                if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, dev) == hipSuccess &&
+                    optin > max_lds)
+                    max_lds = optin;
+            }
+            (void)hipGetLastError();
             const size_t need = std::max<size_t>((size_t)d.p * d.p * 8 + (size_t)d.n * 10 + 512, (size_t)16 * d.n);
             if (need > (size_t)max_lds)
                 return fail(nullptr, GA_ERR_INVALID, "n too large for this device's LDS (exact kernels)");
@@ -763,6 +773,22 @@ ga_status ga_profile_read(ga_ctx *ctx, double *ms_total, int64_t *launches)
     }
     if (ms_total) *ms_total = tot;
     if (launches) *launches = ctx->ev_used / 2;
+    return GA_OK;
+}
+
+ga_status ga_set_stream(ga_ctx *ctx, void *hip_stream)
+{
+    CTXCHK(ctx);
+    hipStream_t ns = (hipStream_t)hip_stream;
+    if (ns == ctx->st) return GA_OK;
+    hipEvent_t ev;
+    HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    hipError_t e1 = hipEventRecord(ev, ctx->st);
+    hipError_t e2 = e1 == hipSuccess ? hipStreamWaitEvent(ns, ev, 0) : e1;
+    (void)hipEventDestroy(ev);   // released once the recorded work completes
+    HIPCHK(e2);
+    ctx->st = ns;
+    ctx->graph_failed = false;   // a capture refused on the old stream may succeed on this one
     return GA_OK;
 }
 

@@ -28,7 +28,7 @@ DEFAULT_KERNEL = {GA_PREC_FP64: GA_KERN_PLAIN, GA_PREC_FP32: GA_KERN_PLAIN, GA_P
 EXPORTS = ("ga_params_default", "ga_workspace_bytes", "ga_init", "ga_evaluate", "ga_evaluate_dev", "ga_step",
            "ga_best", "ga_solve", "ga_population", "ga_ancestors", "ga_get_state", "ga_set_state", "ga_stats",
            "ga_profile_enable", "ga_profile_read", "ga_tile_config_count", "ga_tile_config_info",
-           "ga_set_tile_config", "ga_batch_create", "ga_batch_set", "ga_batch_step", "ga_batch_free",
+           "ga_set_tile_config", "ga_set_stream", "ga_batch_create", "ga_batch_set", "ga_batch_step", "ga_batch_free",
            "ga_status_str", "ga_last_error", "ga_free")
 
 
@@ -86,6 +86,8 @@ def lib():
         L.ga_tile_config_count.restype = i32
         L.ga_tile_config_info.argtypes = [i32, ct.POINTER(i32), ct.POINTER(i32), ct.POINTER(i32)]
         L.ga_tile_config_info.restype = ct.c_int
+        L.ga_set_stream.argtypes = [vp, vp]
+        L.ga_set_stream.restype = ct.c_int
         L.ga_set_tile_config.argtypes = [vp, i32]
         L.ga_set_tile_config.restype = ct.c_int
         L.ga_batch_create.argtypes = [vp, i32, ct.POINTER(vp)]
@@ -279,6 +281,11 @@ class Solver:
         s = np.zeros(4, np.int64)
         _check(lib().ga_stats(self.ctx, s.ctypes.data), self.ctx)
         return dict(generations=int(s[0]), rechecks=int(s[1]), islands_rechecked=int(s[2]), evaluations=int(s[3]))
+
+    def set_stream(self, stream):
+        """Issue later work on ``stream`` (ordered after the work already queued)."""
+        _check(lib().ga_set_stream(self.ctx, ct.c_void_p(stream.cuda_stream)), self.ctx)
+        self.stream = stream
 
     def set_tile_config(self, config: int):
         _check(lib().ga_set_tile_config(self.ctx, int(config)), self.ctx)

@@ -45,11 +45,12 @@ def test_graph_replay_equals_direct_launches():
         b.profile_enable(True)         # profiling launches kernels directly
         b.step(9)
         b.profile_enable(False)
-        assert same(state_of(a), state_of(b))
+        sa = state_of(a)
+        assert same(sa, state_of(b))
     st = oracle.ga_init(inst.C64(), inst.W64(), inst.p, 512, 64, inst.chi, inst.alpha, inst.delta)
     oracle.ga_run(inst.C64(), inst.W64(), st, 9, S=512, m=64, n1=4, seed=3, chi=inst.chi, alpha=inst.alpha,
                   delta=inst.delta)
-    assert np.array_equal(state_of(a)[0], st.anc) and state_of(a)[3] == st.best_cost[0]
+    assert np.array_equal(sa[0], st.anc) and sa[3] == st.best_cost[0]
 
 
 MIX = [  # (instance, population, island, precision)
@@ -122,3 +123,18 @@ def test_batch_rejects_foreign_stream_and_empty_is_noop():
     with pytest.raises(hubga.HubGAError):
         hubga.Batch(tile_config=0)    # not a pipelined configuration
     batch.close()
+
+
+def test_set_stream_keeps_order_and_trajectory():
+    import torch
+    inst = I.medium()
+    kw = dict(population=512, island_size=64, n1=4, seed=8, precision="split_bf16")
+    with make(inst, **kw) as a:
+        a.step(7)
+        ref = state_of(a)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    with make(inst, stream=s1, **kw) as b:
+        b.step(3)                      # queued on s1, not waited for
+        b.set_stream(s2)
+        b.step(4)
+        assert same(state_of(b), ref)
