@@ -381,8 +381,11 @@ __device__ __forceinline__ void mfma_pipe_tile(const MfmaJob &J, int tile, u32x4
     const int nind = s_hi - s_lo + 1;
     const size_t need = (size_t)nind * MT * 2 + (size_t)nind * p * p * 4;
     const bool staged = need <= sizeof(u32x4) * NST * STAGE;
-    uint16_t *lk = (uint16_t *)ring;                                     // [ind][row]
-    float *lch = (float *)((char *)ring + (((size_t)nind * MT * 2 + 15) & ~(size_t)15));   // [ind][k][l]
+    // Indices into the staged arrays are offsets from their start (never a
+    // pointer moved before it): LDS pointer arithmetic is 32-bit, and a
+    // negative intermediate would leave the LDS aperture of a flat address.
+    uint16_t *lk = (uint16_t *)ring;                                              // [ind][row - M0]
+    float *lch = (float *)(ring + (nind * MT * 2 + 15) / 16);                     // [ind][k][l]
     if (staged) {
         for (int e = tid; e < nind * MT; e += 256) {
             const int ind = e / MT, row = e % MT;
@@ -397,14 +400,26 @@ __device__ __forceinline__ void mfma_pipe_tile(const MfmaJob &J, int tile, u32x4
         double part[4] = {0.0, 0.0, 0.0, 0.0};
         if (col[b] < NS) {
             const int s = col[b] / p;
-            const uint16_t *kr = staged ? lk + (size_t)(s - s_lo) * MT - M0 : kidx + (size_t)s * n_pad;
-            const float *ch = (staged ? lch + (size_t)(s - s_lo) * p * p : Ch32 + (size_t)s * p * p) + lq[b];
+            if (staged) {
+                const int kb = (s - s_lo) * MT, cb = (s - s_lo) * p * p + (int)lq[b];
 #pragma unroll
-            for (int a = 0; a < ROWB; ++a) {
+                for (int a = 0; a < ROWB; ++a) {
 #pragma unroll
-                for (int v = 0; v < 16; ++v) {
-                    const int i = M0 + a * 32 + 8 * (v >> 2) + 4 * half + (v & 3);
-                    if (i < n) part[v & 3] += (double)acc[a][b][v] * (double)ch[kr[i] * p];
+                    for (int v = 0; v < 16; ++v) {
+                        const int r = a * 32 + 8 * (v >> 2) + 4 * half + (v & 3);
+                        if (M0 + r < n) part[v & 3] += (double)acc[a][b][v] * (double)lch[cb + lk[kb + r] * p];
+                    }
+                }
+            } else {
+                const uint16_t *kr = kidx + (size_t)s * n_pad;
+                const float *ch = Ch32 + (size_t)s * p * p + lq[b];
+#pragma unroll
+                for (int a = 0; a < ROWB; ++a) {
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) {
+                        const int i = M0 + a * 32 + 8 * (v >> 2) + 4 * half + (v & 3);
+                        if (i < n) part[v & 3] += (double)acc[a][b][v] * (double)ch[kr[i] * p];
+                    }
                 }
             }
         }
