@@ -389,7 +389,9 @@ __device__ __forceinline__ void mfma_pipe_tile(const MfmaJob &J, int tile, u32x4
     if (staged) {
         for (int e = tid; e < nind * MT; e += 256) {
             const int ind = e / MT, row = e % MT;
-            lk[e] = kidx[(size_t)(s_lo + ind) * n_pad + M0 + row];
+            // rows past n get position 0: their products are exactly zero (W is
+            // zero-padded), which keeps the sum below free of branches
+            lk[e] = M0 + row < n ? kidx[(size_t)(s_lo + ind) * n_pad + M0 + row] : 0;
         }
         const int pp = p * p;
         for (int e = tid; e < nind * pp; e += 256) lch[e] = Ch32[(size_t)s_lo * pp + e];
@@ -401,13 +403,19 @@ __device__ __forceinline__ void mfma_pipe_tile(const MfmaJob &J, int tile, u32x4
         if (col[b] < NS) {
             const int s = col[b] / p;
             if (staged) {
-                const int kb = (s - s_lo) * MT, cb = (s - s_lo) * p * p + (int)lq[b];
+                // rows a*32 + 8j + 4*half + t (t = 0..3) are 4 consecutive positions
+                const int kb = (s - s_lo) * MT + 4 * half, cb = (s - s_lo) * p * p + (int)lq[b];
 #pragma unroll
                 for (int a = 0; a < ROWB; ++a) {
 #pragma unroll
-                    for (int v = 0; v < 16; ++v) {
-                        const int r = a * 32 + 8 * (v >> 2) + 4 * half + (v & 3);
-                        if (M0 + r < n) part[v & 3] += (double)acc[a][b][v] * (double)lch[cb + lk[kb + r] * p];
+                    for (int j = 0; j < 4; ++j) {
+                        const uint2 k4 = *(const uint2 *)(lk + kb + a * 32 + 8 * j);
+                        const int k0 = (int)(k4.x & 0xFFFFu), k1 = (int)(k4.x >> 16);
+                        const int k2 = (int)(k4.y & 0xFFFFu), k3 = (int)(k4.y >> 16);
+                        part[0] += (double)acc[a][b][4 * j + 0] * (double)lch[cb + k0 * p];
+                        part[1] += (double)acc[a][b][4 * j + 1] * (double)lch[cb + k1 * p];
+                        part[2] += (double)acc[a][b][4 * j + 2] * (double)lch[cb + k2 * p];
+                        part[3] += (double)acc[a][b][4 * j + 3] * (double)lch[cb + k3 * p];
                     }
                 }
             } else {
