@@ -104,7 +104,7 @@ def cpu_baseline(inst, gpu_hubs, gpu_cost, budget_s=12.0, label="n=1000, p=20"):
                        f"{t_used:.1f} s of CPU work"), float(err.max())
 
 
-def serving_leg(count, warmup, rate=200.0, budget=16 << 30, slots=32):
+def serving_leg(count, warmup, rate=200.0, budget=16 << 30, slots=64):
     """Continuous-batching serving of a Poisson request stream: p50/p99
     latency from scheduled arrival to result, completed solves/s and
     evaluations/s.  Instances come from a pool of 4 seeded instances per size
@@ -129,7 +129,9 @@ def serving_leg(count, warmup, rate=200.0, budget=16 << 30, slots=32):
     measured = [r for r in res if r.rid >= warmup]
     st = serve.latency_stats(measured)
     evals = sum(reqs[r.rid].population * reqs[r.rid].generations for r in res)
+    offered = rate * sum(q.population * q.generations for q in reqs) / len(reqs)
     return {"requests": count, "warmup": warmup, "rate_per_s": rate, "generations": 100,
+            "offered_evals_per_s": offered,
             "p50_latency_s": st.get("p50_s"), "p99_latency_s": st.get("p99_s"), "mean_latency_s": st.get("mean_s"),
             "completed_per_s": len(res) / wall, "evals_per_s": evals / wall, "max_resident": srv.max_resident,
             "ticks": srv.ticks, "budget_bytes": budget, "slots": slots}

@@ -15,22 +15,25 @@ namespace hubga {
 
 constexpr int kAllocPer = 1;   // individuals per workgroup
 
+// Workgroup blk (of a grid of alloc_blocks(count)) of one context.
 template <typename CT>
-__global__ __launch_bounds__(256) void k_alloc(const int32_t *__restrict__ hubs, int count, int n, int n_pad, int p,
-                                               const CT *__restrict__ Ct, const float *__restrict__ Ct32,
-                                               const double *__restrict__ O, const double *__restrict__ D,
-                                               uint16_t *__restrict__ kidx, double *__restrict__ parts,
-                                               int32_t *__restrict__ cmax, float *__restrict__ Ch32, int want_sums)
+__device__ __forceinline__ void alloc_body(const int32_t *__restrict__ hubs, int count, int n, int n_pad, int p,
+                                           const CT *__restrict__ Ct, const float *__restrict__ Ct32,
+                                           const double *__restrict__ O, const double *__restrict__ D,
+                                           uint16_t *__restrict__ kidx, double *__restrict__ parts,
+                                           int32_t *__restrict__ cmax, float *__restrict__ Ch32, int want_sums,
+                                           int blk)
 {
 #pragma clang fp contract(off)
     __shared__ int sh_h[kAllocPer][kMaxP];
     __shared__ int sh_cnt[kAllocPer][kMaxP];
     __shared__ double red_c[kAllocPer][256], red_d[kAllocPer][256];
     // XCD-major group order: consecutive groups (children of one island) run
-    // on the same XCD (blockIdx % 8) and share its L2.
+    // on the same XCD (workgroup index % 8; a grouped launch starts every
+    // context on a multiple of 8) and share its L2.
     const int groups = (count + kAllocPer - 1) / kAllocPer;
     const int per = (groups + 7) / 8;
-    const int grp = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    const int grp = (blk & 7) * per + (blk >> 3);
     if (grp >= groups) return;
     const int s0 = grp * kAllocPer;
     const int nind = min(kAllocPer, count - s0);
@@ -162,19 +165,57 @@ hipError_t launch_copy_clamp(const int32_t *src, int32_t *dst, int total, int n,
     return hipGetLastError();
 }
 
+template <typename CT>
+__global__ __launch_bounds__(256) void k_alloc(const int32_t *__restrict__ hubs, int count, int n, int n_pad, int p,
+                                               const CT *__restrict__ Ct, const float *__restrict__ Ct32,
+                                               const double *__restrict__ O, const double *__restrict__ D,
+                                               uint16_t *__restrict__ kidx, double *__restrict__ parts,
+                                               int32_t *__restrict__ cmax, float *__restrict__ Ch32, int want_sums)
+{
+    alloc_body<CT>(hubs, count, n, n_pad, p, Ct, Ct32, O, D, kidx, parts, cmax, Ch32, want_sums, blockIdx.x);
+}
+
+// Grouped: the children of every context, with their sums and hub tables
+// (the split-bf16 generation).
+__global__ __launch_bounds__(256) void k_alloc_group(const TickJob *__restrict__ jobs, int njobs)
+{
+    const TickJob &J = jobs[tick_job(jobs, njobs, kTickAlloc, blockIdx.x)];
+    const int blk = blockIdx.x - J.start[kTickAlloc];
+    const DevPtrs &P = J.P;
+    const Dims &d = J.d;
+    if (d.c_f32)
+        alloc_body<float>(P.hubs, d.S, d.n, d.n_pad, d.p, (const float *)P.Ct, P.Ct32, P.O, P.D, P.kidx, P.parts,
+                          P.cmax, P.Ch32, 1, blk);
+    else
+        alloc_body<double>(P.hubs, d.S, d.n, d.n_pad, d.p, (const double *)P.Ct, P.Ct32, P.O, P.D, P.kidx,
+                           P.parts, P.cmax, P.Ch32, 1, blk);
+}
+
+int alloc_blocks(int count)
+{
+    const int groups = (count + kAllocPer - 1) / kAllocPer;
+    return ((groups + 7) / 8) * 8;
+}
+
 hipError_t launch_alloc(const DevPtrs &P, const Dims &d, const int32_t *hubs, int count, uint16_t *kidx,
                         int want_sums, int want_ch, hipStream_t st)
 {
     if (count <= 0) return hipSuccess;
     float *ch = want_ch ? P.Ch32 : nullptr;
-    const int groups = (count + kAllocPer - 1) / kAllocPer;
-    const unsigned grid = (unsigned)(((groups + 7) / 8) * 8);
+    const unsigned grid = (unsigned)alloc_blocks(count);
     if (d.c_f32)
         k_alloc<float><<<grid, 256, 0, st>>>(hubs, count, d.n, d.n_pad, d.p, (const float *)P.Ct, P.Ct32, P.O, P.D,
                                              kidx, P.parts, P.cmax, ch, want_sums);
     else
         k_alloc<double><<<grid, 256, 0, st>>>(hubs, count, d.n, d.n_pad, d.p, (const double *)P.Ct, P.Ct32, P.O,
                                               P.D, kidx, P.parts, P.cmax, ch, want_sums);
+    return hipGetLastError();
+}
+
+hipError_t launch_alloc_group(const TickJob *jobs, int njobs, int blocks, hipStream_t st)
+{
+    if (njobs <= 0 || blocks <= 0) return hipSuccess;
+    k_alloc_group<<<blocks, 256, 0, st>>>(jobs, njobs);
     return hipGetLastError();
 }
 

@@ -66,6 +66,36 @@ struct Dims {
     uint64_t seed;
 };
 
+// ----------------------------------------------------- grouped launches --
+// One generation of several contexts with one launch per step: the grid is
+// the concatenation of the contexts' own grids, start[phase] being the first
+// workgroup of context j, so every workgroup serves exactly one context.
+enum TickPhase { kTickOps = 0, kTickAlloc, kTickFinal, kTickSel1, kTickCols, kTickSums, kTickSel2, kTickPhases };
+constexpr int kTickColsBlocks = 64;   // per context: persistent workgroups of the column-parallel re-evaluation
+constexpr int kTickSumsBlocks = 32;   // per context: workgroups of the candidate sums
+
+struct TickJob {
+    DevPtrs P;
+    Dims d;
+    int n_mt;                  // row tiles of the epilogue partials
+    int start[kTickPhases];
+    int blocks[kTickPhases];
+};
+
+// The context owning workgroup b of a grouped launch (last job with start <= b).
+__device__ inline int tick_job(const TickJob *__restrict__ jobs, int njobs, int phase, int b)
+{
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].start[phase] <= b)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
 // ----------------------------------------------------------------- RNG --
 // Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
 // 64x64->128 multiplies with the halves crossed and xored with the round key,

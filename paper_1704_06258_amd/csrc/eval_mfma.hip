@@ -474,13 +474,12 @@ __global__ __launch_bounds__(256, OCC) void k_eval_mfma_pipe_group(const MfmaJob
 // T_s = sum of the individual's p*n_mt partials (contiguous), one wave per
 // individual with a fixed reduction order; cost assembly
 // f = ((chi*Cc) + (alpha*T)) + (delta*Dd) and its relative error bound.
-__global__ __launch_bounds__(256) void k_finalize_split(const double *__restrict__ partial,
-                                                        const int32_t *__restrict__ cmax, int count, int p, int n_mt,
-                                                        int n, int c_f32, double chi, double alpha, double delta,
-                                                        double scale, double *__restrict__ cost,
-                                                        double *__restrict__ parts, double *__restrict__ eps)
+__device__ __forceinline__ void finalize_body(const double *__restrict__ partial, const int32_t *__restrict__ cmax,
+                                              int count, int p, int n_mt, int n, int c_f32, double chi, double alpha,
+                                              double delta, double scale, double *__restrict__ cost,
+                                              double *__restrict__ parts, double *__restrict__ eps, int blk)
 {
-    const int s = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int s = blk * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (s >= count) return;
     const int len = p * n_mt;
@@ -499,6 +498,24 @@ __global__ __launch_bounds__(256) void k_finalize_split(const double *__restrict
         eps[s] = kSplitResidual + gamma_k(2.0 * cmax[s], kU32Faithful) + (c_f32 ? 0.0 : kU32) +
                  gamma_k((double)n + (double)len + 8.0, kU64) + gamma_k(n + 2.0, kU64) + gamma_k(8.0, kU64) + 1e-9;
     }
+}
+
+__global__ __launch_bounds__(256) void k_finalize_split(const double *__restrict__ partial,
+                                                        const int32_t *__restrict__ cmax, int count, int p, int n_mt,
+                                                        int n, int c_f32, double chi, double alpha, double delta,
+                                                        double scale, double *__restrict__ cost,
+                                                        double *__restrict__ parts, double *__restrict__ eps)
+{
+    finalize_body(partial, cmax, count, p, n_mt, n, c_f32, chi, alpha, delta, scale, cost, parts, eps, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_finalize_group(const TickJob *__restrict__ jobs, int njobs)
+{
+    const TickJob &J = jobs[tick_job(jobs, njobs, kTickFinal, blockIdx.x)];
+    const DevPtrs &P = J.P;
+    const Dims &d = J.d;
+    finalize_body(P.partial, P.cmax, d.S, d.p, J.n_mt, d.n, d.c_f32, d.chi, d.alpha, d.delta, d.scale, P.cost,
+                  P.parts, P.eps, blockIdx.x - J.start[kTickFinal]);
 }
 
 template <int ROWB, int COLB, int KT, int OCC>
@@ -589,6 +606,15 @@ hipError_t launch_finalize(const DevPtrs &P, const Dims &d, int count, int cfg, 
     const int n_mt = mfma_partial_tiles(d, cfg);
     k_finalize_split<<<(count + 3) / 4, 256, 0, st>>>(P.partial, P.cmax, count, d.p, n_mt, d.n, d.c_f32, d.chi,
                                                       d.alpha, d.delta, d.scale, P.cost, P.parts, P.eps);
+    return hipGetLastError();
+}
+
+int finalize_blocks(int count) { return (count + 3) / 4; }
+
+hipError_t launch_finalize_group(const TickJob *jobs, int njobs, int blocks, hipStream_t st)
+{
+    if (njobs <= 0 || blocks <= 0) return hipSuccess;
+    k_finalize_group<<<blocks, 256, 0, st>>>(jobs, njobs);
     return hipGetLastError();
 }
 

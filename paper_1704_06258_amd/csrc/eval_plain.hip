@@ -159,17 +159,16 @@ __host__ __device__ inline size_t canon_cols_smem(int n, int p)
     return (size_t)p * p * 8 + (size_t)kCanonRows * kCanonCols * 8 + (((size_t)n * 2 + 15) / 16) * 16;
 }
 
+// Workgroup blk of nblk persistent ones of a context (LDS: canon_cols_smem).
 template <typename CT, typename WT>
-__global__ __launch_bounds__(256) void k_canon_cols(const int32_t *__restrict__ hubs,
-                                                    const uint16_t *__restrict__ kidx,
-                                                    const int32_t *__restrict__ cand, const int32_t *__restrict__ slot_r,
-                                                    const int32_t *__restrict__ slot_c,
-                                                    const int32_t *__restrict__ total, int m, int n, int n_pad, int p,
-                                                    const CT *__restrict__ C, const WT *__restrict__ W,
-                                                    double *__restrict__ tbuf)
+__device__ __forceinline__ void canon_cols_body(const int32_t *__restrict__ hubs, const uint16_t *__restrict__ kidx,
+                                                const int32_t *__restrict__ cand, const int32_t *__restrict__ slot_r,
+                                                const int32_t *__restrict__ slot_c,
+                                                const int32_t *__restrict__ total, int m, int n, int n_pad, int p,
+                                                const CT *__restrict__ C, const WT *__restrict__ W,
+                                                double *__restrict__ tbuf, char *smem, int blk, int nblk)
 {
 #pragma clang fp contract(off)
-    extern __shared__ __align__(16) char smem[];
     double *Ch = (double *)smem;
     double *tile = Ch + (size_t)p * p;                        // products [row][col]
     uint16_t *kid = (uint16_t *)(tile + kCanonRows * kCanonCols);
@@ -179,7 +178,7 @@ __global__ __launch_bounds__(256) void k_canon_cols(const int32_t *__restrict__ 
     const int items = *total * nchunks;
     constexpr int PER = kCanonRows * kCanonCols / 256;   // tile elements per thread
     const int nb = (n + kCanonRows - 1) / kCanonRows;
-    for (int item = blockIdx.x; item < items; item += gridDim.x) {
+    for (int item = blk; item < items; item += nblk) {
         const int slot = item / nchunks, chunk = item % nchunks;
         const int r = slot_r[slot], c = slot_c[slot];
         const int s = cand[(size_t)r * m + c];
@@ -246,22 +245,21 @@ __global__ __launch_bounds__(256) void k_canon_cols(const int32_t *__restrict__ 
     }
 }
 
+// Workgroup blk of nblk of a context (LDS: canon_sums_smem).
 template <typename CT, typename WT>
-__global__ __launch_bounds__(256) void k_canon_sums(SelState S, const int32_t *__restrict__ kidx,
-                                                    const int32_t *__restrict__ slot_r,
-                                                    const int32_t *__restrict__ slot_c,
-                                                    const int32_t *__restrict__ total,
-                                                    const int32_t *__restrict__ extra_r,
-                                                    const int32_t *__restrict__ extra_c,
-                                                    const int32_t *__restrict__ nextra, int n, int n_pad,
-                                                    const CT *__restrict__ C, const WT *__restrict__ W,
-                                                    const double *__restrict__ O, const double *__restrict__ D,
-                                                    const double *__restrict__ tbuf, double chi, double alpha,
-                                                    double delta, double scale, double *__restrict__ cand_cost,
-                                                    double *__restrict__ cand_parts)
+__device__ __forceinline__ void canon_sums_body(const SelState &S, const int32_t *__restrict__ kidx,
+                                                const int32_t *__restrict__ slot_r, const int32_t *__restrict__ slot_c,
+                                                const int32_t *__restrict__ total,
+                                                const int32_t *__restrict__ extra_r,
+                                                const int32_t *__restrict__ extra_c,
+                                                const int32_t *__restrict__ nextra, int n, int n_pad,
+                                                const CT *__restrict__ C, const WT *__restrict__ W,
+                                                const double *__restrict__ O, const double *__restrict__ D,
+                                                const double *__restrict__ tbuf, double chi, double alpha,
+                                                double delta, double scale, double *__restrict__ cand_cost,
+                                                double *__restrict__ cand_parts, char *smem, int blk, int nblk)
 {
 #pragma clang fp contract(off)
-    extern __shared__ __align__(16) char smem[];
     double *bufA = (double *)smem, *bufB = bufA + n;
     __shared__ int h[kMaxP];
     __shared__ double sh_cc;
@@ -269,7 +267,7 @@ __global__ __launch_bounds__(256) void k_canon_sums(SelState S, const int32_t *_
     const int p = S.p, m = S.m;
     const uint16_t *kid16 = (const uint16_t *)kidx;
     const int tot = *total;
-    for (int slot = blockIdx.x; slot < tot; slot += gridDim.x) {
+    for (int slot = blk; slot < tot; slot += nblk) {
         const int r = slot_r[slot], c = slot_c[slot];
         const int s = S.cand[(size_t)r * m + c];
         __syncthreads();
@@ -299,7 +297,7 @@ __global__ __launch_bounds__(256) void k_canon_sums(SelState S, const int32_t *_
     }
     // candidates beyond the slots: evaluated whole, one workgroup each
     const int ne = *nextra;
-    for (int e = blockIdx.x; e < ne; e += gridDim.x) {
+    for (int e = blk; e < ne; e += nblk) {
         const int r = extra_r[e], c = extra_c[e];
         const int s = S.cand[(size_t)r * m + c];
         __syncthreads();
@@ -311,11 +309,106 @@ __global__ __launch_bounds__(256) void k_canon_sums(SelState S, const int32_t *_
 
 // Island decisions on exact costs, one workgroup per island; the last
 // workgroup ends the generation (global step, best so far, g + 1).
+__device__ __forceinline__ void select2_body(const SelState &S, int *__restrict__ sync, int blk, int nblk)
+{
+    select_island_exact(S, blk);
+    if (!last_block(sync, nblk)) return;
+    global_step(S);
+}
+
+template <typename CT, typename WT>
+__global__ __launch_bounds__(256) void k_canon_cols(const int32_t *__restrict__ hubs,
+                                                    const uint16_t *__restrict__ kidx,
+                                                    const int32_t *__restrict__ cand, const int32_t *__restrict__ slot_r,
+                                                    const int32_t *__restrict__ slot_c,
+                                                    const int32_t *__restrict__ total, int m, int n, int n_pad, int p,
+                                                    const CT *__restrict__ C, const WT *__restrict__ W,
+                                                    double *__restrict__ tbuf)
+{
+    extern __shared__ __align__(16) char smem[];
+    canon_cols_body<CT, WT>(hubs, kidx, cand, slot_r, slot_c, total, m, n, n_pad, p, C, W, tbuf, smem, blockIdx.x,
+                            gridDim.x);
+}
+
+template <typename CT, typename WT>
+__global__ __launch_bounds__(256) void k_canon_sums(SelState S, const int32_t *__restrict__ kidx,
+                                                    const int32_t *__restrict__ slot_r,
+                                                    const int32_t *__restrict__ slot_c,
+                                                    const int32_t *__restrict__ total,
+                                                    const int32_t *__restrict__ extra_r,
+                                                    const int32_t *__restrict__ extra_c,
+                                                    const int32_t *__restrict__ nextra, int n, int n_pad,
+                                                    const CT *__restrict__ C, const WT *__restrict__ W,
+                                                    const double *__restrict__ O, const double *__restrict__ D,
+                                                    const double *__restrict__ tbuf, double chi, double alpha,
+                                                    double delta, double scale, double *__restrict__ cand_cost,
+                                                    double *__restrict__ cand_parts)
+{
+    extern __shared__ __align__(16) char smem[];
+    canon_sums_body<CT, WT>(S, kidx, slot_r, slot_c, total, extra_r, extra_c, nextra, n, n_pad, C, W, O, D, tbuf,
+                            chi, alpha, delta, scale, cand_cost, cand_parts, smem, blockIdx.x, gridDim.x);
+}
+
 __global__ __launch_bounds__(256) void k_select2(SelState S, int *__restrict__ sync)
 {
-    select_island_exact(S, blockIdx.x);
-    if (!last_block(sync, gridDim.x)) return;
-    global_step(S);
+    select2_body(S, sync, blockIdx.x, gridDim.x);
+}
+
+// Grouped re-evaluation and decisions (split-bf16 generations of several
+// contexts); each context runs its own persistent share of the grid.
+template <typename CT, typename WT>
+__device__ __forceinline__ void cols_job(const TickJob &J, char *smem, int blk)
+{
+    const DevPtrs &P = J.P;
+    const Dims &d = J.d;
+    canon_cols_body<CT, WT>(P.hubs, P.kidx, P.cand, P.slot_r, P.slot_c, P.total, d.m, d.n, d.n_pad, d.p,
+                            (const CT *)P.C, (const WT *)P.W, P.tbuf, smem, blk, J.blocks[kTickCols]);
+}
+
+__global__ __launch_bounds__(256) void k_canon_cols_group(const TickJob *__restrict__ jobs, int njobs)
+{
+    extern __shared__ __align__(16) char smem[];
+    const TickJob &J = jobs[tick_job(jobs, njobs, kTickCols, blockIdx.x)];
+    const int blk = blockIdx.x - J.start[kTickCols];
+    if (J.d.c_f32) {
+        if (J.d.w_f32) cols_job<float, float>(J, smem, blk);
+        else cols_job<float, double>(J, smem, blk);
+    } else {
+        if (J.d.w_f32) cols_job<double, float>(J, smem, blk);
+        else cols_job<double, double>(J, smem, blk);
+    }
+}
+
+template <typename CT, typename WT>
+__device__ __forceinline__ void sums_job(const TickJob &J, char *smem, int blk)
+{
+    const DevPtrs &P = J.P;
+    const Dims &d = J.d;
+    const SelState S = make_sel_state(P, d);
+    canon_sums_body<CT, WT>(S, (const int32_t *)P.kidx, P.slot_r, P.slot_c, P.total, P.extra_r, P.extra_c, P.nextra,
+                            d.n, d.n_pad, (const CT *)P.C, (const WT *)P.W, P.O, P.D, P.tbuf, d.chi, d.alpha,
+                            d.delta, d.scale, P.cand_cost, P.cand_parts, smem, blk, J.blocks[kTickSums]);
+}
+
+__global__ __launch_bounds__(256) void k_canon_sums_group(const TickJob *__restrict__ jobs, int njobs)
+{
+    extern __shared__ __align__(16) char smem[];
+    const TickJob &J = jobs[tick_job(jobs, njobs, kTickSums, blockIdx.x)];
+    const int blk = blockIdx.x - J.start[kTickSums];
+    if (J.d.c_f32) {
+        if (J.d.w_f32) sums_job<float, float>(J, smem, blk);
+        else sums_job<float, double>(J, smem, blk);
+    } else {
+        if (J.d.w_f32) sums_job<double, float>(J, smem, blk);
+        else sums_job<double, double>(J, smem, blk);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_select2_group(const TickJob *__restrict__ jobs, int njobs)
+{
+    const TickJob &J = jobs[tick_job(jobs, njobs, kTickSel2, blockIdx.x)];
+    const SelState S = make_sel_state(J.P, J.d);
+    select2_body(S, J.P.sync + 1, blockIdx.x - J.start[kTickSel2], J.blocks[kTickSel2]);
 }
 
 // ------------------------------------------------------------- FP32 --
@@ -436,6 +529,22 @@ hipError_t launch_recheck(const DevPtrs &P, const Dims &d, const SelState &S, hi
     return recheck_launch<double, double>(P, d, S, st);
 }
 
+size_t recheck_lds_cols(int n, int p) { return canon_cols_smem(n, p); }
+size_t recheck_lds_sums(int n, int p) { return std::max((size_t)16 * n, exact_smem_bytes(n, p)); }
+
+hipError_t launch_recheck_group(const TickJob *jobs, int njobs, const int *blocks, size_t lds_cols, size_t lds_sums,
+                                hipStream_t st)
+{
+    if (njobs <= 0) return hipSuccess;
+    hipError_t e;
+    k_canon_cols_group<<<blocks[kTickCols], 256, lds_cols, st>>>(jobs, njobs);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_canon_sums_group<<<blocks[kTickSums], 256, lds_sums, st>>>(jobs, njobs);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_select2_group<<<blocks[kTickSel2], 256, 0, st>>>(jobs, njobs);
+    return hipGetLastError();
+}
+
 double fp32_eps_bound(int n)
 {
     return gamma_k(n + 2.0, kU32) + gamma_k(2.0 * n + 16.0, kU64);
@@ -462,6 +571,10 @@ hipError_t launch_eval_fp32(const DevPtrs &P, const Dims &d, const int32_t *hubs
 
 // Raise the dynamic-LDS cap of every kernel here that may need more than the
 // default, once per process (never during graph capture).
+static size_t g_group_lds_cap[2] = {0, 0};   // dynamic LDS limits of the grouped re-evaluation kernels
+
+size_t recheck_group_lds_cap(int which) { return g_group_lds_cap[which ? 1 : 0]; }
+
 hipError_t prepare_plain_kernels(int max_lds)
 {
     const void *fns[] = {(const void *)k_eval_exact<double, double>, (const void *)k_eval_exact<double, float>,
@@ -470,7 +583,8 @@ hipError_t prepare_plain_kernels(int max_lds)
                          (const void *)k_canon_cols<float, double>,  (const void *)k_canon_cols<float, float>,
                          (const void *)k_canon_sums<double, double>, (const void *)k_canon_sums<double, float>,
                          (const void *)k_canon_sums<float, double>,  (const void *)k_canon_sums<float, float>,
-                         (const void *)k_eval_fp32<double>,          (const void *)k_eval_fp32<float>};
+                         (const void *)k_eval_fp32<double>,          (const void *)k_eval_fp32<float>,
+                         (const void *)k_canon_cols_group,           (const void *)k_canon_sums_group};
     for (const void *f : fns) {
         hipFuncAttributes fa;
         hipError_t e = hipFuncGetAttributes(&fa, f);
@@ -478,6 +592,8 @@ hipError_t prepare_plain_kernels(int max_lds)
         const int dyn = max_lds - (int)fa.sharedSizeBytes;   // the cap excludes the kernel's static LDS
         e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
         if (e != hipSuccess) return e;
+        if (f == (const void *)k_canon_cols_group) g_group_lds_cap[0] = (size_t)dyn;
+        if (f == (const void *)k_canon_sums_group) g_group_lds_cap[1] = (size_t)dyn;
     }
     return hipSuccess;
 }

@@ -69,13 +69,14 @@ __device__ __forceinline__ void wave_swap(int n, WList &x, int &cnt, uint64_t w_
 
 }  // namespace
 
-__global__ __launch_bounds__(256) void k_ga_ops(const int32_t *__restrict__ anc, int32_t *__restrict__ children,
-                                                const int64_t *__restrict__ gen, int n, int p, int S, int m,
-                                                uint64_t seed)
+// Workgroup blk of a context: children 4*blk .. 4*blk+3, one per wave.
+__device__ __forceinline__ void ga_ops_body(const int32_t *__restrict__ anc, int32_t *__restrict__ children,
+                                            const int64_t *__restrict__ gen, int n, int p, int S, int m,
+                                            uint64_t seed, int blk)
 {
     __shared__ int lists[4][3][128];   // per wave: parent a, parent b, child
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int s = blockIdx.x * 4 + wave;
+    const int s = blk * 4 + wave;
     if (s >= S) return;
     const uint64_t g = (uint64_t)*gen;
     WList pa{lists[wave][0]}, pb{lists[wave][1]}, cx{lists[wave][2]};
@@ -123,9 +124,31 @@ __global__ __launch_bounds__(256) void k_ga_ops(const int32_t *__restrict__ anc,
     if (lane < p) children[(size_t)s * p + lane] = cx.a[lane];
 }
 
+__global__ __launch_bounds__(256) void k_ga_ops(const int32_t *__restrict__ anc, int32_t *__restrict__ children,
+                                                const int64_t *__restrict__ gen, int n, int p, int S, int m,
+                                                uint64_t seed)
+{
+    ga_ops_body(anc, children, gen, n, p, S, m, seed, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_ga_ops_group(const TickJob *__restrict__ jobs, int njobs)
+{
+    const TickJob &J = jobs[tick_job(jobs, njobs, kTickOps, blockIdx.x)];
+    ga_ops_body(J.P.anc, J.P.hubs, J.P.gen, J.d.n, J.d.p, J.d.S, J.d.m, J.d.seed, blockIdx.x - J.start[kTickOps]);
+}
+
+int ga_ops_blocks(const Dims &d) { return (d.S + 3) / 4; }
+
 hipError_t launch_ga_ops(const DevPtrs &P, const Dims &d, hipStream_t st)
 {
-    k_ga_ops<<<(d.S + 3) / 4, 256, 0, st>>>(P.anc, P.hubs, P.gen, d.n, d.p, d.S, d.m, d.seed);
+    k_ga_ops<<<ga_ops_blocks(d), 256, 0, st>>>(P.anc, P.hubs, P.gen, d.n, d.p, d.S, d.m, d.seed);
+    return hipGetLastError();
+}
+
+hipError_t launch_ga_ops_group(const TickJob *jobs, int njobs, int blocks, hipStream_t st)
+{
+    if (njobs <= 0 || blocks <= 0) return hipSuccess;
+    k_ga_ops_group<<<blocks, 256, 0, st>>>(jobs, njobs);
     return hipGetLastError();
 }
 

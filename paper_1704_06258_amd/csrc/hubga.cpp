@@ -171,24 +171,28 @@ struct ga_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     bool graph_failed = false;
-    // the two halves of a generation around a grouped matrix-core launch,
-    // captured for one grouping (grouped_cfg, or -1 for not grouped)
-    hipGraphExec_t pre_exec = nullptr, post_exec = nullptr;
-    int halves_cfg = -2;
 };
 
 struct ga_batch {
     hipStream_t st = nullptr;
     int cfg = 7;
     std::vector<ga_ctx *> ctxs;
-    std::vector<char> grouped;
+    std::vector<ga_ctx *> solo;      // stepped by their own generation on side streams
     std::vector<hipStream_t> side;
-    std::vector<hipEvent_t> ev;      // fork/join events
-    void *d_jobs = nullptr;          // device job table of the grouped launch
-    void *h_jobs = nullptr;          // pinned staging of the job table
-    size_t jobs_cap = 0;
-    hipEvent_t jobs_copied = nullptr;
-    int njobs = 0, total_tiles = 0, min_p = 0;
+    std::vector<hipEvent_t> ev;      // [0] fork, [1 + k] join of side stream k
+    // grouped contexts: matrix-core job table, then the TickJob table.  The
+    // device table is rewritten in stream order; its host staging is a ring of
+    // pinned buffers, so a recomposition waits only for a copy kStageRing
+    // recompositions old.
+    static constexpr int kStageRing = 8;
+    void *d_tab = nullptr;
+    void *h_tab[kStageRing] = {};
+    hipEvent_t tab_copied[kStageRing] = {};
+    int stage = 0;
+    size_t tab_cap = 0, tick_off = 0;
+    int njobs = 0, total_tiles = 0, min_p = 0, sel_threads = 64;
+    int blocks[kTickPhases] = {};
+    size_t lds_cols = 0, lds_sums = 0;
 };
 
 namespace {
@@ -256,36 +260,19 @@ ga_status run_eval(ga_ctx *ctx, const int32_t *hubs, int count, uint16_t *kidx)
     return run_eval(ctx, hubs, count, kidx, ctx->st);
 }
 
-// A generation in two halves around the batched evaluation.  With `grouped`
-// the matrix-core product is left to a grouped launch over several contexts.
-ga_status gen_pre(ga_ctx *ctx, hipStream_t s, bool grouped)
+// One generation on stream s: operators, evaluation, selection.
+ga_status run_generation(ga_ctx *ctx, hipStream_t s)
 {
     const Dims &d = ctx->d;
     const DevPtrs &P = ctx->P;
     HIPCHK(launch_ga_ops(P, d, s));
-    if (grouped) {
-        HIPCHK(launch_alloc(P, d, P.hubs, d.S, P.kidx, 1, 1, s));
-        return GA_OK;
-    }
-    return run_eval(ctx, P.hubs, d.S, P.kidx, s);
-}
-
-ga_status gen_post(ga_ctx *ctx, hipStream_t s, bool grouped, int group_cfg)
-{
-    const Dims &d = ctx->d;
-    const DevPtrs &P = ctx->P;
-    const int exact = d.prec == kFP64;
-    if (grouped) HIPCHK(launch_finalize(P, d, d.S, group_cfg, s));
-    HIPCHK(launch_select(P, d, exact, s));
+    ga_status st = run_eval(ctx, P.hubs, d.S, P.kidx, s);
+    if (st != GA_OK) return st;
+    HIPCHK(launch_select(P, d, d.prec == kFP64, s));
     return GA_OK;
 }
 
-ga_status run_generation(ga_ctx *ctx)
-{
-    ga_status st = gen_pre(ctx, ctx->st, false);
-    if (st != GA_OK) return st;
-    return gen_post(ctx, ctx->st, false, 0);
-}
+ga_status run_generation(ga_ctx *ctx) { return run_generation(ctx, ctx->st); }
 
 void drop_graph(ga_ctx *ctx)
 {
@@ -816,47 +803,6 @@ ga_status ga_set_tile_config(ga_ctx *ctx, int32_t cfg)
 
 // ------------------------------------------------------------- batches --
 
-static void drop_halves(ga_ctx *ctx)
-{
-    if (ctx->pre_exec) (void)hipGraphExecDestroy(ctx->pre_exec);
-    if (ctx->post_exec) (void)hipGraphExecDestroy(ctx->post_exec);
-    ctx->pre_exec = ctx->post_exec = nullptr;
-    ctx->halves_cfg = -2;
-}
-
-// Capture one half of a generation of ctx on its stream as an executable graph.
-template <typename F>
-static hipError_t capture_half(ga_ctx *ctx, F &&body, hipGraphExec_t *out)
-{
-    hipError_t e = hipStreamBeginCapture(ctx->st, hipStreamCaptureModeRelaxed);
-    if (e != hipSuccess) return e;
-    ga_status gs = body();
-    hipGraph_t g = nullptr;
-    e = hipStreamEndCapture(ctx->st, &g);
-    if (gs != GA_OK || e != hipSuccess || !g) {
-        if (g) (void)hipGraphDestroy(g);
-        (void)hipGetLastError();
-        ctx->poisoned = false;
-        return e != hipSuccess ? e : hipErrorUnknown;
-    }
-    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    return e;
-}
-
-static hipError_t ensure_halves(ga_ctx *ctx, int group_cfg)
-{
-    if (ctx->halves_cfg == group_cfg && ctx->pre_exec && ctx->post_exec) return hipSuccess;
-    drop_halves(ctx);
-    const bool grouped = group_cfg >= 0;
-    hipError_t e = capture_half(ctx, [&] { return gen_pre(ctx, ctx->st, grouped); }, &ctx->pre_exec);
-    if (e != hipSuccess) return e;
-    e = capture_half(ctx, [&] { return gen_post(ctx, ctx->st, grouped, group_cfg); }, &ctx->post_exec);
-    if (e != hipSuccess) return e;
-    ctx->halves_cfg = group_cfg;
-    return hipSuccess;
-}
-
 extern "C" {
 
 ga_status ga_batch_create(void *hip_stream, int32_t tile_config, ga_batch **out)
@@ -870,10 +816,11 @@ ga_status ga_batch_create(void *hip_stream, int32_t tile_config, ga_batch **out)
     if (!b) return fail(nullptr, GA_ERR_OOM, "host allocation failed");
     b->st = (hipStream_t)hip_stream;
     b->cfg = tile_config;
-    if (hipEventCreateWithFlags(&b->jobs_copied, hipEventDisableTiming) != hipSuccess) {
-        delete b;
-        return fail(nullptr, GA_ERR_DEVICE, "event");
-    }
+    for (auto &ev : b->tab_copied)
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+            ga_batch_free(b);
+            return fail(nullptr, GA_ERR_DEVICE, "event");
+        }
     *out = b;
     return GA_OK;
 }
@@ -889,101 +836,159 @@ ga_status ga_batch_set(ga_batch *b, ga_ctx *const *ctxs, int32_t count)
             if (ctxs[k] == ctxs[i]) return fail(nullptr, GA_ERR_INVALID, "context listed twice");
     }
     hipError_t e;
-    // per-context halves (captured once per context and grouping)
-    std::vector<char> grouped(count, 0);
+    // split-bf16 contexts whose hub count the tile configuration takes are
+    // grouped; the others step alone (their own generation graph) beside them
+    std::vector<ga_ctx *> grouped, solo;
     for (int i = 0; i < count; ++i) {
-        grouped[i] = ctxs[i]->d.prec == kSplitBF16 && mfma_groupable(ctxs[i]->d, b->cfg);
-        if ((e = ensure_halves(ctxs[i], grouped[i] ? b->cfg : -1)) != hipSuccess)
-            return fail(nullptr, GA_ERR_DEVICE, std::string("capture: ") + hipGetErrorString(e));
+        ga_ctx *c = ctxs[i];
+        if (c->d.prec == kSplitBF16 && mfma_groupable(c->d, b->cfg))
+            grouped.push_back(c);
+        else
+            solo.push_back(c);
     }
-    // grouped job table, copied in stream order after earlier generations
+    for (ga_ctx *c : solo)
+        if (!c->gexec && !c->prof_on) (void)capture_generation(c);
+    const int njobs = (int)grouped.size();
     std::vector<const DevPtrs *> P;
     std::vector<const Dims *> D;
-    int min_p = 1 << 30;
-    for (int i = 0; i < count; ++i)
-        if (grouped[i]) {
-            P.push_back(&ctxs[i]->P);
-            D.push_back(&ctxs[i]->d);
-            min_p = std::min(min_p, ctxs[i]->d.p);
+    std::vector<TickJob> tj(njobs);
+    int min_p = 1 << 30, sel_threads = 64;
+    int blocks[kTickPhases] = {};
+    size_t lds_cols = 0, lds_sums = 0;
+    for (int j = 0; j < njobs; ++j) {
+        const ga_ctx *c = grouped[j];
+        const Dims &d = c->d;
+        P.push_back(&c->P);
+        D.push_back(&c->d);
+        min_p = std::min(min_p, d.p);
+        sel_threads = std::max(sel_threads, select_threads(d.m));
+        lds_cols = std::max(lds_cols, recheck_lds_cols(d.n, d.p));
+        lds_sums = std::max(lds_sums, recheck_lds_sums(d.n, d.p));
+        TickJob &J = tj[j];
+        memset(&J, 0, sizeof(J));
+        J.P = c->P;
+        J.d = d;
+        J.n_mt = mfma_partial_tiles(d, b->cfg);
+        J.blocks[kTickOps] = ga_ops_blocks(d);
+        J.blocks[kTickAlloc] = alloc_blocks(d.S);   // a multiple of 8: every context starts on XCD 0
+        J.blocks[kTickFinal] = finalize_blocks(d.S);
+        J.blocks[kTickSel1] = d.R;
+        J.blocks[kTickCols] = kTickColsBlocks;
+        J.blocks[kTickSums] = kTickSumsBlocks;
+        J.blocks[kTickSel2] = d.R;
+        for (int q = 0; q < kTickPhases; ++q) {
+            J.start[q] = blocks[q];
+            blocks[q] += J.blocks[q];
         }
-    const int njobs = (int)P.size();
-    const size_t bytes = mfma_job_bytes() * std::max(1, njobs);
-    if ((e = hipEventSynchronize(b->jobs_copied)) != hipSuccess)
-        return fail(nullptr, GA_ERR_DEVICE, hipGetErrorString(e));
-    if (bytes > b->jobs_cap) {
+    }
+    if (njobs && (lds_cols > recheck_group_lds_cap(0) || lds_sums > recheck_group_lds_cap(1)))
+        return fail(nullptr, GA_ERR_INVALID, "batch: re-evaluation LDS exceeds the device limit");
+    // tables, copied in stream order after earlier generations
+    const size_t mbytes = ((mfma_job_bytes() * std::max(1, njobs)) + 255) & ~(size_t)255;
+    const size_t bytes = mbytes + sizeof(TickJob) * std::max(1, njobs);
+    if (bytes > b->tab_cap) {
         if ((e = hipStreamSynchronize(b->st)) != hipSuccess) return fail(nullptr, GA_ERR_DEVICE, hipGetErrorString(e));
-        if (b->d_jobs) (void)hipFree(b->d_jobs);
-        if (b->h_jobs) (void)hipHostFree(b->h_jobs);
-        b->d_jobs = b->h_jobs = nullptr;
-        const size_t cap = std::max(bytes * 2, mfma_job_bytes() * 64);
-        if (hipMalloc(&b->d_jobs, cap) != hipSuccess || hipHostMalloc(&b->h_jobs, cap, 0) != hipSuccess)
-            return fail(nullptr, GA_ERR_OOM, "job table");
-        b->jobs_cap = cap;
+        if (b->d_tab) (void)hipFree(b->d_tab);
+        b->d_tab = nullptr;
+        for (auto &h : b->h_tab) {
+            if (h) (void)hipHostFree(h);
+            h = nullptr;
+        }
+        b->tab_cap = 0;
+        const size_t cap = std::max(bytes * 2, (size_t)64 * (mfma_job_bytes() + sizeof(TickJob)) + 256);
+        if (hipMalloc(&b->d_tab, cap) != hipSuccess) return fail(nullptr, GA_ERR_OOM, "job table");
+        for (auto &h : b->h_tab)
+            if (hipHostMalloc(&h, cap, 0) != hipSuccess) return fail(nullptr, GA_ERR_OOM, "job table staging");
+        b->tab_cap = cap;
     }
-    b->total_tiles = njobs ? mfma_fill_jobs(P.data(), D.data(), njobs, b->cfg, b->h_jobs) : 0;
     if (njobs) {
-        if ((e = hipMemcpyAsync(b->d_jobs, b->h_jobs, bytes, hipMemcpyHostToDevice, b->st)) != hipSuccess)
+        const int k = b->stage;
+        b->stage = (k + 1) % ga_batch::kStageRing;
+        if ((e = hipEventSynchronize(b->tab_copied[k])) != hipSuccess)   // this staging buffer's last copy
             return fail(nullptr, GA_ERR_DEVICE, hipGetErrorString(e));
-        if ((e = hipEventRecord(b->jobs_copied, b->st)) != hipSuccess)
+        b->total_tiles = mfma_fill_jobs(P.data(), D.data(), njobs, b->cfg, b->h_tab[k]);
+        memcpy((char *)b->h_tab[k] + mbytes, tj.data(), sizeof(TickJob) * njobs);
+        if ((e = hipMemcpyAsync(b->d_tab, b->h_tab[k], bytes, hipMemcpyHostToDevice, b->st)) != hipSuccess)
             return fail(nullptr, GA_ERR_DEVICE, hipGetErrorString(e));
+        if ((e = hipEventRecord(b->tab_copied[k], b->st)) != hipSuccess)
+            return fail(nullptr, GA_ERR_DEVICE, hipGetErrorString(e));
+    } else {
+        b->total_tiles = 0;
     }
+    b->tick_off = mbytes;
     b->njobs = njobs;
     b->min_p = min_p;
-    // side streams (default priority) for the per-context branches
-    const int nside = std::min(std::max(count, 1), 16);
+    b->sel_threads = sel_threads;
+    b->lds_cols = lds_cols;
+    b->lds_sums = lds_sums;
+    memcpy(b->blocks, blocks, sizeof(blocks));
+    // side streams (default priority) for the contexts stepped alone
+    const int nside = std::min((int)solo.size(), 16);
     while ((int)b->side.size() < nside) {
         hipStream_t s2;
         if ((e = hipStreamCreateWithFlags(&s2, hipStreamNonBlocking)) != hipSuccess)
             return fail(nullptr, GA_ERR_DEVICE, hipGetErrorString(e));
         b->side.push_back(s2);
     }
-    while ((int)b->ev.size() < 2 * 16 + 2) {
+    while ((int)b->ev.size() < 1 + 16) {
         hipEvent_t ev;
         if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess)
             return fail(nullptr, GA_ERR_DEVICE, hipGetErrorString(e));
         b->ev.push_back(ev);
     }
     b->ctxs.assign(ctxs, ctxs + count);
-    b->grouped = grouped;
+    b->solo = solo;
     return GA_OK;
 }
 
 ga_status ga_batch_step(ga_batch *b, int32_t generations)
 {
     if (!b || generations < 0) return GA_ERR_INVALID;
-    const int count = (int)b->ctxs.size();
-    if (count == 0 || generations == 0) return GA_OK;
-    const int nside = std::min(count, (int)b->side.size());
+    if (b->ctxs.empty() || generations == 0) return GA_OK;
+    const int nsolo = (int)b->solo.size();
+    const int nside = std::min(nsolo, (int)b->side.size());
     auto dev_fail = [&](hipError_t e, const char *what) {
         for (auto *c : b->ctxs) c->poisoned = true;
         return fail(nullptr, GA_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
     };
+    const void *mjobs = b->d_tab;
+    const TickJob *tjobs = (const TickJob *)((char *)b->d_tab + b->tick_off);
+    const int nj = b->njobs;
     hipError_t e;
     for (int g = 0; g < generations; ++g) {
-        // fork: every branch starts after the previous generation
-        if ((e = hipEventRecord(b->ev[0], b->st)) != hipSuccess) return dev_fail(e, "fork");
-        for (int k = 0; k < nside; ++k)
-            if ((e = hipStreamWaitEvent(b->side[k], b->ev[0], 0)) != hipSuccess) return dev_fail(e, "fork wait");
-        for (int i = 0; i < count; ++i)
-            if ((e = hipGraphLaunch(b->ctxs[i]->pre_exec, b->side[i % nside])) != hipSuccess)
-                return dev_fail(e, "pre");
-        for (int k = 0; k < nside; ++k) {
-            if ((e = hipEventRecord(b->ev[2 + k], b->side[k])) != hipSuccess) return dev_fail(e, "join");
-            if ((e = hipStreamWaitEvent(b->st, b->ev[2 + k], 0)) != hipSuccess) return dev_fail(e, "join wait");
+        if (nsolo) {   // fork: every alone-stepped context starts after the previous generation
+            if ((e = hipEventRecord(b->ev[0], b->st)) != hipSuccess) return dev_fail(e, "fork");
+            for (int k = 0; k < nside; ++k)
+                if ((e = hipStreamWaitEvent(b->side[k], b->ev[0], 0)) != hipSuccess) return dev_fail(e, "fork wait");
+            for (int i = 0; i < nsolo; ++i) {
+                ga_ctx *c = b->solo[i];
+                hipStream_t s2 = b->side[i % nside];
+                if (c->gexec) {
+                    if ((e = hipGraphLaunch(c->gexec, s2)) != hipSuccess) return dev_fail(e, "generation graph");
+                } else if (run_generation(c, s2) != GA_OK) {
+                    return dev_fail(hipErrorUnknown, "generation");
+                }
+            }
         }
-        if (b->njobs && (e = launch_mfma_group(b->d_jobs, b->njobs, b->total_tiles, b->cfg, b->min_p, b->st)) !=
-                            hipSuccess)
-            return dev_fail(e, "grouped launch");
-        if ((e = hipEventRecord(b->ev[1], b->st)) != hipSuccess) return dev_fail(e, "fork2");
-        for (int k = 0; k < nside; ++k)
-            if ((e = hipStreamWaitEvent(b->side[k], b->ev[1], 0)) != hipSuccess) return dev_fail(e, "fork2 wait");
-        for (int i = 0; i < count; ++i)
-            if ((e = hipGraphLaunch(b->ctxs[i]->post_exec, b->side[i % nside])) != hipSuccess)
-                return dev_fail(e, "post");
-        for (int k = 0; k < nside; ++k) {
-            if ((e = hipEventRecord(b->ev[2 + 16 + k], b->side[k])) != hipSuccess) return dev_fail(e, "join2");
-            if ((e = hipStreamWaitEvent(b->st, b->ev[2 + 16 + k], 0)) != hipSuccess) return dev_fail(e, "join2 wait");
+        if (nj) {
+            if ((e = launch_ga_ops_group(tjobs, nj, b->blocks[kTickOps], b->st)) != hipSuccess)
+                return dev_fail(e, "grouped operators");
+            if ((e = launch_alloc_group(tjobs, nj, b->blocks[kTickAlloc], b->st)) != hipSuccess)
+                return dev_fail(e, "grouped allocation");
+            if ((e = launch_mfma_group(mjobs, nj, b->total_tiles, b->cfg, b->min_p, b->st)) != hipSuccess)
+                return dev_fail(e, "grouped matrix-core evaluation");
+            if ((e = launch_finalize_group(tjobs, nj, b->blocks[kTickFinal], b->st)) != hipSuccess)
+                return dev_fail(e, "grouped cost assembly");
+            if ((e = launch_select1_group(tjobs, nj, b->blocks[kTickSel1], b->sel_threads, b->st)) != hipSuccess)
+                return dev_fail(e, "grouped selection");
+            if ((e = launch_recheck_group(tjobs, nj, b->blocks, b->lds_cols, b->lds_sums, b->st)) != hipSuccess)
+                return dev_fail(e, "grouped re-evaluation");
         }
+        if (nsolo)   // join
+            for (int k = 0; k < nside; ++k) {
+                if ((e = hipEventRecord(b->ev[1 + k], b->side[k])) != hipSuccess) return dev_fail(e, "join");
+                if ((e = hipStreamWaitEvent(b->st, b->ev[1 + k], 0)) != hipSuccess) return dev_fail(e, "join wait");
+            }
     }
     return GA_OK;
 }
@@ -995,9 +1000,11 @@ void ga_batch_free(ga_batch *b)
     for (auto s2 : b->side) (void)hipStreamSynchronize(s2);
     for (auto s2 : b->side) (void)hipStreamDestroy(s2);
     for (auto ev : b->ev) (void)hipEventDestroy(ev);
-    if (b->jobs_copied) (void)hipEventDestroy(b->jobs_copied);
-    if (b->d_jobs) (void)hipFree(b->d_jobs);
-    if (b->h_jobs) (void)hipHostFree(b->h_jobs);
+    for (auto ev : b->tab_copied)
+        if (ev) (void)hipEventDestroy(ev);
+    if (b->d_tab) (void)hipFree(b->d_tab);
+    for (auto h : b->h_tab)
+        if (h) (void)hipHostFree(h);
     delete b;
 }
 
@@ -1020,7 +1027,6 @@ void ga_free(ga_ctx *ctx)
     if (!ctx) return;
     (void)hipStreamSynchronize(ctx->st);
     drop_graph(ctx);
-    drop_halves(ctx);
     for (auto &e : ctx->ev) (void)hipEventDestroy(e);
     if (ctx->own_ws) (void)hipFree(ctx->ws);
     delete ctx;

@@ -13,6 +13,8 @@ hipError_t launch_middle_nodes(const DevPtrs &P, const Dims &d, int32_t *hubs_ou
 hipError_t launch_alloc(const DevPtrs &P, const Dims &d, const int32_t *hubs, int count, uint16_t *kidx,
                         int want_sums, int want_ch, hipStream_t st);
 hipError_t launch_copy_clamp(const int32_t *src, int32_t *dst, int total, int n, hipStream_t st);
+int alloc_blocks(int count);
+hipError_t launch_alloc_group(const TickJob *jobs, int njobs, int blocks, hipStream_t st);
 
 // per-individual evaluation (eval_plain.hip)
 hipError_t launch_eval_exact(const DevPtrs &P, const Dims &d, const int32_t *hubs, const uint16_t *kidx, int count,
@@ -21,6 +23,11 @@ hipError_t launch_eval_fp32(const DevPtrs &P, const Dims &d, const int32_t *hubs
                             hipStream_t st);
 hipError_t launch_recheck(const DevPtrs &P, const Dims &d, const SelState &S, hipStream_t st);
 double fp32_eps_bound(int n);
+size_t recheck_lds_cols(int n, int p);
+size_t recheck_lds_sums(int n, int p);
+size_t recheck_group_lds_cap(int which);   // 0: column sums, 1: candidate sums
+hipError_t launch_recheck_group(const TickJob *jobs, int njobs, const int *blocks, size_t lds_cols, size_t lds_sums,
+                                hipStream_t st);
 hipError_t prepare_plain_kernels(int max_lds);
 
 // batched matrix-core evaluation (eval_mfma.hip)
@@ -29,6 +36,8 @@ hipError_t launch_eval_split(const DevPtrs &P, const Dims &d, const uint16_t *ki
 hipError_t launch_mfma(const DevPtrs &P, const Dims &d, const uint16_t *kidx, int count, hipStream_t st);
 hipError_t launch_finalize(const DevPtrs &P, const Dims &d, int count, int cfg, hipStream_t st);
 int mfma_partial_tiles(const Dims &d, int cfg);
+int finalize_blocks(int count);
+hipError_t launch_finalize_group(const TickJob *jobs, int njobs, int blocks, hipStream_t st);
 bool mfma_groupable(const Dims &d, int cfg);
 size_t mfma_job_bytes();
 int mfma_fill_jobs(const DevPtrs *const *P, const Dims *const *d, int njobs, int cfg, void *jobs_host);
@@ -41,6 +50,10 @@ int mfma_k_tile(int cfg);
 
 // GA (ga_ops.hip, select.hip)
 hipError_t launch_ga_ops(const DevPtrs &P, const Dims &d, hipStream_t st);
+int ga_ops_blocks(const Dims &d);
+hipError_t launch_ga_ops_group(const TickJob *jobs, int njobs, int blocks, hipStream_t st);
+int select_threads(int m);
+hipError_t launch_select1_group(const TickJob *jobs, int njobs, int blocks, int threads, hipStream_t st);
 hipError_t launch_select(const DevPtrs &P, const Dims &d, int exact, hipStream_t st);
 hipError_t launch_init_state(const DevPtrs &P, const Dims &d, hipStream_t st);
 

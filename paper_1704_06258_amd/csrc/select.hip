@@ -76,18 +76,20 @@ __device__ inline void compact_candidates(const int32_t *__restrict__ cand_cnt, 
         }
 }
 
-__global__ __launch_bounds__(1024) void k_select1(SelState S, const double *__restrict__ cost,
-                                                  const double *__restrict__ eps, const double *__restrict__ parts,
-                                                  int32_t *__restrict__ cand, int32_t *__restrict__ cand_cnt, int tot,
-                                                  int32_t *__restrict__ slot_r, int32_t *__restrict__ slot_c,
-                                                  int32_t *__restrict__ handled, int32_t *__restrict__ total,
-                                                  int32_t *__restrict__ extra_r, int32_t *__restrict__ extra_c,
-                                                  int32_t *__restrict__ nextra, int *__restrict__ sync)
+// Island r = blk of a grid of nblk = R workgroups (block size: a power of two
+// >= m).
+__device__ __forceinline__ void select1_body(const SelState &S, const double *__restrict__ cost,
+                                             const double *__restrict__ eps, const double *__restrict__ parts,
+                                             int32_t *__restrict__ cand, int32_t *__restrict__ cand_cnt, int tot,
+                                             int32_t *__restrict__ slot_r, int32_t *__restrict__ slot_c,
+                                             int32_t *__restrict__ handled, int32_t *__restrict__ total,
+                                             int32_t *__restrict__ extra_r, int32_t *__restrict__ extra_c,
+                                             int32_t *__restrict__ nextra, int *__restrict__ sync, int blk, int nblk)
 {
     __shared__ int wave_cnt[16];
     __shared__ int sh_best;
     const int m = S.m, p = S.p;
-    const int r = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+    const int r = blk, tid = threadIdx.x, nt = blockDim.x;
     const int s = r * m + tid;
     const bool live = tid < m;
     const double fa = S.anc_cost[r];
@@ -153,11 +155,32 @@ __global__ __launch_bounds__(1024) void k_select1(SelState S, const double *__re
             cand_cnt[r] = tt;
         }
     }
-    if (!last_block(sync, gridDim.x)) return;
+    if (!last_block(sync, nblk)) return;
     if (S.exact)
         global_step(S);
     else
         compact_candidates(cand_cnt, S.R, tot, slot_r, slot_c, handled, total, extra_r, extra_c, nextra);
+}
+
+__global__ __launch_bounds__(1024) void k_select1(SelState S, const double *__restrict__ cost,
+                                                  const double *__restrict__ eps, const double *__restrict__ parts,
+                                                  int32_t *__restrict__ cand, int32_t *__restrict__ cand_cnt, int tot,
+                                                  int32_t *__restrict__ slot_r, int32_t *__restrict__ slot_c,
+                                                  int32_t *__restrict__ handled, int32_t *__restrict__ total,
+                                                  int32_t *__restrict__ extra_r, int32_t *__restrict__ extra_c,
+                                                  int32_t *__restrict__ nextra, int *__restrict__ sync)
+{
+    select1_body(S, cost, eps, parts, cand, cand_cnt, tot, slot_r, slot_c, handled, total, extra_r, extra_c, nextra,
+                 sync, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(1024) void k_select1_group(const TickJob *__restrict__ jobs, int njobs)
+{
+    const TickJob &J = jobs[tick_job(jobs, njobs, kTickSel1, blockIdx.x)];
+    const DevPtrs &P = J.P;
+    const SelState S = make_sel_state(P, J.d);
+    select1_body(S, P.cost, P.eps, P.parts, P.cand, P.cand_cnt, J.d.tot, P.slot_r, P.slot_c, P.handled, P.total,
+                 P.extra_r, P.extra_c, P.nextra, P.sync, blockIdx.x - J.start[kTickSel1], J.blocks[kTickSel1]);
 }
 
 // Every island ancestor <- the single solution in best / best_cost (the
@@ -188,43 +211,32 @@ hipError_t launch_init_state(const DevPtrs &P, const Dims &d, hipStream_t st)
     return hipGetLastError();
 }
 
-SelState make_sel_state(const DevPtrs &P, const Dims &d)
+
+int select_threads(int m)
 {
-    SelState S;
-    S.R = d.R;
-    S.m = d.m;
-    S.p = d.p;
-    S.S = d.S;
-    S.n1 = d.n1;
-    S.elitist = d.elitist;
-    S.exact = d.prec == kFP64;
-    S.children = P.hubs;
-    S.anc = P.anc;
-    S.anc_cost = P.anc_cost;
-    S.anc_parts = P.anc_parts;
-    S.best = P.best;
-    S.best_cost = P.best_cost;
-    S.gen = P.gen;
-    S.stats = P.stats;
-    S.cand = P.cand;
-    S.cand_cnt = P.cand_cnt;
-    S.cand_cost = P.cand_cost;
-    S.cand_parts = P.cand_parts;
-    return S;
+    int bt = 64;   // power of two for the tree reduction
+    while (bt < m) bt *= 2;
+    return bt;
 }
 
 // Selection and the end of the generation: k_select1 (with the global step
-// for exact costs), else k_select1 -> k_canon_cols -> k_canon_sums.
+// for exact costs), else k_select1 -> k_canon_cols -> k_canon_sums -> k_select2.
 hipError_t launch_select(const DevPtrs &P, const Dims &d, int exact, hipStream_t st)
 {
-    int bt = 64;   // power of two for the tree reduction
-    while (bt < d.m) bt *= 2;
+    const int bt = select_threads(d.m);
     const SelState S = make_sel_state(P, d);
     k_select1<<<d.R, bt, 0, st>>>(S, P.cost, P.eps, P.parts, P.cand, P.cand_cnt, d.tot, P.slot_r, P.slot_c,
                                   P.handled, P.total, P.extra_r, P.extra_c, P.nextra, P.sync);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || exact) return e;
     return launch_recheck(P, d, S, st);
+}
+
+hipError_t launch_select1_group(const TickJob *jobs, int njobs, int blocks, int threads, hipStream_t st)
+{
+    if (njobs <= 0 || blocks <= 0) return hipSuccess;
+    k_select1_group<<<blocks, threads, 0, st>>>(jobs, njobs);
+    return hipGetLastError();
 }
 
 }  // namespace hubga

@@ -88,6 +88,31 @@ struct SelState {
     const double *cand_cost, *cand_parts;
 };
 
+__host__ __device__ inline SelState make_sel_state(const DevPtrs &P, const Dims &d)
+{
+    SelState S;
+    S.R = d.R;
+    S.m = d.m;
+    S.p = d.p;
+    S.S = d.S;
+    S.n1 = d.n1;
+    S.elitist = d.elitist;
+    S.exact = d.prec == kFP64;
+    S.children = P.hubs;
+    S.anc = P.anc;
+    S.anc_cost = P.anc_cost;
+    S.anc_parts = P.anc_parts;
+    S.best = P.best;
+    S.best_cost = P.best_cost;
+    S.gen = P.gen;
+    S.stats = P.stats;
+    S.cand = P.cand;
+    S.cand_cnt = P.cand_cnt;
+    S.cand_cost = P.cand_cost;
+    S.cand_parts = P.cand_parts;
+    return S;
+}
+
 // Island r: the exactly re-evaluated candidates decide (ties to the lower
 // candidate, i.e. the lower child index); elitist mode keeps the ancestor
 // unless strictly beaten.

@@ -5,16 +5,18 @@ The server keeps every admitted request's instance, population and GA state
 resident on the GPU (one context each, in a workspace sized by
 ga_workspace_bytes).  Admission is FIFO: a waiting request is admitted while
 a slot is free and its workspace fits into the HBM budget next to the
-resident ones.  Every tick advances all resident requests by one generation
-in one replayed batch graph (ga_batch_*), with one grouped matrix-core launch
-for their populations.  Requests join and leave at generation boundaries;
-each result is exactly what the request would give alone.  Latency is
-measured from the scheduled arrival to the result on the host.
+resident and in-flight ones.  Every tick advances all resident requests by
+one generation (ga_batch_step): one launch per GA step over all their
+populations.  Requests join and leave at generation boundaries; each result
+is exactly what the request would give alone.  Latency is measured from the
+scheduled arrival to the result on the host.
 """
 from __future__ import annotations
 
 import collections
+import concurrent.futures
 import dataclasses
+import threading
 import time
 
 import numpy as np
@@ -75,7 +77,18 @@ def workspace_bytes(req: SolveRequest) -> int:
 
 
 class Server:
-    def __init__(self, hbm_budget: int = 16 << 30, max_slots: int = 32, tile_config: int = 7, device: int = 0):
+    """Continuous batching on one GPU.
+
+    The tick loop (this thread) only launches work: every tick is one batched
+    generation of all resident requests.  Building a request's context (copy
+    of C and W, preparation, evaluation of P0) runs on worker threads, each
+    with a stream of its own, and a finished request is read back and freed
+    on a worker too; contexts move between those streams and the batch stream
+    with ga_set_stream, which orders them by an event instead of a host wait.
+    So admissions and completions overlap the generations of the others."""
+
+    def __init__(self, hbm_budget: int = 16 << 30, max_slots: int = 64, tile_config: int = 7, device: int = 0,
+                 workers: int = 4):
         self.budget = int(hbm_budget)
         self.max_slots = int(max_slots)
         self.batch = hubga.Batch(device=device, tile_config=tile_config)
@@ -85,12 +98,40 @@ class Server:
         self.ticks = 0
         self.evaluations = 0
         self.max_resident = 0
+        self.workers = int(workers)
+        self._pool = concurrent.futures.ThreadPoolExecutor(self.workers) if self.workers > 0 else None
+        self._local = threading.local()
+        self._harvest = None
+
+    def _stream(self):
+        """This thread's side stream (None with a backend that has no streams)."""
+        if self.batch.stream is None:
+            return None
+        st = getattr(self._local, "stream", None)
+        if st is None:
+            import torch
+            st = self._local.stream = torch.cuda.Stream(torch.device("cuda", self.device))
+        return st
 
     def _admit(self, req: SolveRequest, now: float) -> _Job:
         solver = hubga.Solver(req.C, req.W, req.p, chi=req.chi, alpha=req.alpha, delta=req.delta, seed=req.seed,
                               population=req.population, island_size=min(req.island_size, req.population),
-                              n1=req.n1, precision=req.precision, stream=self.batch.stream, device=self.device)
+                              n1=req.n1, precision=req.precision, stream=self._stream(), device=self.device)
         return _Job(req, solver, solver.workspace_bytes, now)
+
+    def _finish(self, job: _Job, t0: float, clock) -> SolveResult:
+        b = job.solver.best()                  # waits for this request's last generation only
+        res = SolveResult(job.req.rid, b["hubs"], b["cost"], b["generation"], job.req.arrival, job.admitted,
+                          clock() - t0)
+        job.solver.close()
+        return res
+
+    def _submit(self, fn, *args):
+        if self._pool is None:
+            f = concurrent.futures.Future()
+            f.set_result(fn(*args))
+            return f
+        return self._pool.submit(fn, *args)
 
     def run(self, requests, realtime: bool = True, clock=time.perf_counter):
         """Serve ``requests`` (sorted by arrival).  With ``realtime`` arrivals
@@ -98,49 +139,71 @@ class Server:
         once (closed loop).  Returns the results in completion order."""
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
         waiting: collections.deque = collections.deque()
+        building: list = []                    # (future, bytes reserved)
+        finishing: list = []                   # (future, bytes held)
         results: list[SolveResult] = []
+        if self.batch.stream is not None and self._harvest is None:
+            import torch
+            self._harvest = torch.cuda.Stream(torch.device("cuda", self.device))
         t0 = clock()
-        while pending or waiting or self.resident:
+        while pending or waiting or building or self.resident or finishing:
             now = clock() - t0
             while pending and (not realtime or pending[0].arrival <= now):
                 waiting.append(pending.popleft())
-            changed = False
-            while waiting and len(self.resident) < self.max_slots:
+            # FIFO admission by slots and HBM budget (building contexts hold both)
+            while waiting and len(self.resident) + len(building) < self.max_slots:
                 need = workspace_bytes(waiting[0])
                 if self.used + need > self.budget:
-                    if not self.resident:
+                    if not (self.resident or building or finishing):
                         raise MemoryError(f"request {waiting[0].rid} needs {need} bytes > budget {self.budget}")
                     break
                 req = waiting.popleft()
-                job = self._admit(req, clock() - t0)
-                self.resident.append(job)
-                self.used += job.nbytes
-                changed = True
+                self.used += need
+                building.append((self._submit(self._admit, req, clock() - t0), need))
+            # contexts built since the last tick join at this generation boundary
+            changed = False
+            still = []
+            for fut, need in building:
+                if fut.done():
+                    job = fut.result()
+                    job.nbytes = need
+                    if self.batch.stream is not None:
+                        job.solver.set_stream(self.batch.stream)
+                    self.resident.append(job)
+                    changed = True
+                else:
+                    still.append((fut, need))
+            building = still
             if changed:
                 self.batch.set([j.solver for j in self.resident])
                 self.max_resident = max(self.max_resident, len(self.resident))
-            if not self.resident:
-                if pending:
-                    delay = pending[0].arrival - (clock() - t0)
-                    if delay > 0:
-                        time.sleep(min(delay, 0.01))
-                continue
-            self.batch.step(1)
-            self.ticks += 1
-            for j in self.resident:
-                j.gens += 1
-                self.evaluations += j.req.population
-            done = [j for j in self.resident if j.gens >= j.req.generations]
-            if done:
-                for j in done:
-                    b = j.solver.best()          # waits for this request's generations
-                    results.append(SolveResult(j.req.rid, b["hubs"], b["cost"], b["generation"], j.req.arrival,
-                                               j.admitted, clock() - t0))
-                self.resident = [j for j in self.resident if j.gens < j.req.generations]
-                self.batch.set([j.solver for j in self.resident])
-                for j in done:                   # out of the batch before it is freed
-                    j.solver.close()
-                    self.used -= j.nbytes
+            if self.resident:
+                self.batch.step(1)
+                self.ticks += 1
+                for j in self.resident:
+                    j.gens += 1
+                    self.evaluations += j.req.population
+                done = [j for j in self.resident if j.gens >= j.req.generations]
+                if done:
+                    self.resident = [j for j in self.resident if j.gens < j.req.generations]
+                    self.batch.set([j.solver for j in self.resident])
+                    for j in done:             # out of the batch: read back and freed on a worker
+                        if self._harvest is not None:
+                            j.solver.set_stream(self._harvest)
+                        finishing.append((self._submit(self._finish, j, t0, clock), j.nbytes))
+            else:
+                delay = 0.0005 if (building or finishing) else (
+                    pending[0].arrival - (clock() - t0) if pending and realtime else 0.0)
+                if delay > 0:
+                    time.sleep(min(delay, 0.01))
+            still = []
+            for fut, nb in finishing:
+                if fut.done():
+                    results.append(fut.result())
+                    self.used -= nb
+                else:
+                    still.append((fut, nb))
+            finishing = still
         self.batch.synchronize()
         return results
 
@@ -148,6 +211,9 @@ class Server:
         for j in self.resident:
             j.solver.close()
         self.resident = []
+        if self._pool is not None:
+            self._pool.shutdown(wait=True)
+            self._pool = None
         self.batch.close()
 
 

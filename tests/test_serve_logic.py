@@ -25,6 +25,9 @@ class FakeSolver:
     def best(self):
         return {"hubs": np.arange(self.p), "cost": float(self.gen), "generation": self.gen}
 
+    def set_stream(self, stream):
+        pass
+
     def close(self):
         self.closed = True
 
@@ -72,13 +75,13 @@ def make_requests(k, sizes, gens):
 def test_admission_respects_budget_and_slots(fake):
     reqs = make_requests(12, [50, 100, 200], [3, 5, 8])
     one = serve.workspace_bytes(reqs[2])
-    srv = serve.Server(hbm_budget=int(2.5 * one), max_slots=3)
+    srv = serve.Server(hbm_budget=int(2.5 * one), max_slots=3, workers=0)
     peak = {"bytes": 0, "slots": 0}
     orig = srv._admit
 
     def admit(req, now):
         job = orig(req, now)
-        peak["bytes"] = max(peak["bytes"], srv.used + job.nbytes)
+        peak["bytes"] = max(peak["bytes"], srv.used)      # the request's bytes are reserved before it is built
         peak["slots"] = max(peak["slots"], len(srv.resident) + 1)
         return job
 
@@ -89,6 +92,7 @@ def test_admission_respects_budget_and_slots(fake):
         assert r.generations == reqs[r.rid].generations
     assert peak["bytes"] <= srv.budget and peak["slots"] <= 3
     assert srv.used == 0 and all(s.closed for s in FakeSolver.live)
+    srv.close()
     # FIFO: admission order is arrival order
     admitted = sorted(res, key=lambda r: r.admitted)
     assert [r.rid for r in admitted] == sorted(r.rid for r in admitted)
@@ -96,7 +100,7 @@ def test_admission_respects_budget_and_slots(fake):
 
 def test_request_larger_than_budget_is_refused(fake):
     reqs = make_requests(1, [200], [2])
-    srv = serve.Server(hbm_budget=1000, max_slots=4)
+    srv = serve.Server(hbm_budget=1000, max_slots=4, workers=0)
     with pytest.raises(MemoryError):
         srv.run(reqs, realtime=False)
 
@@ -107,3 +111,14 @@ def test_poisson_stream_generator():
     assert abs(gaps.mean() - 1 / 200.0) < 0.1 / 200.0
     assert {r.n for r in reqs} <= set(I.SERVING_N) and {r.p for r in reqs} <= set(I.SERVING_P)
     assert {r.S for r in reqs} <= set(I.SERVING_S)
+
+
+def test_worker_threads_give_the_same_results(fake):
+    reqs = make_requests(9, [50, 100], [2, 4, 6])
+    srv = serve.Server(hbm_budget=1 << 40, max_slots=4, workers=3)
+    res = srv.run(reqs, realtime=False)
+    srv.close()
+    assert sorted(r.rid for r in res) == list(range(9))
+    for r in res:
+        assert r.generations == reqs[r.rid].generations and r.cost == float(reqs[r.rid].generations)
+    assert srv.used == 0
