@@ -191,24 +191,31 @@ ga_status ga_set_stream(ga_ctx *ctx, void *hip_stream);
  * gives rows and columns of W x [A_1..A_S] per workgroup tile and the K depth
  * staged per step.  ga_set_tile_config selects one for the context's later
  * batched evaluations (results agree to the returned error bounds in every
- * configuration; the default is 0). */
+ * configuration; the default is 0).  Pipelined configurations (those with a
+ * K depth of 32 staged through an LDS ring) are the ones batches take. */
 int32_t ga_tile_config_count(void);
 ga_status ga_tile_config_info(int32_t config, int32_t *rows, int32_t *cols, int32_t *ktile);
 ga_status ga_set_tile_config(ga_ctx *ctx, int32_t config);
 
 /* Batches: several contexts advanced together, generation by generation (the
- * islands of every context run the steps of ga_step).  One generation of the
- * whole batch is captured once as a HIP graph: per-context operator,
- * allocation and selection chains run as parallel branches, and the
- * matrix-core products of all split-bf16 contexts with p >= 3 are one grouped
- * launch over their concatenated tiles (tile_config must be a pipelined
- * configuration, see ga_tile_config_info).  Every context must use the
- * batch's (non-null) stream and must not be stepped on its own while it is
- * in the batch.  ga_batch_set waits for queued work, replaces the batch's
- * contexts and captures a new graph; ga_batch_step replays it (enqueued,
- * returns without waiting).  Results are those of stepping each context
- * alone.  For callers that mix requests: a context's generation counter,
- * best and state are read with the usual per-context calls. */
+ * islands of every context run the steps of ga_step).  Split-bf16 contexts
+ * whose hub count the tile configuration takes (p >= 3 for the default one)
+ * are grouped: each step of their generation (operators, allocation, the
+ * matrix-core product, cost assembly, selection, exact re-evaluation, island
+ * decisions) is one launch over all of them, its grid the concatenation of
+ * the contexts' own grids.  Other contexts replay their own generation graph
+ * on side streams beside the grouped launches.  tile_config must be a
+ * pipelined configuration (see ga_tile_config_info).  Every context must use
+ * the batch's (non-null) stream (ga_set_stream moves one there) and must not
+ * be stepped on its own while it is in the batch.  ga_batch_set replaces the
+ * batch's contexts without waiting for queued generations: the new job tables
+ * are copied in stream order from pinned staging; it fails with
+ * GA_ERR_INVALID for a NULL or repeated context or one on another stream, and
+ * GA_ERR_STATE for a poisoned one.  ga_batch_step enqueues `generations`
+ * generations and returns without waiting.  Results are those of stepping each
+ * context alone.  A context's generation counter, best and state are read
+ * with the usual per-context calls.  The batch does not own its contexts;
+ * ga_batch_free waits for the batch's stream and frees only the batch. */
 typedef struct ga_batch ga_batch;
 ga_status ga_batch_create(void *hip_stream, int32_t tile_config, ga_batch **out);
 ga_status ga_batch_set(ga_batch *batch, ga_ctx *const *ctxs, int32_t count);

@@ -213,6 +213,14 @@ __device__ __forceinline__ u32x4 ds_read16(uint32_t addr)
     return v;
 }
 __device__ __forceinline__ void lds_wait() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+// Wait until at most N LDS reads of this wave are outstanding (they complete in
+// order; nothing else that counts here is in flight in the K loop).
+template <int N>
+__device__ __forceinline__ void lds_wait_n()
+{
+    static_assert(N >= 0 && N <= 15, "lgkmcnt range");
+    asm volatile("s_waitcnt lgkmcnt(%0)" ::"n"(N) : "memory");
+}
 __device__ __forceinline__ void pin(u32x4 &v) { asm volatile("" : "+v"(v)); }
 
 // s_waitcnt vmcnt(N), other counters untouched (gfx9 encoding).
@@ -246,7 +254,9 @@ constexpr int pipe_ring_chunks()
     return NST * (2 * 2 * 2 * 32 * ROWB + 4 * KINS * 64);
 }
 
-template <int ROWB, int COLB, int NST, int KINS>
+// EARLY: the LDS reads of every k-step of a tile are issued up front, so the
+// reads of step k+1 land while step k's products run.
+template <int ROWB, int COLB, int NST, int KINS, int EARLY>
 __device__ __forceinline__ void mfma_pipe_tile(const MfmaJob &J, int tile, u32x4 *ring)
 {
     constexpr int MT = 32 * ROWB, NT = 128 * COLB, KTILE = 32, KSTEPS = KTILE / 16;
@@ -333,41 +343,54 @@ __device__ __forceinline__ void mfma_pipe_tile(const MfmaJob &J, int tile, u32x4
         wg_barrier();
         if (kt + NST - 1 < ktiles) issue(kt + NST - 1);
         const uint32_t soff = (uint32_t)((kt % NST) * STAGE * 16);
-        static_for<KSTEPS>([&](auto KK) {
+        constexpr int RPK = 2 * ROWB + COLB;   // LDS reads per k-step
+        u32x4 af[KSTEPS][2][ROWB], kv[KSTEPS][COLB];
+        auto reads = [&](auto KK) {
             constexpr int kk = KK.value;
-            u32x4 af[2][ROWB], kv[COLB];
             static_for<2>([&](auto M) {
                 static_for<ROWB>([&](auto A) {
-                    af[M.value][A.value] = ds_read16<((M.value * KSTEPS + kk) * 2 * MT + A.value * 32) * 16>(a_lane + soff);
+                    af[kk][M.value][A.value] =
+                        ds_read16<((M.value * KSTEPS + kk) * 2 * MT + A.value * 32) * 16>(a_lane + soff);
                 });
             });
-            static_for<COLB>([&](auto B) { kv[B.value] = ds_read16<kk * 32>(k_lane[B.value] + soff); });
-            lds_wait();
+            static_for<COLB>([&](auto B) { kv[kk][B.value] = ds_read16<kk * 32>(k_lane[B.value] + soff); });
+        };
+        if constexpr (EARLY) static_for<KSTEPS>(reads);
+        static_for<KSTEPS>([&](auto KK) {
+            constexpr int kk = KK.value;
+            if constexpr (EARLY) {
+                lds_wait_n<(KSTEPS - 1 - kk) * RPK>();
+            } else {
+                reads(KK);
+                lds_wait();
+            }
 #pragma unroll
             for (int m = 0; m < 2; ++m)
 #pragma unroll
-                for (int a = 0; a < ROWB; ++a) pin(af[m][a]);
+                for (int a = 0; a < ROWB; ++a) pin(af[kk][m][a]);
 #pragma unroll
-            for (int b = 0; b < COLB; ++b) pin(kv[b]);
+            for (int b = 0; b < COLB; ++b) pin(kv[kk][b]);
             bf16x8 bfrag[COLB];
 #pragma unroll
             for (int b = 0; b < COLB; ++b) {
                 u32x4 bb;
-                bb.x = onehot2(kv[b].x, lq[b]);
-                bb.y = onehot2(kv[b].y, lq[b]);
-                bb.z = onehot2(kv[b].z, lq[b]);
-                bb.w = onehot2(kv[b].w, lq[b]);
+                bb.x = onehot2(kv[kk][b].x, lq[b]);
+                bb.y = onehot2(kv[kk][b].y, lq[b]);
+                bb.z = onehot2(kv[kk][b].z, lq[b]);
+                bb.w = onehot2(kv[kk][b].w, lq[b]);
                 bfrag[b] = __builtin_bit_cast(bf16x8, bb);
             }
 #pragma unroll
             for (int m = 0; m < 2; ++m)
 #pragma unroll
                 for (int a = 0; a < ROWB; ++a) {
-                    const bf16x8 afr = __builtin_bit_cast(bf16x8, af[m][a]);
+                    const bf16x8 afr = __builtin_bit_cast(bf16x8, af[kk][m][a]);
 #pragma unroll
                     for (int b = 0; b < COLB; ++b)
                         acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afr, bfrag[b], acc[a][b], 0, 0, 0);
                 }
+            // keep this step's products ahead of the next step's wait
+            if constexpr (EARLY) __builtin_amdgcn_sched_barrier(0);
         });
     }
 
@@ -437,7 +460,7 @@ __device__ __forceinline__ void mfma_pipe_tile(const MfmaJob &J, int tile, u32x4
     }
 }
 
-template <int ROWB, int COLB, int NST, int KINS, int OCC>
+template <int ROWB, int COLB, int NST, int KINS, int OCC, int EARLY>
 __global__ __launch_bounds__(256, OCC) void k_eval_mfma_pipe(MfmaJob J)
 {
     __shared__ __align__(16) u32x4 ring[pipe_ring_chunks<ROWB, COLB, NST, KINS>()];
@@ -445,13 +468,13 @@ __global__ __launch_bounds__(256, OCC) void k_eval_mfma_pipe(MfmaJob J)
     const int per = (tiles + 7) / 8;
     const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
     if (tile >= tiles) return;
-    mfma_pipe_tile<ROWB, COLB, NST, KINS>(J, tile, ring);
+    mfma_pipe_tile<ROWB, COLB, NST, KINS, EARLY>(J, tile, ring);
 }
 
 // One launch over the tiles of several contexts: the concatenated tile list
 // (each context row-tile major) is split into 8 contiguous ranges, one per
 // XCD (blockIdx % 8), so every XCD walks whole row panels.
-template <int ROWB, int COLB, int NST, int KINS, int OCC>
+template <int ROWB, int COLB, int NST, int KINS, int OCC, int EARLY>
 __global__ __launch_bounds__(256, OCC) void k_eval_mfma_pipe_group(const MfmaJob *__restrict__ jobs, int njobs,
                                                                    int total_tiles)
 {
@@ -468,7 +491,7 @@ __global__ __launch_bounds__(256, OCC) void k_eval_mfma_pipe_group(const MfmaJob
             hi = mid - 1;
     }
     const MfmaJob J = jobs[lo];
-    mfma_pipe_tile<ROWB, COLB, NST, KINS>(J, t - J.tile_start, ring);
+    mfma_pipe_tile<ROWB, COLB, NST, KINS, EARLY>(J, t - J.tile_start, ring);
 }
 
 // T_s = sum of the individual's p*n_mt partials (contiguous), one wave per
@@ -532,7 +555,7 @@ static hipError_t mfma_launch(const DevPtrs &P, const Dims &d, const uint16_t *k
     return hipGetLastError();
 }
 
-template <int ROWB, int COLB, int NST, int KINS, int OCC>
+template <int ROWB, int COLB, int NST, int KINS, int OCC, int EARLY>
 static hipError_t pipe_launch(const DevPtrs &P, const Dims &d, const uint16_t *kidx, int count, hipStream_t st)
 {
     const int MT = 32 * ROWB, NT = 128 * COLB;
@@ -543,19 +566,19 @@ static hipError_t pipe_launch(const DevPtrs &P, const Dims &d, const uint16_t *k
     const int per = (tiles + 7) / 8;
     MfmaJob J{(const u32x4 *)P.Whsw, (const u32x4 *)P.Wlsw, kidx, P.Ch32, P.partial, d.n, d.n_pad, d.p, count,
               NS, n_mt, n_nt, 0};
-    k_eval_mfma_pipe<ROWB, COLB, NST, KINS, OCC><<<per * 8, 256, 0, st>>>(J);
+    k_eval_mfma_pipe<ROWB, COLB, NST, KINS, OCC, EARLY><<<per * 8, 256, 0, st>>>(J);
     return hipGetLastError();
 }
 
 // Individuals one wave's columns can touch, in 16-individual transfers.
 static int kidx_transfers(int colb, int p) { return (((32 * colb + p - 2) / p + 2) + 15) / 16; }
 
-template <int ROWB, int COLB, int NST, int OCC>
+template <int ROWB, int COLB, int NST, int OCC, int EARLY = 0>
 static hipError_t pipe_dispatch(const DevPtrs &P, const Dims &d, const uint16_t *kidx, int count, hipStream_t st)
 {
     const int kins = kidx_transfers(COLB, d.p);
-    if (kins <= 1) return pipe_launch<ROWB, COLB, NST, 1, OCC>(P, d, kidx, count, st);
-    if (kins <= 2) return pipe_launch<ROWB, COLB, NST, 2, OCC>(P, d, kidx, count, st);
+    if (kins <= 1) return pipe_launch<ROWB, COLB, NST, 1, OCC, EARLY>(P, d, kidx, count, st);
+    if (kins <= 2) return pipe_launch<ROWB, COLB, NST, 2, OCC, EARLY>(P, d, kidx, count, st);
     return mfma_launch<4, 2, 32, 2>(P, d, kidx, count, st);   // few hubs: per-lane fragment loads
 }
 
@@ -565,7 +588,9 @@ static hipError_t pipe_dispatch(const DevPtrs &P, const Dims &d, const uint16_t 
 struct MfmaCfg { int rowb, colb, kt, occ, nst; };
 static const MfmaCfg kMfmaCfgs[] = {{4, 2, 32, 2, 0}, {4, 2, 64, 1, 0}, {4, 4, 32, 1, 0}, {2, 4, 32, 2, 0},
                                     {4, 4, 64, 1, 0}, {2, 2, 64, 2, 0}, {4, 2, 32, 1, 4}, {4, 2, 32, 2, 3},
-                                    {4, 4, 32, 1, 4}, {4, 4, 32, 1, 3}, {2, 4, 32, 2, 4}};
+                                    {4, 4, 32, 1, 4}, {4, 4, 32, 1, 3}, {2, 4, 32, 2, 4},
+                                    // the same shapes with early LDS reads
+                                    {4, 2, 32, 2, 3}, {4, 2, 32, 1, 4}, {2, 4, 32, 2, 4}};
 constexpr int kNumMfmaCfgs = sizeof(kMfmaCfgs) / sizeof(kMfmaCfgs[0]);
 
 int mfma_num_configs() { return kNumMfmaCfgs; }
@@ -588,7 +613,10 @@ hipError_t launch_mfma(const DevPtrs &P, const Dims &d, const uint16_t *kidx, in
     case 7: return pipe_dispatch<4, 2, 3, 2>(P, d, kidx, count, st);
     case 8: return pipe_dispatch<4, 4, 4, 1>(P, d, kidx, count, st);
     case 9: return pipe_dispatch<4, 4, 3, 1>(P, d, kidx, count, st);
-    default: return pipe_dispatch<2, 4, 4, 2>(P, d, kidx, count, st);
+    case 10: return pipe_dispatch<2, 4, 4, 2>(P, d, kidx, count, st);
+    case 11: return pipe_dispatch<4, 2, 3, 2, 1>(P, d, kidx, count, st);
+    case 12: return pipe_dispatch<4, 2, 4, 1, 1>(P, d, kidx, count, st);
+    default: return pipe_dispatch<2, 4, 4, 2, 1>(P, d, kidx, count, st);
     }
 }
 
@@ -654,20 +682,20 @@ int mfma_fill_jobs(const DevPtrs *const *P, const Dims *const *d, int njobs, int
     return start;
 }
 
-template <int ROWB, int COLB, int NST, int KINS, int OCC>
+template <int ROWB, int COLB, int NST, int KINS, int OCC, int EARLY>
 static hipError_t group_launch(const void *d_jobs, int njobs, int total, hipStream_t st)
 {
     const int per = (total + 7) / 8;
-    k_eval_mfma_pipe_group<ROWB, COLB, NST, KINS, OCC><<<per * 8, 256, 0, st>>>((const MfmaJob *)d_jobs, njobs,
-                                                                               total);
+    k_eval_mfma_pipe_group<ROWB, COLB, NST, KINS, OCC, EARLY><<<per * 8, 256, 0, st>>>((const MfmaJob *)d_jobs,
+                                                                                      njobs, total);
     return hipGetLastError();
 }
 
-template <int ROWB, int COLB, int NST, int OCC>
+template <int ROWB, int COLB, int NST, int OCC, int EARLY = 0>
 static hipError_t group_dispatch(int kins, const void *d_jobs, int njobs, int total, hipStream_t st)
 {
-    if (kins <= 1) return group_launch<ROWB, COLB, NST, 1, OCC>(d_jobs, njobs, total, st);
-    return group_launch<ROWB, COLB, NST, 2, OCC>(d_jobs, njobs, total, st);
+    if (kins <= 1) return group_launch<ROWB, COLB, NST, 1, OCC, EARLY>(d_jobs, njobs, total, st);
+    return group_launch<ROWB, COLB, NST, 2, OCC, EARLY>(d_jobs, njobs, total, st);
 }
 
 hipError_t launch_mfma_group(const void *d_jobs, int njobs, int total, int cfg, int min_p, hipStream_t st)
@@ -681,6 +709,9 @@ hipError_t launch_mfma_group(const void *d_jobs, int njobs, int total, int cfg, 
     case 8: return group_dispatch<4, 4, 4, 1>(kins, d_jobs, njobs, total, st);
     case 9: return group_dispatch<4, 4, 3, 1>(kins, d_jobs, njobs, total, st);
     case 10: return group_dispatch<2, 4, 4, 2>(kins, d_jobs, njobs, total, st);
+    case 11: return group_dispatch<4, 2, 3, 2, 1>(kins, d_jobs, njobs, total, st);
+    case 12: return group_dispatch<4, 2, 4, 1, 1>(kins, d_jobs, njobs, total, st);
+    case 13: return group_dispatch<2, 4, 4, 2, 1>(kins, d_jobs, njobs, total, st);
     default: return hipErrorInvalidValue;
     }
 }

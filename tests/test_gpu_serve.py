@@ -19,13 +19,14 @@ def gpu():
     yield
 
 
-def requests(k=10, gens=12):
+def requests(k=10, gens=30):
     out = []
     sizes = [(50, 3, 256), (100, 5, 512), (200, 10, 256), (150, 20, 256), (120, 2, 256)]
     for r in range(k):
         n, p, S = sizes[r % len(sizes)]
         inst = I.uniform(seed=100 + r, n=n, p=p)
-        out.append(serve.SolveRequest(r, 0.002 * r, inst.C, inst.W, p, inst.chi, inst.alpha, inst.delta, S,
+        # arrivals 0.2 ms apart, well inside one request's service time
+        out.append(serve.SolveRequest(r, 0.0002 * r, inst.C, inst.W, p, inst.chi, inst.alpha, inst.delta, S,
                                       gens + (r % 3), 7 + r))
     return out
 
