@@ -13,7 +13,8 @@
 
 namespace hubga {
 
-constexpr int kAllocPer = 1;   // individuals per workgroup
+constexpr int kAllocPer = 1;     // individuals per workgroup
+constexpr int kScanChunk = 16;   // hub distances loaded together by one lane
 
 // Workgroup blk (of a grid of alloc_blocks(count)) of one context.
 template <typename CT>
@@ -61,17 +62,25 @@ __device__ __forceinline__ void alloc_body(const int32_t *__restrict__ hubs, int
             // minimum is also the unique minimum of the instance values.  When
             // several hubs share the FP32 minimum, rescan in the instance
             // dtype (strict <, ties to the smaller hub id).
+            // The p loads of a chunk are issued before any comparison (a
+            // compare-as-you-load loop waits for every load in turn).
             int best = 0;
-            float bd = Ct32[(size_t)h[0] * n + i];
+            float bd = __builtin_huge_valf();
             bool tie = false;
-            for (int k = 1; k < p; ++k) {
-                const float v = Ct32[(size_t)h[k] * n + i];
-                if (v < bd) {
-                    bd = v;
-                    best = k;
-                    tie = false;
-                } else if (v == bd) {
-                    tie = true;
+            for (int k0 = 0; k0 < p; k0 += kScanChunk) {
+                float v[kScanChunk];
+#pragma unroll
+                for (int u = 0; u < kScanChunk; ++u)
+                    v[u] = k0 + u < p ? Ct32[(size_t)h[k0 + u] * n + i] : __builtin_huge_valf();
+#pragma unroll
+                for (int u = 0; u < kScanChunk; ++u) {
+                    if (v[u] < bd) {
+                        bd = v[u];
+                        best = k0 + u;
+                        tie = false;
+                    } else if (v[u] == bd && k0 + u < p) {
+                        tie = true;
+                    }
                 }
             }
             if (tie) {

@@ -590,7 +590,9 @@ static const MfmaCfg kMfmaCfgs[] = {{4, 2, 32, 2, 0}, {4, 2, 64, 1, 0}, {4, 4, 3
                                     {4, 4, 64, 1, 0}, {2, 2, 64, 2, 0}, {4, 2, 32, 1, 4}, {4, 2, 32, 2, 3},
                                     {4, 4, 32, 1, 4}, {4, 4, 32, 1, 3}, {2, 4, 32, 2, 4},
                                     // the same shapes with early LDS reads
-                                    {4, 2, 32, 2, 3}, {4, 2, 32, 1, 4}, {2, 4, 32, 2, 4}};
+                                    {4, 2, 32, 2, 3}, {4, 2, 32, 1, 4}, {2, 4, 32, 2, 4},
+                                    // four stages at two workgroups per CU (fits for one hub-position transfer)
+                                    {4, 2, 32, 2, 4}, {4, 2, 32, 2, 4}};
 constexpr int kNumMfmaCfgs = sizeof(kMfmaCfgs) / sizeof(kMfmaCfgs[0]);
 
 int mfma_num_configs() { return kNumMfmaCfgs; }
@@ -616,7 +618,9 @@ hipError_t launch_mfma(const DevPtrs &P, const Dims &d, const uint16_t *kidx, in
     case 10: return pipe_dispatch<2, 4, 4, 2>(P, d, kidx, count, st);
     case 11: return pipe_dispatch<4, 2, 3, 2, 1>(P, d, kidx, count, st);
     case 12: return pipe_dispatch<4, 2, 4, 1, 1>(P, d, kidx, count, st);
-    default: return pipe_dispatch<2, 4, 4, 2, 1>(P, d, kidx, count, st);
+    case 13: return pipe_dispatch<2, 4, 4, 2, 1>(P, d, kidx, count, st);
+    case 14: return pipe_dispatch<4, 2, 4, 2>(P, d, kidx, count, st);
+    default: return pipe_dispatch<4, 2, 4, 2, 1>(P, d, kidx, count, st);
     }
 }
 
@@ -712,6 +716,8 @@ hipError_t launch_mfma_group(const void *d_jobs, int njobs, int total, int cfg, 
     case 11: return group_dispatch<4, 2, 3, 2, 1>(kins, d_jobs, njobs, total, st);
     case 12: return group_dispatch<4, 2, 4, 1, 1>(kins, d_jobs, njobs, total, st);
     case 13: return group_dispatch<2, 4, 4, 2, 1>(kins, d_jobs, njobs, total, st);
+    case 14: return group_dispatch<4, 2, 4, 2>(kins, d_jobs, njobs, total, st);
+    case 15: return group_dispatch<4, 2, 4, 2, 1>(kins, d_jobs, njobs, total, st);
     default: return hipErrorInvalidValue;
     }
 }
