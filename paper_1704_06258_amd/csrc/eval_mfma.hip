@@ -248,10 +248,91 @@ struct MfmaJob {
     int n, n_pad, p, count, NS, n_mt, n_nt, tile_start;
 };
 
-template <int ROWB, int COLB, int NST, int KINS>
+// Ring size in 16-byte chunks; MODE 2 stages K tiles of 64 (the rest 32).
+template <int ROWB, int COLB, int NST, int KINS, int MODE = 0>
 constexpr int pipe_ring_chunks()
 {
-    return NST * (2 * 2 * 2 * 32 * ROWB + 4 * KINS * 64);
+    constexpr int KH = MODE == 2 ? 2 : 1;   // 32-deep halves of the K tile
+    return NST * (2 * (2 * KH) * 2 * 32 * ROWB + 4 * KINS * KH * 64);
+}
+
+// Epilogue of a pipelined tile: sum_i G[i][(s,l)] * C[h_k(i)][h_l] over the
+// tile's rows in binary64, one partial per (column, row tile).  The ring
+// (ring_chunks 16-byte chunks) is free once every wave has left the K loop.
+template <int ROWB, int COLB>
+__device__ __forceinline__ void pipe_epilogue(const MfmaJob &J, f32x16 (&acc)[ROWB][COLB], const int (&col)[COLB],
+                                              const uint32_t (&lq)[COLB], int mt, int nt, u32x4 *ring,
+                                              int ring_chunks)
+{
+    constexpr int MT = 32 * ROWB, NT = 128 * COLB;
+    const uint16_t *__restrict__ kidx = J.kidx;
+    const float *__restrict__ Ch32 = J.Ch32;
+    double *__restrict__ partial = J.partial;
+    const int n = J.n, n_pad = J.n_pad, p = J.p, NS = J.NS, n_mt = J.n_mt;
+    const int M0 = mt * MT, N0 = nt * NT;
+    const int tid = threadIdx.x, half = (tid & 63) >> 5;
+    // The ring takes the hub positions of the tile's rows and the FP32
+    // hub-distance tables of the workgroup's individuals, so the gathers hit
+    // LDS.  Accumulator v of a 32x32 block holds row 8*(v/4) + 4*half + (v%4).
+    wg_barrier();
+    const int s_lo = min(N0, NS - 1) / p, s_hi = min(N0 + NT - 1, NS - 1) / p;
+    const int nind = s_hi - s_lo + 1;
+    const size_t need = (size_t)nind * MT * 2 + (size_t)nind * p * p * 4;
+    const bool staged = need <= sizeof(u32x4) * (size_t)ring_chunks;
+    // Indices into the staged arrays are offsets from their start (never a
+    // pointer moved before it): LDS pointer arithmetic is 32-bit, and a
+    // negative intermediate would leave the LDS aperture of a flat address.
+    uint16_t *lk = (uint16_t *)ring;                                              // [ind][row - M0]
+    float *lch = (float *)(ring + (nind * MT * 2 + 15) / 16);                     // [ind][k][l]
+    if (staged) {
+        for (int e = tid; e < nind * MT; e += 256) {
+            const int ind = e / MT, row = e % MT;
+            // rows past n get position 0: their products are exactly zero (W is
+            // zero-padded), which keeps the sum below free of branches
+            lk[e] = M0 + row < n ? kidx[(size_t)(s_lo + ind) * n_pad + M0 + row] : 0;
+        }
+        const int pp = p * p;
+        for (int e = tid; e < nind * pp; e += 256) lch[e] = Ch32[(size_t)s_lo * pp + e];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int b = 0; b < COLB; ++b) {
+        double part[4] = {0.0, 0.0, 0.0, 0.0};
+        if (col[b] < NS) {
+            const int s = col[b] / p;
+            if (staged) {
+                // rows a*32 + 8j + 4*half + t (t = 0..3) are 4 consecutive positions
+                const int kb = (s - s_lo) * MT + 4 * half, cb = (s - s_lo) * p * p + (int)lq[b];
+#pragma unroll
+                for (int a = 0; a < ROWB; ++a) {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const uint2 k4 = *(const uint2 *)(lk + kb + a * 32 + 8 * j);
+                        const int k0 = (int)(k4.x & 0xFFFFu), k1 = (int)(k4.x >> 16);
+                        const int k2 = (int)(k4.y & 0xFFFFu), k3 = (int)(k4.y >> 16);
+                        part[0] += (double)acc[a][b][4 * j + 0] * (double)lch[cb + k0 * p];
+                        part[1] += (double)acc[a][b][4 * j + 1] * (double)lch[cb + k1 * p];
+                        part[2] += (double)acc[a][b][4 * j + 2] * (double)lch[cb + k2 * p];
+                        part[3] += (double)acc[a][b][4 * j + 3] * (double)lch[cb + k3 * p];
+                    }
+                }
+            } else {
+                const uint16_t *kr = kidx + (size_t)s * n_pad;
+                const float *ch = Ch32 + (size_t)s * p * p + lq[b];
+#pragma unroll
+                for (int a = 0; a < ROWB; ++a) {
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) {
+                        const int i = M0 + a * 32 + 8 * (v >> 2) + 4 * half + (v & 3);
+                        if (i < n) part[v & 3] += (double)acc[a][b][v] * (double)ch[kr[i] * p];
+                    }
+                }
+            }
+        }
+        double sum = (part[0] + part[1]) + (part[2] + part[3]);
+        sum += __shfl_xor(sum, 32);
+        if (half == 0 && col[b] < NS) partial[(size_t)col[b] * n_mt + mt] = sum;
+    }
 }
 
 // EARLY: the LDS reads of every k-step of a tile are issued up front, so the
@@ -394,81 +475,190 @@ __device__ __forceinline__ void mfma_pipe_tile(const MfmaJob &J, int tile, u32x4
         });
     }
 
-    // Epilogue: sum_i G[i][(s,l)] * C[h_k(i)][h_l] over this tile's rows in
-    // binary64.  The ring is free once every wave has left the K loop: it
-    // takes the hub positions of the tile's rows and the FP32 hub-distance
-    // tables of the workgroup's individuals, so the gathers hit LDS.
-    // Accumulator v of a 32x32 block holds row 8*(v/4) + 4*half + (v%4).
-    wg_barrier();
-    const int s_lo = min(N0, NS - 1) / p, s_hi = min(N0 + NT - 1, NS - 1) / p;
-    const int nind = s_hi - s_lo + 1;
-    const size_t need = (size_t)nind * MT * 2 + (size_t)nind * p * p * 4;
-    const bool staged = need <= sizeof(u32x4) * NST * STAGE;
-    // Indices into the staged arrays are offsets from their start (never a
-    // pointer moved before it): LDS pointer arithmetic is 32-bit, and a
-    // negative intermediate would leave the LDS aperture of a flat address.
-    uint16_t *lk = (uint16_t *)ring;                                              // [ind][row - M0]
-    float *lch = (float *)(ring + (nind * MT * 2 + 15) / 16);                     // [ind][k][l]
-    if (staged) {
-        for (int e = tid; e < nind * MT; e += 256) {
-            const int ind = e / MT, row = e % MT;
-            // rows past n get position 0: their products are exactly zero (W is
-            // zero-padded), which keeps the sum below free of branches
-            lk[e] = M0 + row < n ? kidx[(size_t)(s_lo + ind) * n_pad + M0 + row] : 0;
-        }
-        const int pp = p * p;
-        for (int e = tid; e < nind * pp; e += 256) lch[e] = Ch32[(size_t)s_lo * pp + e];
-        __syncthreads();
-    }
+    pipe_epilogue<ROWB, COLB>(J, acc, col, lq, mt, nt, ring, NST * STAGE);
+}
+
+// K tiles of 64 (four 16-deep k-steps between barriers) with a rolling
+// register pipeline: the LDS reads of step k+1 are in flight while step k's
+// products run, the one-hot fragment of the second column block is built
+// between the products of the first, and the barrier that hands over the
+// next K tile is taken before the last step's products, whose operands are
+// already in registers.
+template <int ROWB, int COLB, int NST, int KINS>
+__device__ __forceinline__ void mfma_pipe_tile64(const MfmaJob &J, int tile, u32x4 *ring)
+{
+    constexpr int MT = 32 * ROWB, NT = 128 * COLB, KTILE = 64, KSTEPS = KTILE / 16, KH = 2;
+    constexpr int A_CHUNKS = 2 * KSTEPS * 2 * MT;   // [hi/lo][kk][half][row] 16-byte chunks per stage
+    constexpr int K_CHUNKS = 4 * KINS * KH * 64;    // [wave][ins][k half][lane]
+    constexpr int STAGE = A_CHUNKS + K_CHUNKS;
+    constexpr int A_INS = A_CHUNKS / 64 / 4;        // 1 KB transfers per wave per tile for W
+    constexpr int LPT = A_INS + KINS * KH;          // vector-memory instructions per wave per tile
+    constexpr int RPK = 2 * ROWB + COLB;            // LDS reads per k-step
+    static_assert(MT % 64 == 0 && (A_CHUNKS / 64) % 4 == 0 && RPK <= 15, "tile shape");
+    static_assert(NST * STAGE == pipe_ring_chunks<ROWB, COLB, NST, KINS, 2>(), "ring size");
+    const u32x4 *__restrict__ Whsw = J.Whsw;
+    const u32x4 *__restrict__ Wlsw = J.Wlsw;
+    const uint16_t *__restrict__ kidx = J.kidx;
+    const int n_pad = J.n_pad, p = J.p, count = J.count, NS = J.NS, n_nt = J.n_nt;
+    const int mt = tile / n_nt, nt = tile % n_nt;
+    const int N0 = nt * NT;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int half = lane >> 5, l32 = lane & 31;
+    const int KS = n_pad / 16;
+
+    const int c_first = min(N0 + wave * 32 * COLB, NS - 1);
+    const int s_first = c_first / p;
+    int col[COLB], li[COLB];
+    uint32_t lq[COLB];
 #pragma unroll
     for (int b = 0; b < COLB; ++b) {
-        double part[4] = {0.0, 0.0, 0.0, 0.0};
+        col[b] = N0 + wave * 32 * COLB + b * 32 + l32;
         if (col[b] < NS) {
-            const int s = col[b] / p;
-            if (staged) {
-                // rows a*32 + 8j + 4*half + t (t = 0..3) are 4 consecutive positions
-                const int kb = (s - s_lo) * MT + 4 * half, cb = (s - s_lo) * p * p + (int)lq[b];
+            li[b] = col[b] / p - s_first;
+            lq[b] = (uint32_t)(col[b] % p);
+        } else {
+            li[b] = 0;
+            lq[b] = 0xFFFFu;
+        }
+    }
+
+    const uint32_t ring_addr = (uint32_t)(uintptr_t)(lds_void *)ring;
+    auto issue = [&](int kt) {
+        u32x4 *stage = ring + (kt % NST) * STAGE;
 #pragma unroll
-                for (int a = 0; a < ROWB; ++a) {
+        for (int q = 0; q < A_INS; ++q) {
+            const int ins = wave + 4 * q;                    // ((mat*KSTEPS + kk)*2 + h)*(MT/64) + gl
+            const int gl = ins % (MT / 64), t = ins / (MT / 64);
+            const int h = t & 1, kk = (t >> 1) % KSTEPS, mat = (t >> 1) / KSTEPS;
+            const size_t gchunk = (((size_t)(mt * (MT / 64) + gl) * KS + kt * KSTEPS + kk) * 2 + h) * 64;
+            const u32x4 *src = (mat ? Wlsw : Whsw) + gchunk + lane;
+            __builtin_amdgcn_global_load_lds((const void *)src, (lds_void *)(stage + ins * 64), 16, 0, 0);
+        }
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const uint2 k4 = *(const uint2 *)(lk + kb + a * 32 + 8 * j);
-                        const int k0 = (int)(k4.x & 0xFFFFu), k1 = (int)(k4.x >> 16);
-                        const int k2 = (int)(k4.y & 0xFFFFu), k3 = (int)(k4.y >> 16);
-                        part[0] += (double)acc[a][b][4 * j + 0] * (double)lch[cb + k0 * p];
-                        part[1] += (double)acc[a][b][4 * j + 1] * (double)lch[cb + k1 * p];
-                        part[2] += (double)acc[a][b][4 * j + 2] * (double)lch[cb + k2 * p];
-                        part[3] += (double)acc[a][b][4 * j + 3] * (double)lch[cb + k3 * p];
-                    }
-                }
-            } else {
-                const uint16_t *kr = kidx + (size_t)s * n_pad;
-                const float *ch = Ch32 + (size_t)s * p * p + lq[b];
+        for (int q = 0; q < KINS; ++q) {
+            const int si = min(s_first + q * 16 + (lane >> 2), count - 1);
 #pragma unroll
-                for (int a = 0; a < ROWB; ++a) {
-#pragma unroll
-                    for (int v = 0; v < 16; ++v) {
-                        const int i = M0 + a * 32 + 8 * (v >> 2) + 4 * half + (v & 3);
-                        if (i < n) part[v & 3] += (double)acc[a][b][v] * (double)ch[kr[i] * p];
-                    }
-                }
+            for (int kh = 0; kh < KH; ++kh) {
+                const uint16_t *src = kidx + (size_t)si * n_pad + kt * KTILE + kh * 32 + (lane & 3) * 8;
+                __builtin_amdgcn_global_load_lds((const void *)src,
+                                                 (lds_void *)(stage + A_CHUNKS + ((wave * KINS + q) * KH + kh) * 64),
+                                                 16, 0, 0);
             }
         }
-        double sum = (part[0] + part[1]) + (part[2] + part[3]);
-        sum += __shfl_xor(sum, 32);
-        if (half == 0 && col[b] < NS) partial[(size_t)col[b] * n_mt + mt] = sum;
+    };
+    auto wait_tile = [&](int kt) {   // this wave's transfers of tile kt have landed
+        const int younger = min(NST - 2, (n_pad / KTILE) - 1 - kt);
+        static_for<NST - 1>([&](auto Y) {
+            if (younger == Y.value) vm_wait<Y.value * LPT>();
+        });
+    };
+
+    f32x16 acc[ROWB][COLB];
+#pragma unroll
+    for (int a = 0; a < ROWB; ++a)
+#pragma unroll
+        for (int b = 0; b < COLB; ++b) acc[a][b] = (f32x16)(0.0f);
+
+    const uint32_t a_lane = ring_addr + (uint32_t)((half * MT + l32) * 16);
+    uint32_t k_lane[COLB];
+#pragma unroll
+    for (int b = 0; b < COLB; ++b)
+        k_lane[b] = ring_addr +
+                    (uint32_t)((A_CHUNKS + (wave * KINS + li[b] / 16) * KH * 64 + (li[b] % 16) * 4 + half) * 16);
+
+    u32x4 af[2][2][ROWB], kv[2][COLB];   // [register set][hi/lo][row block]
+    auto reads = [&](auto R, auto KK, uint32_t soff) {
+        constexpr int r = decltype(R)::value, kk = decltype(KK)::value;
+        static_for<2>([&](auto M) {
+            static_for<ROWB>([&](auto A) {
+                af[r][M.value][A.value] =
+                    ds_read16<((M.value * KSTEPS + kk) * 2 * MT + A.value * 32) * 16>(a_lane + soff);
+            });
+        });
+        static_for<COLB>([&](auto B) {
+            kv[r][B.value] = ds_read16<((kk / 2) * 64 + (kk % 2) * 2) * 16>(k_lane[B.value] + soff);
+        });
+    };
+
+    const int ktiles = n_pad / KTILE;
+#pragma unroll
+    for (int t = 0; t < NST - 1; ++t)
+        if (t < ktiles) issue(t);
+    wait_tile(0);
+    wg_barrier();
+    if (NST - 1 < ktiles) issue(NST - 1);
+    reads(std::integral_constant<int, 0>{}, std::integral_constant<int, 0>{}, 0u);
+
+    for (int kt = 0; kt < ktiles; ++kt) {
+        const uint32_t soff = (uint32_t)((kt % NST) * STAGE * 16);
+        static_for<KSTEPS>([&](auto KK) {
+            constexpr int kk = KK.value, r = kk & 1;
+            if constexpr (kk + 1 < KSTEPS) {
+                reads(std::integral_constant<int, r ^ 1>{}, std::integral_constant<int, kk + 1>{}, soff);
+                lds_wait_n<RPK>();
+            } else {
+                lds_wait_n<0>();   // every read of tile kt has landed
+                if (kt + 1 < ktiles) {
+                    wait_tile(kt + 1);
+                    wg_barrier();   // tile kt+1 visible to all waves; tile kt's stage is free
+                    if (kt + NST < ktiles) issue(kt + NST);
+                    reads(std::integral_constant<int, 0>{}, std::integral_constant<int, 0>{},
+                          (uint32_t)(((kt + 1) % NST) * STAGE * 16));
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+#pragma unroll
+                for (int a = 0; a < ROWB; ++a) pin(af[r][m][a]);
+#pragma unroll
+            for (int b = 0; b < COLB; ++b) pin(kv[r][b]);
+            bf16x8 bfrag[COLB];
+#pragma unroll
+            for (int b = 0; b < COLB; ++b) {
+                u32x4 bb;
+                bb.x = onehot2(kv[r][b].x, lq[b]);
+                bb.y = onehot2(kv[r][b].y, lq[b]);
+                bb.z = onehot2(kv[r][b].z, lq[b]);
+                bb.w = onehot2(kv[r][b].w, lq[b]);
+                bfrag[b] = __builtin_bit_cast(bf16x8, bb);
+            }
+            // column block by column block, so that the next block's one-hot
+            // fragment is built while this block's products run
+#pragma unroll
+            for (int b = 0; b < COLB; ++b)
+#pragma unroll
+                for (int m = 0; m < 2; ++m)
+#pragma unroll
+                    for (int a = 0; a < ROWB; ++a)
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                            __builtin_bit_cast(bf16x8, af[r][m][a]), bfrag[b], acc[a][b], 0, 0, 0);
+            __builtin_amdgcn_sched_group_barrier(0x002, 24, 0);   // one-hot of block 0
+            static_for<COLB - 1>([&](auto) {
+                static_for<2 * ROWB>([&](auto) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);
+                });
+            });
+            __builtin_amdgcn_sched_group_barrier(0x008, 2 * ROWB, 0);
+            __builtin_amdgcn_sched_barrier(0);
+        });
     }
+
+    pipe_epilogue<ROWB, COLB>(J, acc, col, lq, mt, nt, ring, NST * STAGE);
 }
 
 template <int ROWB, int COLB, int NST, int KINS, int OCC, int EARLY>
 __global__ __launch_bounds__(256, OCC) void k_eval_mfma_pipe(MfmaJob J)
 {
-    __shared__ __align__(16) u32x4 ring[pipe_ring_chunks<ROWB, COLB, NST, KINS>()];
+    __shared__ __align__(16) u32x4 ring[pipe_ring_chunks<ROWB, COLB, NST, KINS, EARLY>()];
     const int tiles = J.n_mt * J.n_nt;
     const int per = (tiles + 7) / 8;
     const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
     if (tile >= tiles) return;
-    mfma_pipe_tile<ROWB, COLB, NST, KINS, EARLY>(J, tile, ring);
+    if constexpr (EARLY == 2)
+        mfma_pipe_tile64<ROWB, COLB, NST, KINS>(J, tile, ring);
+    else
+        mfma_pipe_tile<ROWB, COLB, NST, KINS, EARLY>(J, tile, ring);
 }
 
 // One launch over the tiles of several contexts: the concatenated tile list
@@ -478,7 +668,7 @@ template <int ROWB, int COLB, int NST, int KINS, int OCC, int EARLY>
 __global__ __launch_bounds__(256, OCC) void k_eval_mfma_pipe_group(const MfmaJob *__restrict__ jobs, int njobs,
                                                                    int total_tiles)
 {
-    __shared__ __align__(16) u32x4 ring[pipe_ring_chunks<ROWB, COLB, NST, KINS>()];
+    __shared__ __align__(16) u32x4 ring[pipe_ring_chunks<ROWB, COLB, NST, KINS, EARLY>()];
     const int per = (total_tiles + 7) / 8;
     const int t = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
     if (t >= total_tiles) return;
@@ -491,7 +681,10 @@ __global__ __launch_bounds__(256, OCC) void k_eval_mfma_pipe_group(const MfmaJob
             hi = mid - 1;
     }
     const MfmaJob J = jobs[lo];
-    mfma_pipe_tile<ROWB, COLB, NST, KINS, EARLY>(J, t - J.tile_start, ring);
+    if constexpr (EARLY == 2)
+        mfma_pipe_tile64<ROWB, COLB, NST, KINS>(J, t - J.tile_start, ring);
+    else
+        mfma_pipe_tile<ROWB, COLB, NST, KINS, EARLY>(J, t - J.tile_start, ring);
 }
 
 // T_s = sum of the individual's p*n_mt partials (contiguous), one wave per
@@ -592,7 +785,9 @@ static const MfmaCfg kMfmaCfgs[] = {{4, 2, 32, 2, 0}, {4, 2, 64, 1, 0}, {4, 4, 3
                                     // the same shapes with early LDS reads
                                     {4, 2, 32, 2, 3}, {4, 2, 32, 1, 4}, {2, 4, 32, 2, 4},
                                     // four stages at two workgroups per CU (fits for one hub-position transfer)
-                                    {4, 2, 32, 2, 4}, {4, 2, 32, 2, 4}};
+                                    {4, 2, 32, 2, 4}, {4, 2, 32, 2, 4},
+                                    // K tiles of 64 with the rolling register pipeline
+                                    {4, 2, 64, 2, 2}, {4, 2, 64, 1, 3}};
 constexpr int kNumMfmaCfgs = sizeof(kMfmaCfgs) / sizeof(kMfmaCfgs[0]);
 
 int mfma_num_configs() { return kNumMfmaCfgs; }
@@ -620,7 +815,9 @@ hipError_t launch_mfma(const DevPtrs &P, const Dims &d, const uint16_t *kidx, in
     case 12: return pipe_dispatch<4, 2, 4, 1, 1>(P, d, kidx, count, st);
     case 13: return pipe_dispatch<2, 4, 4, 2, 1>(P, d, kidx, count, st);
     case 14: return pipe_dispatch<4, 2, 4, 2>(P, d, kidx, count, st);
-    default: return pipe_dispatch<4, 2, 4, 2, 1>(P, d, kidx, count, st);
+    case 15: return pipe_dispatch<4, 2, 4, 2, 1>(P, d, kidx, count, st);
+    case 16: return pipe_dispatch<4, 2, 2, 2, 2>(P, d, kidx, count, st);
+    default: return pipe_dispatch<4, 2, 3, 1, 2>(P, d, kidx, count, st);
     }
 }
 
@@ -718,6 +915,8 @@ hipError_t launch_mfma_group(const void *d_jobs, int njobs, int total, int cfg, 
     case 13: return group_dispatch<2, 4, 4, 2, 1>(kins, d_jobs, njobs, total, st);
     case 14: return group_dispatch<4, 2, 4, 2>(kins, d_jobs, njobs, total, st);
     case 15: return group_dispatch<4, 2, 4, 2, 1>(kins, d_jobs, njobs, total, st);
+    case 16: return group_dispatch<4, 2, 2, 2, 2>(kins, d_jobs, njobs, total, st);
+    case 17: return group_dispatch<4, 2, 3, 1, 2>(kins, d_jobs, njobs, total, st);
     default: return hipErrorInvalidValue;
     }
 }
