@@ -34,6 +34,33 @@ __device__ __forceinline__ uint32_t onehot2(uint32_t kk, uint32_t lq)
     return lo | hi;
 }
 
+// The same for the pipelined kernels, in three packed 16-bit operations: with
+// d = positions xor (l, l), min(d, 1) is 0 where a position equals l, and
+// m * 0xC080 + 0x3F80 (mod 2^16) is then bf16 1.0 for m = 0 and 0 for m = 1.
+// lq2 holds l in both halves.  The three constants come from registers the
+// compiler cannot see into (it would turn the arithmetic back into compares
+// and selects, twice the instructions).
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+struct OneHotK {
+    u16x2 one, mul, add;
+};
+__device__ __forceinline__ u16x2 opaque_u16x2(int v)
+{
+    uint32_t r;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "i"(v));
+    return __builtin_bit_cast(u16x2, r);
+}
+__device__ __forceinline__ OneHotK onehot_consts()
+{
+    return OneHotK{opaque_u16x2(0x00010001), opaque_u16x2((int)0xC080C080u), opaque_u16x2(0x3F803F80)};
+}
+__device__ __forceinline__ uint32_t onehot2_packed(uint32_t kk, uint32_t lq2, const OneHotK &c)
+{
+    const u16x2 d = __builtin_bit_cast(u16x2, kk ^ lq2);
+    const u16x2 m = __builtin_elementwise_min(d, c.one);
+    return __builtin_bit_cast(uint32_t, m * c.mul + c.add);
+}
+
 template <int ROWB, int COLB, int KT, int OCC>
 __global__ __launch_bounds__(256, OCC) void k_eval_mfma(const uint16_t *__restrict__ Whi,
                                                       const uint16_t *__restrict__ Wlo,
@@ -375,6 +402,10 @@ __device__ __forceinline__ void mfma_pipe_tile(const MfmaJob &J, int tile, u32x4
             lq[b] = 0xFFFFu;
         }
     }
+    uint32_t lq2[COLB];
+#pragma unroll
+    for (int b = 0; b < COLB; ++b) lq2[b] = lq[b] | (lq[b] << 16);
+    const OneHotK ohk = onehot_consts();
 
     const uint32_t ring_addr = (uint32_t)(uintptr_t)(lds_void *)ring;
     auto issue = [&](int kt) {
@@ -455,10 +486,10 @@ __device__ __forceinline__ void mfma_pipe_tile(const MfmaJob &J, int tile, u32x4
 #pragma unroll
             for (int b = 0; b < COLB; ++b) {
                 u32x4 bb;
-                bb.x = onehot2(kv[kk][b].x, lq[b]);
-                bb.y = onehot2(kv[kk][b].y, lq[b]);
-                bb.z = onehot2(kv[kk][b].z, lq[b]);
-                bb.w = onehot2(kv[kk][b].w, lq[b]);
+                bb.x = onehot2_packed(kv[kk][b].x, lq2[b], ohk);
+                bb.y = onehot2_packed(kv[kk][b].y, lq2[b], ohk);
+                bb.z = onehot2_packed(kv[kk][b].z, lq2[b], ohk);
+                bb.w = onehot2_packed(kv[kk][b].w, lq2[b], ohk);
                 bfrag[b] = __builtin_bit_cast(bf16x8, bb);
             }
 #pragma unroll
@@ -521,6 +552,10 @@ __device__ __forceinline__ void mfma_pipe_tile64(const MfmaJob &J, int tile, u32
             lq[b] = 0xFFFFu;
         }
     }
+    uint32_t lq2[COLB];
+#pragma unroll
+    for (int b = 0; b < COLB; ++b) lq2[b] = lq[b] | (lq[b] << 16);
+    const OneHotK ohk = onehot_consts();
 
     const uint32_t ring_addr = (uint32_t)(uintptr_t)(lds_void *)ring;
     auto issue = [&](int kt) {
@@ -616,10 +651,10 @@ __device__ __forceinline__ void mfma_pipe_tile64(const MfmaJob &J, int tile, u32
 #pragma unroll
             for (int b = 0; b < COLB; ++b) {
                 u32x4 bb;
-                bb.x = onehot2(kv[r][b].x, lq[b]);
-                bb.y = onehot2(kv[r][b].y, lq[b]);
-                bb.z = onehot2(kv[r][b].z, lq[b]);
-                bb.w = onehot2(kv[r][b].w, lq[b]);
+                bb.x = onehot2_packed(kv[r][b].x, lq2[b], ohk);
+                bb.y = onehot2_packed(kv[r][b].y, lq2[b], ohk);
+                bb.z = onehot2_packed(kv[r][b].z, lq2[b], ohk);
+                bb.w = onehot2_packed(kv[r][b].w, lq2[b], ohk);
                 bfrag[b] = __builtin_bit_cast(bf16x8, bb);
             }
             // column block by column block, so that the next block's one-hot
@@ -632,11 +667,11 @@ __device__ __forceinline__ void mfma_pipe_tile64(const MfmaJob &J, int tile, u32
                     for (int a = 0; a < ROWB; ++a)
                         acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
                             __builtin_bit_cast(bf16x8, af[r][m][a]), bfrag[b], acc[a][b], 0, 0, 0);
-            __builtin_amdgcn_sched_group_barrier(0x002, 24, 0);   // one-hot of block 0
+            __builtin_amdgcn_sched_group_barrier(0x002, 12, 0);   // one-hot of block 0
             static_for<COLB - 1>([&](auto) {
                 static_for<2 * ROWB>([&](auto) {
                     __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-                    __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);
                 });
             });
             __builtin_amdgcn_sched_group_barrier(0x008, 2 * ROWB, 0);
