@@ -334,7 +334,7 @@ def test_headline_workload_full_population_two_generations():
     benchmark's configuration: the trajectory equals the oracle's."""
     inst = I.clustered()
     st = oracle_trajectory(inst, 2, S=4096, m=64, n1=10, seed=1)
-    for cfg in (0, 7, 14, 16):
+    for cfg in (0, 7, 14, 16, 18):
         with make(inst, population=4096, island_size=64, n1=10, seed=1, precision="split_bf16") as s:
             s.set_tile_config(cfg)
             s.step(2)
