@@ -824,7 +824,9 @@ static const MfmaCfg kMfmaCfgs[] = {{4, 2, 32, 2, 0}, {4, 2, 64, 1, 0}, {4, 4, 3
                                     // K tiles of 64 with the rolling register pipeline
                                     {4, 2, 64, 2, 2}, {4, 2, 64, 1, 3},
                                     // ... and 128 x 512 workgroup tiles, one workgroup per CU
-                                    {4, 4, 64, 1, 3}, {4, 4, 64, 1, 2}};
+                                    {4, 4, 64, 1, 3}, {4, 4, 64, 1, 2},
+                                    // ... and 64 x 512 workgroup tiles, two workgroups per CU
+                                    {2, 4, 64, 2, 3}, {2, 4, 64, 2, 2}};
 constexpr int kNumMfmaCfgs = sizeof(kMfmaCfgs) / sizeof(kMfmaCfgs[0]);
 
 int mfma_num_configs() { return kNumMfmaCfgs; }
@@ -856,7 +858,9 @@ hipError_t launch_mfma(const DevPtrs &P, const Dims &d, const uint16_t *kidx, in
     case 16: return pipe_dispatch<4, 2, 2, 2, 2>(P, d, kidx, count, st);
     case 17: return pipe_dispatch<4, 2, 3, 1, 2>(P, d, kidx, count, st);
     case 18: return pipe_dispatch<4, 4, 3, 1, 2>(P, d, kidx, count, st);
-    default: return pipe_dispatch<4, 4, 2, 1, 2>(P, d, kidx, count, st);
+    case 19: return pipe_dispatch<4, 4, 2, 1, 2>(P, d, kidx, count, st);
+    case 20: return pipe_dispatch<2, 4, 3, 2, 2>(P, d, kidx, count, st);
+    default: return pipe_dispatch<2, 4, 2, 2, 2>(P, d, kidx, count, st);
     }
 }
 
@@ -958,6 +962,8 @@ hipError_t launch_mfma_group(const void *d_jobs, int njobs, int total, int cfg, 
     case 17: return group_dispatch<4, 2, 3, 1, 2>(kins, d_jobs, njobs, total, st);
     case 18: return group_dispatch<4, 4, 3, 1, 2>(kins, d_jobs, njobs, total, st);
     case 19: return group_dispatch<4, 4, 2, 1, 2>(kins, d_jobs, njobs, total, st);
+    case 20: return group_dispatch<2, 4, 3, 2, 2>(kins, d_jobs, njobs, total, st);
+    case 21: return group_dispatch<2, 4, 2, 2, 2>(kins, d_jobs, njobs, total, st);
     default: return hipErrorInvalidValue;
     }
 }
