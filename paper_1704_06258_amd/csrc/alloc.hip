@@ -171,8 +171,8 @@ __device__ __forceinline__ void alloc_body(const int32_t *__restrict__ hubs, int
 // fixed order by the cost assembly) and adds its cluster sizes into cnt
 // (zeroed by the operators).
 constexpr int kIslandKids = 16;
-constexpr int kTop = 5;
-constexpr int kMaxAdd = 4;   // children of a generation add one to three hubs
+constexpr int kTop = 6;
+constexpr int kMaxAdd = 8;
 
 __host__ __device__ inline int island_quarters(int m) { return (m + kIslandKids - 1) / kIslandKids; }
 __host__ __device__ inline int island_chunks(int n_pad) { return (n_pad + 255) / 256; }
@@ -309,9 +309,9 @@ __device__ __forceinline__ void alloc_island_body(const int32_t *__restrict__ an
         Oi = O[i];
         Di = D[i];
     }
-    // the added hubs' distances, one child ahead (two register sets)
-    float va[2][kMaxAdd];
-    double vx[2][kMaxAdd];
+    // the added hubs' distances, one child ahead
+    float va[kMaxAdd];
+    double vx[kMaxAdd];
     auto fetch = [&](int j, float *fa, double *fx) {
         const int na = sNAdd[j];
 #pragma unroll
@@ -322,19 +322,23 @@ __device__ __forceinline__ void alloc_island_body(const int32_t *__restrict__ an
                 fx[e] = (double)Ct[(size_t)h * n + i];
             }
     };
-    if (nk > 0) fetch(0, va[0], vx[0]);
+    if (nk > 0) fetch(0, va, vx);
     for (int g0 = 0; g0 < nk; g0 += G) {
-#pragma unroll
-        for (int jj = 0; jj < G; ++jj) {   // G even: child j uses register set j & 1
+        for (int jj = 0; jj < G; ++jj) {
             const int j = g0 + jj;
             if (j >= nk) {
                 sP[0][jj][tid] = 0.0;
                 sP[1][jj][tid] = 0.0;
                 continue;
             }
-            const float *ca = va[jj & 1];
-            const double *cx = vx[jj & 1];
-            if (j + 1 < nk) fetch(j + 1, va[(jj + 1) & 1], vx[(jj + 1) & 1]);
+            float ca[kMaxAdd];
+            double cx[kMaxAdd];
+#pragma unroll
+            for (int e = 0; e < kMaxAdd; ++e) {
+                ca[e] = va[e];
+                cx[e] = vx[e];
+            }
+            if (j + 1 < nk) fetch(j + 1, va, vx);
             if (!live) {
                 if (i < n_pad) kidx[(size_t)(s0 + j) * n_pad + i] = kNoHub;
                 sP[0][jj][tid] = 0.0;
