@@ -178,40 +178,23 @@ __host__ __device__ inline int island_quarters(int m) { return (m + kIslandKids 
 __host__ __device__ inline int island_chunks(int n_pad) { return (n_pad + 255) / 256; }
 __host__ __device__ inline int island_units(int R, int m, int n_pad) { return R * island_quarters(m) * island_chunks(n_pad); }
 
-constexpr int kIslandRound = 4;   // children per reduction round
-
-// LDS of one island-allocation workgroup (declared once per kernel).
-struct IslandLds {
-    int A[kMaxP];
-    int K[kIslandKids][kMaxP];
-    unsigned long long Rem[kIslandKids];
-    int Add[kIslandKids][kMaxAdd];      // added hub ids, ascending
-    int AddPos[kIslandKids][kMaxAdd];   // their positions in the child's list
-    int NAdd[kIslandKids];
-    int Cnt[kIslandKids][kMaxP];
-    double P[2][kIslandRound][256];
-    double Seg[2][kIslandKids][32];
-};
-
 template <typename CT>
 __device__ __forceinline__ void alloc_island_body(const int32_t *__restrict__ anc, const int32_t *__restrict__ kids,
                                                   int R, int m, int n, int n_pad, int p, const CT *__restrict__ Ct,
                                                   const float *__restrict__ Ct32, const double *__restrict__ O,
                                                   const double *__restrict__ D, uint16_t *__restrict__ kidx,
                                                   double *__restrict__ part_cd, int32_t *__restrict__ cnt,
-                                                  float *__restrict__ Ch32, int blk, IslandLds &L)
+                                                  float *__restrict__ Ch32, int blk)
 {
 #pragma clang fp contract(off)
-    constexpr int G = kIslandRound;
-    auto &sA = L.A;
-    auto &sK = L.K;
-    auto &sRem = L.Rem;
-    auto &sAdd = L.Add;
-    auto &sAddPos = L.AddPos;
-    auto &sNAdd = L.NAdd;
-    auto &sCnt = L.Cnt;
-    auto &sP = L.P;
-    auto &sSeg = L.Seg;
+    __shared__ int sA[kMaxP];
+    __shared__ int sK[kIslandKids][kMaxP];
+    __shared__ unsigned long long sRem[kIslandKids];
+    __shared__ int sAdd[kIslandKids][kMaxAdd];
+    __shared__ int sNAdd[kIslandKids];
+    __shared__ int sCnt[kIslandKids][kMaxP];
+    __shared__ double sP[2][kIslandKids][256];
+    __shared__ double sSeg[2][kIslandKids][8];
     const int nq = island_quarters(m), nch = island_chunks(n_pad);
     const int units = R * nq * nch;
     const int per = (units + 7) / 8;
@@ -240,10 +223,7 @@ __device__ __forceinline__ void alloc_island_body(const int32_t *__restrict__ an
                 rem |= 1ull << a;
                 ++a;
             } else {
-                if (na < kMaxAdd) {
-                    sAdd[tid][na] = y;
-                    sAddPos[tid][na] = b;
-                }
+                if (na < kMaxAdd) sAdd[tid][na] = y;
                 ++na;
                 ++b;
             }
@@ -254,20 +234,16 @@ __device__ __forceinline__ void alloc_island_body(const int32_t *__restrict__ an
     __syncthreads();
 
     const int i = c * 256 + tid;
-    const bool live = i < n;
-    // the ancestor's kTop nearest hubs (FP32 distance, then position)
-    float tv[kTop];
-    int tp[kTop];
+    if (i < n) {
+        // the ancestor's kTop nearest hubs (FP32 distance, then position)
+        float tv[kTop];
+        int tp[kTop];
 #pragma unroll
-    for (int t = 0; t < kTop; ++t) {
-        tv[t] = __builtin_huge_valf();
-        tp[t] = -1;
-    }
-    bool amb = false;
-    int selfA = -1;
-    double ex[kTop];
-    double Oi = 0.0, Di = 0.0;
-    if (live) {
+        for (int t = 0; t < kTop; ++t) {
+            tv[t] = __builtin_huge_valf();
+            tp[t] = -1;
+        }
+        bool amb = false;
         for (int k0 = 0; k0 < p; k0 += kScanChunk) {
             float v[kScanChunk];
 #pragma unroll
@@ -292,68 +268,40 @@ __device__ __forceinline__ void alloc_island_body(const int32_t *__restrict__ an
                 }
             }
         }
-        int lo = 0, hi = p - 1;   // node i among the ancestor's hubs
-        while (lo <= hi) {
-            const int mid = (lo + hi) >> 1, hv = sA[mid];
-            if (hv == i) {
-                selfA = mid;
-                break;
+        // node i among the ancestor's hubs
+        int selfA = -1;
+        {
+            int lo = 0, hi = p - 1;
+            while (lo <= hi) {
+                const int mid = (lo + hi) >> 1, hv = sA[mid];
+                if (hv == i) {
+                    selfA = mid;
+                    break;
+                }
+                if (hv < i)
+                    lo = mid + 1;
+                else
+                    hi = mid - 1;
             }
-            if (hv < i)
-                lo = mid + 1;
-            else
-                hi = mid - 1;
         }
+        double ex[kTop];
 #pragma unroll
         for (int t = 0; t < kTop; ++t) ex[t] = tp[t] >= 0 ? (double)Ct[(size_t)sA[tp[t]] * n + i] : 0.0;
-        Oi = O[i];
-        Di = D[i];
-    }
-    // the added hubs' distances, one child ahead
-    float va[kMaxAdd];
-    double vx[kMaxAdd];
-    auto fetch = [&](int j, float *fa, double *fx) {
-        const int na = sNAdd[j];
-#pragma unroll
-        for (int e = 0; e < kMaxAdd; ++e)
-            if (live && e < na) {
-                const int h = sAdd[j][e];
-                fa[e] = Ct32[(size_t)h * n + i];
-                fx[e] = (double)Ct[(size_t)h * n + i];
-            }
-    };
-    if (nk > 0) fetch(0, va, vx);
-    for (int g0 = 0; g0 < nk; g0 += G) {
-        for (int jj = 0; jj < G; ++jj) {
-            const int j = g0 + jj;
-            if (j >= nk) {
-                sP[0][jj][tid] = 0.0;
-                sP[1][jj][tid] = 0.0;
-                continue;
-            }
-            float ca[kMaxAdd];
-            double cx[kMaxAdd];
-#pragma unroll
-            for (int e = 0; e < kMaxAdd; ++e) {
-                ca[e] = va[e];
-                cx[e] = vx[e];
-            }
-            if (j + 1 < nk) fetch(j + 1, va, vx);
-            if (!live) {
-                if (i < n_pad) kidx[(size_t)(s0 + j) * n_pad + i] = kNoHub;
-                sP[0][jj][tid] = 0.0;
-                sP[1][jj][tid] = 0.0;
-                continue;
-            }
+        const double Oi = O[i], Di = D[i];
+        for (int j = 0; j < nk; ++j) {
             const unsigned long long rem = sRem[j];
             const int na = sNAdd[j];
-            int pos = -1;        // the winner's position in the child's list
-            double wex = 0.0;    // its exact distance
+            int wh = -1;          // winning hub id
+            double wex = 0.0;     // its exact distance
             bool plain = amb || na < 0;
             if (!plain) {
-                if (selfA >= 0 && !((rem >> selfA) & 1ull)) {   // a kept ancestor hub: itself
-                    pos = selfA - __popcll(rem & ((1ull << selfA) - 1ull));
-                    for (int e = 0; e < na; ++e) pos += sAdd[j][e] < i ? 1 : 0;
+                if (selfA >= 0 && !((rem >> selfA) & 1ull)) {
+                    wh = i;
+                } else {
+                    for (int e = 0; e < na; ++e)
+                        if (sAdd[j][e] == i) wh = i;
+                }
+                if (wh == i) {
                     wex = (double)Ct[(size_t)i * n + i];
                 } else {
                     int t0 = -1;
@@ -364,41 +312,30 @@ __device__ __forceinline__ void alloc_island_body(const int32_t *__restrict__ an
                         plain = true;
                     } else {
                         float wv = tv[0];
-                        int wp = tp[0];
                         wex = ex[0];
 #pragma unroll
                         for (int t = 1; t < kTop; ++t)
                             if (t == t0) {
                                 wv = tv[t];
-                                wp = tp[t];
                                 wex = ex[t];
                             }
-                        const int wh = sA[wp];
-                        int wadd = -1;
-#pragma unroll
-                        for (int e = 0; e < kMaxAdd; ++e)
-                            if (e < na) {
-                                if (sAdd[j][e] == i) {   // an added hub: itself
-                                    wadd = e;
-                                    wex = (double)Ct[(size_t)i * n + i];
-                                    wv = -__builtin_huge_valf();
-                                } else if (ca[e] < wv) {
-                                    wv = ca[e];
-                                    wadd = e;
-                                    wex = cx[e];
-                                } else if (ca[e] == wv) {
-                                    plain = true;
-                                }
+                        wh = sA[tp[t0]];
+                        for (int e = 0; e < na; ++e) {
+                            const int h = sAdd[j][e];
+                            const float v = Ct32[(size_t)h * n + i];
+                            if (v < wv) {
+                                wv = v;
+                                wh = h;
+                                wex = -1.0;   // loaded below
+                            } else if (v == wv) {
+                                plain = true;
                             }
-                        if (wadd >= 0) {
-                            pos = sAddPos[j][wadd];
-                        } else {   // kept ancestor hub at position wp
-                            pos = wp - __popcll(rem & ((1ull << wp) - 1ull));
-                            for (int e = 0; e < na; ++e) pos += sAdd[j][e] < wh ? 1 : 0;
                         }
+                        if (!plain && wex < 0.0) wex = (double)Ct[(size_t)wh * n + i];
                     }
                 }
             }
+            int pos;
             if (plain) {   // the rule itself: self, else strict minimum in the instance dtype
                 pos = -1;
                 int lo = 0, hi = p - 1;
@@ -427,30 +364,52 @@ __device__ __forceinline__ void alloc_island_body(const int32_t *__restrict__ an
                 } else {
                     wex = (double)Ct[(size_t)i * n + i];
                 }
+            } else {   // position of the winning hub in the child's sorted list
+                int lo = 0, hi = p - 1;
+                pos = 0;
+                while (lo <= hi) {
+                    const int mid = (lo + hi) >> 1, hv = sK[j][mid];
+                    if (hv == wh) {
+                        pos = mid;
+                        break;
+                    }
+                    if (hv < wh)
+                        lo = mid + 1;
+                    else
+                        hi = mid - 1;
+                }
             }
             kidx[(size_t)(s0 + j) * n_pad + i] = (uint16_t)pos;
             atomicAdd(&sCnt[j][pos], 1);
-            sP[0][jj][tid] = Oi * wex;
-            sP[1][jj][tid] = Di * wex;
+            sP[0][j][tid] = Oi * wex;
+            sP[1][j][tid] = Di * wex;
         }
-        __syncthreads();
-        {   // 32 segments of 8 nodes per child and quantity, in node order
-            const int qq = tid >> 7, jj = (tid >> 5) & 3, g = tid & 31;
-            double acc = 0.0;
-            for (int e = 0; e < 8; ++e) acc = acc + sP[qq][jj][g * 8 + e];
-            if (g0 + jj < nk) sSeg[qq][g0 + jj][g] = acc;
+    } else {
+        for (int j = 0; j < nk; ++j) {
+            if (i < n_pad) kidx[(size_t)(s0 + j) * n_pad + i] = kNoHub;
+            sP[0][j][tid] = 0.0;
+            sP[1][j][tid] = 0.0;
         }
-        __syncthreads();
+    }
+    __syncthreads();
+    // {Cc, Dd} partials of the chunk in a fixed order: 8 segments of 32 nodes
+    {
+        const int qq = tid >> 7, j = (tid >> 3) & 15, g = tid & 7;
+        double acc = 0.0;
+        if (j < nk)
+            for (int e = 0; e < 32; ++e) acc = acc + sP[qq][j][g * 32 + e];
+        sSeg[qq][j][g] = acc;
     }
     if (c == 0)   // FP32 hub-to-hub distances of the children: C[h_k][h_l]
         for (int e = tid; e < nk * p * p; e += 256) {
             const int j = e / (p * p), kl = e % (p * p);
             Ch32[(size_t)(s0 + j) * p * p + kl] = (float)Ct[(size_t)sK[j][kl % p] * n + sK[j][kl / p]];
         }
+    __syncthreads();
     if (tid < 2 * nk) {
         const int qq = tid / nk, j = tid % nk;
         double acc = 0.0;
-        for (int g = 0; g < 32; ++g) acc = acc + sSeg[qq][j][g];
+        for (int g = 0; g < 8; ++g) acc = acc + sSeg[qq][j][g];
         part_cd[((size_t)(s0 + j) * nch + c) * 2 + qq] = acc;
     }
     for (int e = tid; e < nk * p; e += 256) {
@@ -468,23 +427,21 @@ __global__ __launch_bounds__(256) void k_alloc_island(const int32_t *__restrict_
                                                       double *__restrict__ part_cd, int32_t *__restrict__ cnt,
                                                       float *__restrict__ Ch32)
 {
-    __shared__ IslandLds L;
-    alloc_island_body<CT>(anc, kids, R, m, n, n_pad, p, Ct, Ct32, O, D, kidx, part_cd, cnt, Ch32, blockIdx.x, L);
+    alloc_island_body<CT>(anc, kids, R, m, n, n_pad, p, Ct, Ct32, O, D, kidx, part_cd, cnt, Ch32, blockIdx.x);
 }
 
 __global__ __launch_bounds__(256) void k_alloc_island_group(const TickJob *__restrict__ jobs, int njobs)
 {
-    __shared__ IslandLds L;
     const TickJob &J = jobs[tick_job(jobs, njobs, kTickAlloc, blockIdx.x)];
     const int blk = blockIdx.x - J.start[kTickAlloc];
     const DevPtrs &P = J.P;
     const Dims &d = J.d;
     if (d.c_f32)
         alloc_island_body<float>(P.anc, P.hubs, d.R, d.m, d.n, d.n_pad, d.p, (const float *)P.Ct, P.Ct32, P.O, P.D,
-                                 P.kidx, P.part_cd, P.cnt, P.Ch32, blk, L);
+                                 P.kidx, P.part_cd, P.cnt, P.Ch32, blk);
     else
         alloc_island_body<double>(P.anc, P.hubs, d.R, d.m, d.n, d.n_pad, d.p, (const double *)P.Ct, P.Ct32, P.O,
-                                  P.D, P.kidx, P.part_cd, P.cnt, P.Ch32, blk, L);
+                                  P.D, P.kidx, P.part_cd, P.cnt, P.Ch32, blk);
 }
 
 int alloc_island_blocks(const Dims &d) { return ((island_units(d.R, d.m, d.n_pad) + 7) / 8) * 8; }
