@@ -34,8 +34,6 @@ struct DevPtrs {
     int32_t *cmax;      // S largest cluster size
     float *Ch32;        // S*p*p hub-to-hub distances (split mode)
     double *partial;    // S*p*(n_pad/64) epilogue partials (split mode), [column][row tile]
-    double *part_cd;    // S*(n_pad/256)*2 per node chunk {Cc, Dd} partials of a generation (split mode)
-    int32_t *cnt;       // S*p cluster sizes of a generation's children (split mode)
     // GA state
     int32_t *anc;       // R*p
     double *anc_cost;   // R

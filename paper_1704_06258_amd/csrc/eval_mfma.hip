@@ -725,15 +725,10 @@ __global__ __launch_bounds__(256, OCC) void k_eval_mfma_pipe_group(const MfmaJob
 // T_s = sum of the individual's p*n_mt partials (contiguous), one wave per
 // individual with a fixed reduction order; cost assembly
 // f = ((chi*Cc) + (alpha*T)) + (delta*Dd) and its relative error bound.
-// With part_cd (a generation's island allocation): Cc and Dd are the sums of
-// the per node-chunk partials in chunk order and cmax the largest of the
-// cluster sizes in cnt; else both come from parts / cmax.
 __device__ __forceinline__ void finalize_body(const double *__restrict__ partial, const int32_t *__restrict__ cmax,
                                               int count, int p, int n_mt, int n, int c_f32, double chi, double alpha,
                                               double delta, double scale, double *__restrict__ cost,
-                                              double *__restrict__ parts, double *__restrict__ eps, int blk,
-                                              const double *__restrict__ part_cd = nullptr,
-                                              const int32_t *__restrict__ cnt = nullptr, int nch = 0)
+                                              double *__restrict__ parts, double *__restrict__ eps, int blk)
 {
     const int s = blk * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -746,29 +741,12 @@ __device__ __forceinline__ void finalize_body(const double *__restrict__ partial
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
     if (lane == 0) {
         const double T = v;
-        double Cc, Dd;
-        int cm;
-        if (part_cd) {
-            Cc = 0.0;
-            Dd = 0.0;
-            for (int c = 0; c < nch; ++c) {
-                Cc = Cc + part_cd[((size_t)s * nch + c) * 2];
-                Dd = Dd + part_cd[((size_t)s * nch + c) * 2 + 1];
-            }
-            cm = 0;
-            for (int k = 0; k < p; ++k) cm = max(cm, cnt[(size_t)s * p + k]);
-            parts[3 * (size_t)s] = Cc;
-            parts[3 * (size_t)s + 2] = Dd;
-        } else {
-            Cc = parts[3 * (size_t)s];
-            Dd = parts[3 * (size_t)s + 2];
-            cm = cmax[s];
-        }
+        const double Cc = parts[3 * (size_t)s], Dd = parts[3 * (size_t)s + 2];
         parts[3 * (size_t)s + 1] = T;
         cost[s] = (((chi * Cc) + (alpha * T)) + (delta * Dd)) * scale;
         // split residual + FP32 accumulation of at most 2*cmax non-zero addends
         // per output (any faithful rounding) + FP32 hub distances + binary64 sums
-        eps[s] = kSplitResidual + gamma_k(2.0 * cm, kU32Faithful) + (c_f32 ? 0.0 : kU32) +
+        eps[s] = kSplitResidual + gamma_k(2.0 * cmax[s], kU32Faithful) + (c_f32 ? 0.0 : kU32) +
                  gamma_k((double)n + (double)len + 8.0, kU64) + gamma_k(n + 2.0, kU64) + gamma_k(8.0, kU64) + 1e-9;
     }
 }
@@ -788,19 +766,7 @@ __global__ __launch_bounds__(256) void k_finalize_group(const TickJob *__restric
     const DevPtrs &P = J.P;
     const Dims &d = J.d;
     finalize_body(P.partial, P.cmax, d.S, d.p, J.n_mt, d.n, d.c_f32, d.chi, d.alpha, d.delta, d.scale, P.cost,
-                  P.parts, P.eps, blockIdx.x - J.start[kTickFinal], P.part_cd, P.cnt, (d.n_pad + 255) / 256);
-}
-
-// The cost assembly of a generation after the island allocation.
-__global__ __launch_bounds__(256) void k_finalize_island(double *__restrict__ partial, const int32_t *__restrict__ cnt,
-                                                         const double *__restrict__ part_cd, int count, int p,
-                                                         int n_mt, int n, int nch, int c_f32, double chi,
-                                                         double alpha, double delta, double scale,
-                                                         double *__restrict__ cost, double *__restrict__ parts,
-                                                         double *__restrict__ eps)
-{
-    finalize_body(partial, nullptr, count, p, n_mt, n, c_f32, chi, alpha, delta, scale, cost, parts, eps, blockIdx.x,
-                  part_cd, cnt, nch);
+                  P.parts, P.eps, blockIdx.x - J.start[kTickFinal]);
 }
 
 template <int ROWB, int COLB, int KT, int OCC>
@@ -916,15 +882,6 @@ hipError_t launch_finalize(const DevPtrs &P, const Dims &d, int count, int cfg, 
 }
 
 int finalize_blocks(int count) { return (count + 3) / 4; }
-
-hipError_t launch_finalize_island(const DevPtrs &P, const Dims &d, int cfg, hipStream_t st)
-{
-    const int n_mt = mfma_partial_tiles(d, cfg);
-    k_finalize_island<<<finalize_blocks(d.S), 256, 0, st>>>(P.partial, P.cnt, P.part_cd, d.S, d.p, n_mt, d.n,
-                                                             (d.n_pad + 255) / 256, d.c_f32, d.chi, d.alpha, d.delta,
-                                                             d.scale, P.cost, P.parts, P.eps);
-    return hipGetLastError();
-}
 
 hipError_t launch_finalize_group(const TickJob *jobs, int njobs, int blocks, hipStream_t st)
 {

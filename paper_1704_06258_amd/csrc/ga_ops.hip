@@ -72,7 +72,7 @@ __device__ __forceinline__ void wave_swap(int n, WList &x, int &cnt, uint64_t w_
 // Workgroup blk of a context: children 4*blk .. 4*blk+3, one per wave.
 __device__ __forceinline__ void ga_ops_body(const int32_t *__restrict__ anc, int32_t *__restrict__ children,
                                             const int64_t *__restrict__ gen, int n, int p, int S, int m,
-                                            uint64_t seed, int blk, int32_t *__restrict__ csize)
+                                            uint64_t seed, int blk)
 {
     __shared__ int lists[4][3][128];   // per wave: parent a, parent b, child
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -122,29 +122,26 @@ __device__ __forceinline__ void ga_ops_body(const int32_t *__restrict__ anc, int
         wave_edit(cx, cnt, -1, wave_nth_spoke(cx, cnt, uindex(w.x[0], n - cnt), lane), lane);
     }
     if (lane < p) children[(size_t)s * p + lane] = cx.a[lane];
-    if (csize && lane < p) csize[(size_t)s * p + lane] = 0;   // cluster sizes, counted by the island allocation
 }
 
 __global__ __launch_bounds__(256) void k_ga_ops(const int32_t *__restrict__ anc, int32_t *__restrict__ children,
                                                 const int64_t *__restrict__ gen, int n, int p, int S, int m,
-                                                uint64_t seed, int32_t *__restrict__ cnt)
+                                                uint64_t seed)
 {
-    ga_ops_body(anc, children, gen, n, p, S, m, seed, blockIdx.x, cnt);
+    ga_ops_body(anc, children, gen, n, p, S, m, seed, blockIdx.x);
 }
 
 __global__ __launch_bounds__(256) void k_ga_ops_group(const TickJob *__restrict__ jobs, int njobs)
 {
     const TickJob &J = jobs[tick_job(jobs, njobs, kTickOps, blockIdx.x)];
-    ga_ops_body(J.P.anc, J.P.hubs, J.P.gen, J.d.n, J.d.p, J.d.S, J.d.m, J.d.seed, blockIdx.x - J.start[kTickOps],
-                J.P.cnt);
+    ga_ops_body(J.P.anc, J.P.hubs, J.P.gen, J.d.n, J.d.p, J.d.S, J.d.m, J.d.seed, blockIdx.x - J.start[kTickOps]);
 }
 
 int ga_ops_blocks(const Dims &d) { return (d.S + 3) / 4; }
 
 hipError_t launch_ga_ops(const DevPtrs &P, const Dims &d, hipStream_t st)
 {
-    k_ga_ops<<<ga_ops_blocks(d), 256, 0, st>>>(P.anc, P.hubs, P.gen, d.n, d.p, d.S, d.m, d.seed,
-                                               d.prec == kSplitBF16 ? P.cnt : nullptr);
+    k_ga_ops<<<ga_ops_blocks(d), 256, 0, st>>>(P.anc, P.hubs, P.gen, d.n, d.p, d.S, d.m, d.seed);
     return hipGetLastError();
 }
 

@@ -88,7 +88,7 @@ Dims make_dims(const ga_params *q, ga_dtype cdt, ga_dtype wdt)
 
 // Offsets of every device buffer; the same walk sizes and carves.
 struct Carve {
-    size_t C, Ct, Ct32, W, W32, Whi, Wlo, Whsw, Wlsw, O, D, dsum, hubs, kidx, cost, parts, eps, cmax, Ch32, partial, part_cd, cnt, anc, anc_cost,
+    size_t C, Ct, Ct32, W, W32, Whi, Wlo, Whsw, Wlsw, O, D, dsum, hubs, kidx, cost, parts, eps, cmax, Ch32, partial, anc, anc_cost,
         anc_parts, best, best_cost, gen, stats, cand, cand_cnt, cand_cost, cand_parts, kidx_one, scratch, tbuf, slot_r, slot_c, handled, total_slots, extra_r, extra_c, nextra, sync;
     size_t total;
 };
@@ -120,8 +120,6 @@ Carve carve(const Dims &d, int c_symmetric)
     c.cmax = L.take((size_t)d.S * 4);
     c.Ch32 = split ? L.take((size_t)d.S * d.p * d.p * 4) : (size_t)-1;
     c.partial = split ? L.take((size_t)d.n_mtiles * d.S * d.p * 8) : (size_t)-1;
-    c.part_cd = split ? L.take((size_t)d.S * ((d.n_pad + 255) / 256) * 16) : (size_t)-1;
-    c.cnt = split ? L.take((size_t)d.S * d.p * 4) : (size_t)-1;
     c.anc = L.take((size_t)d.R * d.p * 4);
     c.anc_cost = L.take((size_t)d.R * 8);
     c.anc_parts = L.take((size_t)d.R * 24);
@@ -268,18 +266,8 @@ ga_status run_generation(ga_ctx *ctx, hipStream_t s)
     const Dims &d = ctx->d;
     const DevPtrs &P = ctx->P;
     HIPCHK(launch_ga_ops(P, d, s));
-    if (d.prec == kSplitBF16) {   // children of island ancestors: the island allocation
-        HIPCHK(launch_alloc_island(P, d, s));
-        hipEvent_t a, b;
-        prof_events(ctx, &a, &b);
-        if (a) HIPCHK(hipEventRecord(a, s));
-        HIPCHK(launch_mfma(P, d, P.kidx, d.S, s));
-        if (b) HIPCHK(hipEventRecord(b, s));
-        HIPCHK(launch_finalize_island(P, d, d.mfma_cfg, s));
-    } else {
-        ga_status st = run_eval(ctx, P.hubs, d.S, P.kidx, s);
-        if (st != GA_OK) return st;
-    }
+    ga_status st = run_eval(ctx, P.hubs, d.S, P.kidx, s);
+    if (st != GA_OK) return st;
     HIPCHK(launch_select(P, d, d.prec == kFP64, s));
     return GA_OK;
 }
@@ -482,8 +470,6 @@ ga_status ga_init(const ga_params *q, const void *C, ga_dtype cdt, const void *W
         P.cmax = at<int32_t>(b, c.cmax);
         P.Ch32 = at<float>(b, c.Ch32);
         P.partial = at<double>(b, c.partial);
-        P.part_cd = at<double>(b, c.part_cd);
-        P.cnt = at<int32_t>(b, c.cnt);
         P.anc = at<int32_t>(b, c.anc);
         P.anc_cost = at<double>(b, c.anc_cost);
         P.anc_parts = at<double>(b, c.anc_parts);
@@ -884,7 +870,7 @@ ga_status ga_batch_set(ga_batch *b, ga_ctx *const *ctxs, int32_t count)
         J.d = d;
         J.n_mt = mfma_partial_tiles(d, b->cfg);
         J.blocks[kTickOps] = ga_ops_blocks(d);
-        J.blocks[kTickAlloc] = alloc_island_blocks(d);   // a multiple of 8: every context starts on XCD 0
+        J.blocks[kTickAlloc] = alloc_blocks(d.S);   // a multiple of 8: every context starts on XCD 0
         J.blocks[kTickFinal] = finalize_blocks(d.S);
         J.blocks[kTickSel1] = d.R;
         J.blocks[kTickCols] = kTickColsBlocks;
@@ -987,7 +973,7 @@ ga_status ga_batch_step(ga_batch *b, int32_t generations)
         if (nj) {
             if ((e = launch_ga_ops_group(tjobs, nj, b->blocks[kTickOps], b->st)) != hipSuccess)
                 return dev_fail(e, "grouped operators");
-            if ((e = launch_alloc_island_group(tjobs, nj, b->blocks[kTickAlloc], b->st)) != hipSuccess)
+            if ((e = launch_alloc_group(tjobs, nj, b->blocks[kTickAlloc], b->st)) != hipSuccess)
                 return dev_fail(e, "grouped allocation");
             if ((e = launch_mfma_group(mjobs, nj, b->total_tiles, b->cfg, b->min_p, b->st)) != hipSuccess)
                 return dev_fail(e, "grouped matrix-core evaluation");

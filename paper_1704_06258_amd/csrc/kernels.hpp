@@ -14,9 +14,6 @@ hipError_t launch_alloc(const DevPtrs &P, const Dims &d, const int32_t *hubs, in
                         int want_sums, int want_ch, hipStream_t st);
 hipError_t launch_copy_clamp(const int32_t *src, int32_t *dst, int total, int n, hipStream_t st);
 int alloc_blocks(int count);
-int alloc_island_blocks(const Dims &d);
-hipError_t launch_alloc_island(const DevPtrs &P, const Dims &d, hipStream_t st);
-hipError_t launch_alloc_island_group(const TickJob *jobs, int njobs, int blocks, hipStream_t st);
 hipError_t launch_alloc_group(const TickJob *jobs, int njobs, int blocks, hipStream_t st);
 
 // per-individual evaluation (eval_plain.hip)
@@ -40,7 +37,6 @@ hipError_t launch_mfma(const DevPtrs &P, const Dims &d, const uint16_t *kidx, in
 hipError_t launch_finalize(const DevPtrs &P, const Dims &d, int count, int cfg, hipStream_t st);
 int mfma_partial_tiles(const Dims &d, int cfg);
 int finalize_blocks(int count);
-hipError_t launch_finalize_island(const DevPtrs &P, const Dims &d, int cfg, hipStream_t st);
 hipError_t launch_finalize_group(const TickJob *jobs, int njobs, int blocks, hipStream_t st);
 bool mfma_groupable(const Dims &d, int cfg);
 size_t mfma_job_bytes();
