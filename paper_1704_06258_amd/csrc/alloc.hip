@@ -13,10 +13,13 @@
 
 namespace hubga {
 
-constexpr int kAllocPer = 1;     // individuals per workgroup
 constexpr int kScanChunk = 16;   // hub distances loaded together by one lane
 
-// Workgroup blk (of a grid of alloc_blocks(count)) of one context.
+// Workgroup blk (of a grid of alloc_blocks(count)) of one context: individual
+// s = the workgroup's place in XCD-major order.  The hub ids are read with
+// scalar loads (the same for every lane), so each distance load needs no
+// per-lane address arithmetic and no LDS round trip; a node-to-position table
+// in LDS answers "is node i a hub" with one read.
 template <typename CT>
 __device__ __forceinline__ void alloc_body(const int32_t *__restrict__ hubs, int count, int n, int n_pad, int p,
                                            const CT *__restrict__ Ct, const float *__restrict__ Ct32,
@@ -26,52 +29,61 @@ __device__ __forceinline__ void alloc_body(const int32_t *__restrict__ hubs, int
                                            int blk)
 {
 #pragma clang fp contract(off)
-    __shared__ int sh_h[kAllocPer][kMaxP];
-    __shared__ int sh_cnt[kAllocPer][kMaxP];
-    __shared__ double red_c[kAllocPer][256], red_d[kAllocPer][256];
-    // XCD-major group order: consecutive groups (children of one island) run
+    __shared__ int sh_h[kMaxP];
+    __shared__ int sh_cnt[kMaxP];
+    __shared__ uint8_t sh_pos[kMaxN];   // position of node i in the hub list, 0xFF for spokes
+    __shared__ double red_c[256], red_d[256];
+    // XCD-major order: consecutive individuals (children of one island) run
     // on the same XCD (workgroup index % 8; a grouped launch starts every
     // context on a multiple of 8) and share its L2.
-    const int groups = (count + kAllocPer - 1) / kAllocPer;
-    const int per = (groups + 7) / 8;
-    const int grp = (blk & 7) * per + (blk >> 3);
-    if (grp >= groups) return;
-    const int s0 = grp * kAllocPer;
-    const int nind = min(kAllocPer, count - s0);
+    const int per = (count + 7) / 8;
+    const int s = (blk & 7) * per + (blk >> 3);
+    if (s >= count) return;
     const int tid = threadIdx.x;
-    for (int e = tid; e < kAllocPer * kMaxP; e += 256) {
-        const int c = e / kMaxP, k = e % kMaxP;
-        sh_cnt[c][k] = 0;
-        if (c < nind && k < p) sh_h[c][k] = hubs[(size_t)(s0 + c) * p + k];
+    const int32_t *__restrict__ hrow = hubs + (size_t)s * p;
+    for (int e = tid; e < n; e += 256) sh_pos[e] = 0xFF;
+    if (tid < kMaxP) sh_cnt[tid] = 0;
+    __syncthreads();
+    if (tid < p) {
+        const int h = hrow[tid];
+        sh_h[tid] = h;
+        sh_pos[h] = (uint8_t)tid;
     }
     __syncthreads();
-    double pc[kAllocPer], pd[kAllocPer];
-#pragma unroll
-    for (int c = 0; c < kAllocPer; ++c) pc[c] = pd[c] = 0.0;
+    double pc = 0.0, pd = 0.0;
+    uint16_t *krow = kidx + (size_t)s * n_pad;
     for (int i = tid; i < n_pad; i += 256) {
-#pragma unroll
-        for (int c = 0; c < kAllocPer; ++c) {
-            if (c >= nind) break;
-            uint16_t *krow = kidx + (size_t)(s0 + c) * n_pad;
-            if (i >= n) {
-                krow[i] = kNoHub;
-                continue;
-            }
-            const int *h = sh_h[c];
+        if (i >= n) {
+            krow[i] = kNoHub;
+            continue;
+        }
+        int best;
+        const int self = sh_pos[i];
+        if (self != 0xFF) {   // a hub keeps itself
+            best = self;
+        } else {
             // Scan in FP32: rounding to FP32 is monotone, so a unique FP32
             // minimum is also the unique minimum of the instance values.  When
             // several hubs share the FP32 minimum, rescan in the instance
             // dtype (strict <, ties to the smaller hub id).
-            // The p loads of a chunk are issued before any comparison (a
-            // compare-as-you-load loop waits for every load in turn).
-            int best = 0;
+            best = 0;
             float bd = __builtin_huge_valf();
             bool tie = false;
             for (int k0 = 0; k0 < p; k0 += kScanChunk) {
                 float v[kScanChunk];
+                if (k0 + kScanChunk <= p) {   // whole chunk: the hub ids load as one scalar block
 #pragma unroll
-                for (int u = 0; u < kScanChunk; ++u)
-                    v[u] = k0 + u < p ? Ct32[(size_t)h[k0 + u] * n + i] : __builtin_huge_valf();
+                    for (int u = 0; u < kScanChunk; ++u) {
+                        const float *row = Ct32 + (size_t)hrow[k0 + u] * n;
+                        v[u] = row[i];
+                    }
+                } else {
+#pragma unroll
+                    for (int u = 0; u < kScanChunk; ++u) {
+                        const float *row = Ct32 + (size_t)hrow[min(k0 + u, p - 1)] * n;
+                        v[u] = k0 + u < p ? row[i] : __builtin_huge_valf();
+                    }
+                }
 #pragma unroll
                 for (int u = 0; u < kScanChunk; ++u) {
                     if (v[u] < bd) {
@@ -85,93 +97,52 @@ __device__ __forceinline__ void alloc_body(const int32_t *__restrict__ hubs, int
             }
             if (tie) {
                 best = 0;
-                CT be = Ct[(size_t)h[0] * n + i];
+                CT be = Ct[(size_t)hrow[0] * n + i];
                 for (int k = 1; k < p; ++k) {
-                    const CT v = Ct[(size_t)h[k] * n + i];
+                    const CT v = Ct[(size_t)hrow[k] * n + i];
                     if (v < be) {
                         be = v;
                         best = k;
                     }
                 }
             }
-            // a hub keeps itself: binary search of i in the sorted list
-            int lo = 0, hi = p - 1;
-            while (lo <= hi) {
-                const int mid = (lo + hi) >> 1;
-                const int hv = h[mid];
-                if (hv == i) {
-                    best = mid;
-                    break;
-                }
-                if (hv < i)
-                    lo = mid + 1;
-                else
-                    hi = mid - 1;
-            }
-            krow[i] = (uint16_t)best;
-            atomicAdd(&sh_cnt[c][best], 1);
-            if (want_sums) {
-                const double ci = (double)Ct[(size_t)h[best] * n + i];
-                pc[c] = pc[c] + O[i] * ci;
-                pd[c] = pd[c] + D[i] * ci;
-            }
+        }
+        krow[i] = (uint16_t)best;
+        atomicAdd(&sh_cnt[best], 1);
+        if (want_sums) {
+            const double ci = (double)Ct[(size_t)sh_h[best] * n + i];
+            pc = pc + O[i] * ci;
+            pd = pd + D[i] * ci;
         }
     }
-    if (Ch32) {
-        for (int e = tid; e < nind * p * p; e += 256) {
-            const int c = e / (p * p), kl = e % (p * p);
-            const int k = kl / p, l = kl % p;
-            Ch32[(size_t)(s0 + c) * p * p + kl] = (float)Ct[(size_t)sh_h[c][l] * n + sh_h[c][k]];   // C[h_k][h_l]
+    if (Ch32)
+        for (int e = tid; e < p * p; e += 256) {
+            const int k = e / p, l = e % p;
+            Ch32[(size_t)s * p * p + e] = (float)Ct[(size_t)sh_h[l] * n + sh_h[k]];   // C[h_k][h_l]
         }
-    }
     if (want_sums) {
-#pragma unroll
-        for (int c = 0; c < kAllocPer; ++c) {
-            red_c[c][tid] = pc[c];
-            red_d[c][tid] = pd[c];
-        }
+        red_c[tid] = pc;
+        red_d[tid] = pd;
     }
     __syncthreads();
     if (want_sums) {
         for (int w = 128; w > 0; w >>= 1) {
             if (tid < w) {
-#pragma unroll
-                for (int c = 0; c < kAllocPer; ++c) {
-                    red_c[c][tid] = red_c[c][tid] + red_c[c][tid + w];
-                    red_d[c][tid] = red_d[c][tid] + red_d[c][tid + w];
-                }
+                red_c[tid] = red_c[tid] + red_c[tid + w];
+                red_d[tid] = red_d[tid] + red_d[tid + w];
             }
             __syncthreads();
         }
     }
-    if (tid < nind) {
-        const int c = tid;
+    if (tid == 0) {
         int mx = 0;
-        for (int k = 0; k < p; ++k) mx = sh_cnt[c][k] > mx ? sh_cnt[c][k] : mx;
-        cmax[s0 + c] = mx;
+        for (int k = 0; k < p; ++k) mx = sh_cnt[k] > mx ? sh_cnt[k] : mx;
+        cmax[s] = mx;
         if (want_sums) {
-            parts[3 * (size_t)(s0 + c) + 0] = red_c[c][0];
-            parts[3 * (size_t)(s0 + c) + 2] = red_d[c][0];
+            parts[3 * (size_t)s + 0] = red_c[0];
+            parts[3 * (size_t)s + 2] = red_d[0];
         }
     }
-}
-
-// Copy caller-provided device hub lists into the workspace, clamping every id
-// to [0, n) so that malformed input can never address memory out of bounds.
-__global__ void k_copy_clamp(const int32_t *__restrict__ src, int32_t *__restrict__ dst, int total, int n)
-{
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < total) {
-        int v = src[t];
-        dst[t] = v < 0 ? 0 : (v >= n ? n - 1 : v);
-    }
-}
-
-hipError_t launch_copy_clamp(const int32_t *src, int32_t *dst, int total, int n, hipStream_t st)
-{
-    if (total <= 0) return hipSuccess;
-    k_copy_clamp<<<(total + 255) / 256, 256, 0, st>>>(src, dst, total, n);
-    return hipGetLastError();
 }
 
 template <typename CT>
@@ -200,11 +171,7 @@ __global__ __launch_bounds__(256) void k_alloc_group(const TickJob *__restrict__
                            P.parts, P.cmax, P.Ch32, 1, blk);
 }
 
-int alloc_blocks(int count)
-{
-    const int groups = (count + kAllocPer - 1) / kAllocPer;
-    return ((groups + 7) / 8) * 8;
-}
+int alloc_blocks(int count) { return ((count + 7) / 8) * 8; }
 
 hipError_t launch_alloc(const DevPtrs &P, const Dims &d, const int32_t *hubs, int count, uint16_t *kidx,
                         int want_sums, int want_ch, hipStream_t st)
