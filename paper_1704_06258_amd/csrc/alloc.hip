@@ -145,6 +145,24 @@ __device__ __forceinline__ void alloc_body(const int32_t *__restrict__ hubs, int
     }
 }
 
+// Copy caller-provided device hub lists into the workspace, clamping every id
+// to [0, n) so that malformed input can never address memory out of bounds.
+__global__ void k_copy_clamp(const int32_t *__restrict__ src, int32_t *__restrict__ dst, int total, int n)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < total) {
+        int v = src[t];
+        dst[t] = v < 0 ? 0 : (v >= n ? n - 1 : v);
+    }
+}
+
+hipError_t launch_copy_clamp(const int32_t *src, int32_t *dst, int total, int n, hipStream_t st)
+{
+    if (total <= 0) return hipSuccess;
+    k_copy_clamp<<<(total + 255) / 256, 256, 0, st>>>(src, dst, total, n);
+    return hipGetLastError();
+}
+
 template <typename CT>
 __global__ __launch_bounds__(256) void k_alloc(const int32_t *__restrict__ hubs, int count, int n, int n_pad, int p,
                                                const CT *__restrict__ Ct, const float *__restrict__ Ct32,
