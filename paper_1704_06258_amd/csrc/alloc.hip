@@ -30,6 +30,7 @@ __device__ __forceinline__ void alloc_body(const int32_t *__restrict__ hubs, int
 {
 #pragma clang fp contract(off)
     __shared__ int sh_h[kMaxP];
+    __shared__ __align__(16) int sh_off[kMaxP];   // row offsets h*n in the FP32 copy; padding: row n (+inf)
     __shared__ int sh_cnt[kMaxP];
     __shared__ uint8_t sh_pos[kMaxN];   // position of node i in the hub list, 0xFF for spokes
     __shared__ double red_c[256], red_d[256];
@@ -49,7 +50,9 @@ __device__ __forceinline__ void alloc_body(const int32_t *__restrict__ hubs, int
         sh_h[tid] = h;
         sh_pos[h] = (uint8_t)tid;
     }
+    if (tid < kMaxP) sh_off[tid] = (tid < p ? hrow[tid] : n) * n;
     __syncthreads();
+    const int p16 = (p + kScanChunk - 1) / kScanChunk * kScanChunk;
     double pc = 0.0, pd = 0.0;
     uint16_t *krow = kidx + (size_t)s * n_pad;
     for (int i = tid; i < n_pad; i += 256) {
@@ -69,29 +72,18 @@ __device__ __forceinline__ void alloc_body(const int32_t *__restrict__ hubs, int
             best = 0;
             float bd = __builtin_huge_valf();
             bool tie = false;
-            for (int k0 = 0; k0 < p; k0 += kScanChunk) {
+            for (int k0 = 0; k0 < p16; k0 += kScanChunk) {
                 float v[kScanChunk];
-                if (k0 + kScanChunk <= p) {   // whole chunk: the hub ids load as one scalar block
 #pragma unroll
-                    for (int u = 0; u < kScanChunk; ++u) {
-                        const float *row = Ct32 + (size_t)hrow[k0 + u] * n;
-                        v[u] = row[i];
-                    }
-                } else {
-#pragma unroll
-                    for (int u = 0; u < kScanChunk; ++u) {
-                        const float *row = Ct32 + (size_t)hrow[min(k0 + u, p - 1)] * n;
-                        v[u] = k0 + u < p ? row[i] : __builtin_huge_valf();
-                    }
-                }
+                for (int u = 0; u < kScanChunk; ++u) v[u] = Ct32[sh_off[k0 + u] + i];   // padding reads +inf
 #pragma unroll
                 for (int u = 0; u < kScanChunk; ++u) {
                     if (v[u] < bd) {
                         bd = v[u];
                         best = k0 + u;
                         tie = false;
-                    } else if (v[u] == bd && k0 + u < p) {
-                        tie = true;
+                    } else if (v[u] == bd) {
+                        tie = true;   // (+inf padding ties only when every distance is +inf: rescanned)
                     }
                 }
             }

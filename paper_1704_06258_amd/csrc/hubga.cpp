@@ -100,9 +100,11 @@ Carve carve(const Dims &d, int c_symmetric)
     const size_t n2 = (size_t)d.n * d.n, np2 = (size_t)d.n_pad * d.n_pad;
     const size_t cs = d.c_f32 ? 4 : 8, ws = d.w_f32 ? 4 : 8;
     const bool split = d.prec == kSplitBF16;
-    c.C = L.take(n2 * cs);
-    c.Ct = c_symmetric ? c.C : L.take(n2 * cs);
-    c.Ct32 = d.c_f32 ? c.Ct : L.take(n2 * 4);
+    // C, its transpose and the FP32 copy carry one row more: the FP32 copy's
+    // extra row is +inf, the allocation scan's padding hub.
+    c.C = L.take((n2 + d.n) * cs);
+    c.Ct = c_symmetric ? c.C : L.take((n2 + d.n) * cs);
+    c.Ct32 = d.c_f32 ? c.Ct : L.take((n2 + d.n) * 4);
     c.W = L.take(n2 * ws);
     c.W32 = (d.prec == kFP32 && !d.w_f32) ? L.take(n2 * 4) : (size_t)-1;
     c.Whi = split ? L.take(np2 * 2) : (size_t)-1;

@@ -171,6 +171,14 @@ __global__ void k_middle_select(const double *__restrict__ d, int n, int p, int3
     }
 }
 
+// Row n of the FP32 hub-distance copy: +inf, read for the padding hubs of the
+// allocation scan.
+__global__ void k_inf_row(float *__restrict__ row, int n)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) row[t] = __builtin_huge_valf();
+}
+
 // ------------------------------------------------------------ launchers --
 
 hipError_t launch_prep(const DevPtrs &P, const Dims &d, hipStream_t st)
@@ -204,6 +212,7 @@ hipError_t launch_prep(const DevPtrs &P, const Dims &d, hipStream_t st)
         size_t cnt = (size_t)n * n;
         k_to_f32<<<(unsigned)((cnt + tb - 1) / tb), tb, 0, st>>>((const double *)P.Ct, P.Ct32, cnt);
     }
+    k_inf_row<<<nb, tb, 0, st>>>(P.Ct32 + (size_t)n * n, n);
     if (P.Whi) {
         size_t cnt = (size_t)d.n_pad * d.n_pad;
         unsigned g = (unsigned)((cnt + tb - 1) / tb);
