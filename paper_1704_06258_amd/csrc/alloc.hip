@@ -69,24 +69,31 @@ __device__ __forceinline__ void alloc_body(const int32_t *__restrict__ hubs, int
             // minimum is also the unique minimum of the instance values.  When
             // several hubs share the FP32 minimum, rescan in the instance
             // dtype (strict <, ties to the smaller hub id).
+            // Branch-free: per chunk its minimum, first position and number of
+            // hubs at it; merged over chunks (selects, no per-hub branches).
             best = 0;
             float bd = __builtin_huge_valf();
-            bool tie = false;
+            int at_min = 0;   // hubs at the FP32 minimum so far
             for (int k0 = 0; k0 < p16; k0 += kScanChunk) {
                 float v[kScanChunk];
 #pragma unroll
                 for (int u = 0; u < kScanChunk; ++u) v[u] = Ct32[sh_off[k0 + u] + i];   // padding reads +inf
+                float m = v[0];
 #pragma unroll
-                for (int u = 0; u < kScanChunk; ++u) {
-                    if (v[u] < bd) {
-                        bd = v[u];
-                        best = k0 + u;
-                        tie = false;
-                    } else if (v[u] == bd) {
-                        tie = true;   // (+inf padding ties only when every distance is +inf: rescanned)
-                    }
+                for (int u = 1; u < kScanChunk; ++u) m = fminf(m, v[u]);
+                int first = kScanChunk - 1, cnt = 0;
+#pragma unroll
+                for (int u = kScanChunk - 1; u >= 0; --u) {
+                    const int eq = v[u] == m ? 1 : 0;
+                    first = eq ? u : first;
+                    cnt += eq;
                 }
+                const bool lt = m < bd, same = m == bd;
+                at_min = lt ? cnt : (same ? at_min + cnt : at_min);
+                best = lt ? k0 + first : best;
+                bd = lt ? m : bd;
             }
+            const bool tie = at_min > 1;   // (+inf padding ties only when every distance is +inf: rescanned)
             if (tie) {
                 best = 0;
                 CT be = Ct[(size_t)hrow[0] * n + i];
