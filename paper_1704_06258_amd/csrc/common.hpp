@@ -71,8 +71,9 @@ struct Dims {
 // the concatenation of the contexts' own grids, start[phase] being the first
 // workgroup of context j, so every workgroup serves exactly one context.
 enum TickPhase { kTickOps = 0, kTickAlloc, kTickFinal, kTickSel1, kTickCols, kTickSums, kTickSel2, kTickPhases };
-constexpr int kTickColsBlocks = 64;   // per context: persistent workgroups of the column-parallel re-evaluation
-constexpr int kTickSumsBlocks = 32;   // per context: workgroups of the candidate sums
+constexpr int kMaxPoolJobs = 256;      // grouped contexts per batch
+constexpr int kPoolColsBlocks = 1024;  // persistent workgroups of the grouped column sums (all contexts)
+constexpr int kPoolSumsBlocks = 512;   // ... and of the grouped candidate sums
 
 struct TickJob {
     DevPtrs P;

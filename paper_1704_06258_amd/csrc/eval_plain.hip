@@ -159,6 +159,91 @@ __host__ __device__ inline size_t canon_cols_smem(int n, int p)
     return (size_t)p * p * 8 + (size_t)kCanonRows * kCanonCols * 8 + (((size_t)n * 2 + 15) / 16) * 16;
 }
 
+// One item (candidate slot, 32-column chunk) of the column sums (LDS:
+// canon_cols_smem); every lane of the workgroup takes part.
+template <typename CT, typename WT>
+__device__ __forceinline__ void canon_cols_item(const int32_t *__restrict__ hubs, const uint16_t *__restrict__ kidx,
+                                                const int32_t *__restrict__ cand, const int32_t *__restrict__ slot_r,
+                                                const int32_t *__restrict__ slot_c, int m, int n, int n_pad, int p,
+                                                const CT *__restrict__ C, const WT *__restrict__ W,
+                                                double *__restrict__ tbuf, char *smem, int item)
+{
+#pragma clang fp contract(off)
+    double *Ch = (double *)smem;
+    double *tile = Ch + (size_t)p * p;                        // products [row][col]
+    uint16_t *kid = (uint16_t *)(tile + kCanonRows * kCanonCols);
+    __shared__ int h[kMaxP];
+    const int tid = threadIdx.x;
+    const int nchunks = (n + kCanonCols - 1) / kCanonCols;
+    constexpr int PER = kCanonRows * kCanonCols / 256;   // tile elements per thread
+    const int nb = (n + kCanonRows - 1) / kCanonRows;
+    const int slot = item / nchunks, chunk = item % nchunks;
+    const int r = slot_r[slot], c = slot_c[slot];
+    const int s = cand[(size_t)r * m + c];
+    const int j0 = chunk * kCanonCols;
+    const int32_t *hg = hubs + (size_t)s * p;
+    __syncthreads();   // previous item done with LDS
+    if (tid < p) h[tid] = hg[tid];
+    const uint16_t *krow = kidx + (size_t)s * n_pad;
+    for (int i = tid; i < n; i += 256) kid[i] = krow[i];
+    __syncthreads();
+    for (int e = tid; e < p * p; e += 256) Ch[e] = (double)C[(size_t)h[e / p] * n + h[e % p]];
+    // this thread's tile elements: column e % 32 (fixed), rows e / 32
+    const int col = tid % kCanonCols, j = j0 + col;
+    const bool jin = j < n;
+    WT reg0[PER], reg1[PER];
+    auto load = [&](int b, WT *dst) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int i = b * kCanonRows + (tid + q * 256) / kCanonCols;
+            dst[q] = (i < n && jin) ? W[(size_t)i * n + j] : (WT)0;
+        }
+    };
+    const bool owner = tid < kCanonCols && jin;
+    double acc = 0.0;
+    load(0, reg0);
+    if (nb > 1) load(1, reg1);
+    __syncthreads();   // Ch and kid ready
+    const int kj = jin ? kid[j] : 0;
+    auto step = [&](int b, WT *rg) {
+        const int i0 = b * kCanonRows;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = tid + q * 256, i = i0 + e / kCanonCols;
+            tile[e] = i < n ? (double)rg[q] * Ch[(size_t)kid[i] * p + kj] : 0.0;
+        }
+        __syncthreads();
+        if (b + 2 < nb) load(b + 2, rg);
+        if (owner) {
+            const int rows = n - i0 < kCanonRows ? n - i0 : kCanonRows;
+            int ii = 0;
+            for (; ii + 8 <= rows; ii += 8) {
+                double v0 = tile[(ii + 0) * kCanonCols + tid], v1 = tile[(ii + 1) * kCanonCols + tid];
+                double v2 = tile[(ii + 2) * kCanonCols + tid], v3 = tile[(ii + 3) * kCanonCols + tid];
+                double v4 = tile[(ii + 4) * kCanonCols + tid], v5 = tile[(ii + 5) * kCanonCols + tid];
+                double v6 = tile[(ii + 6) * kCanonCols + tid], v7 = tile[(ii + 7) * kCanonCols + tid];
+                acc = acc + v0;
+                acc = acc + v1;
+                acc = acc + v2;
+                acc = acc + v3;
+                acc = acc + v4;
+                acc = acc + v5;
+                acc = acc + v6;
+                acc = acc + v7;
+            }
+            for (; ii < rows; ++ii) acc = acc + tile[ii * kCanonCols + tid];
+        }
+        __syncthreads();
+    };
+    for (int b = 0; b < nb; b += 2) {
+        step(b, reg0);
+        if (b + 1 < nb) step(b + 1, reg1);
+    }
+    if (owner) tbuf[(size_t)slot * n + j] = acc;
+}
+
+__host__ __device__ inline int canon_cols_chunks(int n) { return (n + kCanonCols - 1) / kCanonCols; }
+
 // Workgroup blk of nblk persistent ones of a context (LDS: canon_cols_smem).
 template <typename CT, typename WT>
 __device__ __forceinline__ void canon_cols_body(const int32_t *__restrict__ hubs, const uint16_t *__restrict__ kidx,
@@ -168,96 +253,24 @@ __device__ __forceinline__ void canon_cols_body(const int32_t *__restrict__ hubs
                                                 const CT *__restrict__ C, const WT *__restrict__ W,
                                                 double *__restrict__ tbuf, char *smem, int blk, int nblk)
 {
-#pragma clang fp contract(off)
-    double *Ch = (double *)smem;
-    double *tile = Ch + (size_t)p * p;                        // products [row][col]
-    uint16_t *kid = (uint16_t *)(tile + kCanonRows * kCanonCols);
-    __shared__ int h[kMaxP];
-    const int tid = threadIdx.x;
-    const int nchunks = (n + kCanonCols - 1) / kCanonCols;
-    const int items = *total * nchunks;
-    constexpr int PER = kCanonRows * kCanonCols / 256;   // tile elements per thread
-    const int nb = (n + kCanonRows - 1) / kCanonRows;
-    for (int item = blk; item < items; item += nblk) {
-        const int slot = item / nchunks, chunk = item % nchunks;
-        const int r = slot_r[slot], c = slot_c[slot];
-        const int s = cand[(size_t)r * m + c];
-        const int j0 = chunk * kCanonCols;
-        const int32_t *hg = hubs + (size_t)s * p;
-        __syncthreads();   // previous item done with LDS
-        if (tid < p) h[tid] = hg[tid];
-        const uint16_t *krow = kidx + (size_t)s * n_pad;
-        for (int i = tid; i < n; i += 256) kid[i] = krow[i];
-        __syncthreads();
-        for (int e = tid; e < p * p; e += 256) Ch[e] = (double)C[(size_t)h[e / p] * n + h[e % p]];
-        // this thread's tile elements: column e % 32 (fixed), rows e / 32
-        const int col = tid % kCanonCols, j = j0 + col;
-        const bool jin = j < n;
-        WT reg0[PER], reg1[PER];
-        auto load = [&](int b, WT *dst) {
-#pragma unroll
-            for (int q = 0; q < PER; ++q) {
-                const int i = b * kCanonRows + (tid + q * 256) / kCanonCols;
-                dst[q] = (i < n && jin) ? W[(size_t)i * n + j] : (WT)0;
-            }
-        };
-        const bool owner = tid < kCanonCols && jin;
-        double acc = 0.0;
-        load(0, reg0);
-        if (nb > 1) load(1, reg1);
-        __syncthreads();   // Ch and kid ready
-        const int kj = jin ? kid[j] : 0;
-        auto step = [&](int b, WT *rg) {
-            const int i0 = b * kCanonRows;
-#pragma unroll
-            for (int q = 0; q < PER; ++q) {
-                const int e = tid + q * 256, i = i0 + e / kCanonCols;
-                tile[e] = i < n ? (double)rg[q] * Ch[(size_t)kid[i] * p + kj] : 0.0;
-            }
-            __syncthreads();
-            if (b + 2 < nb) load(b + 2, rg);
-            if (owner) {
-                const int rows = n - i0 < kCanonRows ? n - i0 : kCanonRows;
-                int ii = 0;
-                for (; ii + 8 <= rows; ii += 8) {
-                    double v0 = tile[(ii + 0) * kCanonCols + tid], v1 = tile[(ii + 1) * kCanonCols + tid];
-                    double v2 = tile[(ii + 2) * kCanonCols + tid], v3 = tile[(ii + 3) * kCanonCols + tid];
-                    double v4 = tile[(ii + 4) * kCanonCols + tid], v5 = tile[(ii + 5) * kCanonCols + tid];
-                    double v6 = tile[(ii + 6) * kCanonCols + tid], v7 = tile[(ii + 7) * kCanonCols + tid];
-                    acc = acc + v0;
-                    acc = acc + v1;
-                    acc = acc + v2;
-                    acc = acc + v3;
-                    acc = acc + v4;
-                    acc = acc + v5;
-                    acc = acc + v6;
-                    acc = acc + v7;
-                }
-                for (; ii < rows; ++ii) acc = acc + tile[ii * kCanonCols + tid];
-            }
-            __syncthreads();
-        };
-        for (int b = 0; b < nb; b += 2) {
-            step(b, reg0);
-            if (b + 1 < nb) step(b + 1, reg1);
-        }
-        if (owner) tbuf[(size_t)slot * n + j] = acc;
-    }
+    const int items = *total * canon_cols_chunks(n);
+    for (int item = blk; item < items; item += nblk)
+        canon_cols_item<CT, WT>(hubs, kidx, cand, slot_r, slot_c, m, n, n_pad, p, C, W, tbuf, smem, item);
 }
 
-// Workgroup blk of nblk of a context (LDS: canon_sums_smem).
+// One item of the candidate sums (LDS: canon_sums_smem): item < total is a
+// slot with its column sums in tbuf, the others are extra candidates
+// evaluated whole.
 template <typename CT, typename WT>
-__device__ __forceinline__ void canon_sums_body(const SelState &S, const int32_t *__restrict__ kidx,
+__device__ __forceinline__ void canon_sums_item(const SelState &S, const int32_t *__restrict__ kidx,
                                                 const int32_t *__restrict__ slot_r, const int32_t *__restrict__ slot_c,
-                                                const int32_t *__restrict__ total,
-                                                const int32_t *__restrict__ extra_r,
-                                                const int32_t *__restrict__ extra_c,
-                                                const int32_t *__restrict__ nextra, int n, int n_pad,
+                                                int tot, const int32_t *__restrict__ extra_r,
+                                                const int32_t *__restrict__ extra_c, int n, int n_pad,
                                                 const CT *__restrict__ C, const WT *__restrict__ W,
                                                 const double *__restrict__ O, const double *__restrict__ D,
                                                 const double *__restrict__ tbuf, double chi, double alpha,
                                                 double delta, double scale, double *__restrict__ cand_cost,
-                                                double *__restrict__ cand_parts, char *smem, int blk, int nblk)
+                                                double *__restrict__ cand_parts, char *smem, int item)
 {
 #pragma clang fp contract(off)
     double *bufA = (double *)smem, *bufB = bufA + n;
@@ -266,8 +279,8 @@ __device__ __forceinline__ void canon_sums_body(const SelState &S, const int32_t
     const int tid = threadIdx.x;
     const int p = S.p, m = S.m;
     const uint16_t *kid16 = (const uint16_t *)kidx;
-    const int tot = *total;
-    for (int slot = blk; slot < tot; slot += nblk) {
+    if (item < tot) {
+        const int slot = item;
         const int r = slot_r[slot], c = slot_c[slot];
         const int s = S.cand[(size_t)r * m + c];
         __syncthreads();
@@ -294,10 +307,8 @@ __device__ __forceinline__ void canon_sums_body(const SelState &S, const int32_t
             cand_parts[3 * o + 1] = T;
             cand_parts[3 * o + 2] = Dd;
         }
-    }
-    // candidates beyond the slots: evaluated whole, one workgroup each
-    const int ne = *nextra;
-    for (int e = blk; e < ne; e += nblk) {
+    } else {   // a candidate beyond the slots: evaluated whole
+        const int e = item - tot;
         const int r = extra_r[e], c = extra_c[e];
         const int s = S.cand[(size_t)r * m + c];
         __syncthreads();
@@ -305,6 +316,26 @@ __device__ __forceinline__ void canon_sums_body(const SelState &S, const int32_t
         eval_exact_body<CT, WT>(S.children + (size_t)s * p, kid16 + (size_t)s * n_pad, n, p, C, W, O, D, chi,
                                 alpha, delta, scale, cand_cost + o, cand_parts + 3 * o, smem);
     }
+}
+
+// Workgroup blk of nblk of a context (LDS: canon_sums_smem).
+template <typename CT, typename WT>
+__device__ __forceinline__ void canon_sums_body(const SelState &S, const int32_t *__restrict__ kidx,
+                                                const int32_t *__restrict__ slot_r, const int32_t *__restrict__ slot_c,
+                                                const int32_t *__restrict__ total,
+                                                const int32_t *__restrict__ extra_r,
+                                                const int32_t *__restrict__ extra_c,
+                                                const int32_t *__restrict__ nextra, int n, int n_pad,
+                                                const CT *__restrict__ C, const WT *__restrict__ W,
+                                                const double *__restrict__ O, const double *__restrict__ D,
+                                                const double *__restrict__ tbuf, double chi, double alpha,
+                                                double delta, double scale, double *__restrict__ cand_cost,
+                                                double *__restrict__ cand_parts, char *smem, int blk, int nblk)
+{
+    const int tot = *total, items = tot + *nextra;
+    for (int item = blk; item < items; item += nblk)
+        canon_sums_item<CT, WT>(S, kidx, slot_r, slot_c, tot, extra_r, extra_c, n, n_pad, C, W, O, D, tbuf, chi,
+                                alpha, delta, scale, cand_cost, cand_parts, smem, item);
 }
 
 // Island decisions on exact costs, one workgroup per island; the last
@@ -355,52 +386,99 @@ __global__ __launch_bounds__(256) void k_select2(SelState S, int *__restrict__ s
 }
 
 // Grouped re-evaluation and decisions (split-bf16 generations of several
-// contexts); each context runs its own persistent share of the grid.
+// contexts).  The column sums and candidate sums draw from one pool: the
+// items of all contexts, concatenated in context order, shared by every
+// workgroup of the launch, so a context with many candidates does not wait on
+// a fixed share of workgroups.
+
+// Exclusive prefix of one count per context (njobs <= kMaxPoolJobs, block of
+// 256 lanes): pre[j] = items of contexts before j, pre[njobs] = all items.
+template <typename F>
+__device__ inline int pool_prefix(int njobs, F count, int *pre)
+{
+    const int tid = threadIdx.x;
+    int v = tid < njobs ? count(tid) : 0;
+    pre[tid + 1] = v;
+    if (tid == 0) pre[0] = 0;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {   // inclusive scan of pre[1..256]
+        const int add = tid >= off ? pre[tid + 1 - off] : 0;
+        __syncthreads();
+        pre[tid + 1] += add;
+        __syncthreads();
+    }
+    return pre[njobs];
+}
+
+__device__ inline int pool_job(const int *pre, int njobs, int g)   // last j with pre[j] <= g
+{
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= g)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
 template <typename CT, typename WT>
-__device__ __forceinline__ void cols_job(const TickJob &J, char *smem, int blk)
+__device__ __forceinline__ void cols_item(const TickJob &J, char *smem, int item)
 {
     const DevPtrs &P = J.P;
     const Dims &d = J.d;
-    canon_cols_body<CT, WT>(P.hubs, P.kidx, P.cand, P.slot_r, P.slot_c, P.total, d.m, d.n, d.n_pad, d.p,
-                            (const CT *)P.C, (const WT *)P.W, P.tbuf, smem, blk, J.blocks[kTickCols]);
+    canon_cols_item<CT, WT>(P.hubs, P.kidx, P.cand, P.slot_r, P.slot_c, d.m, d.n, d.n_pad, d.p, (const CT *)P.C,
+                            (const WT *)P.W, P.tbuf, smem, item);
 }
 
 __global__ __launch_bounds__(256) void k_canon_cols_group(const TickJob *__restrict__ jobs, int njobs)
 {
     extern __shared__ __align__(16) char smem[];
-    const TickJob &J = jobs[tick_job(jobs, njobs, kTickCols, blockIdx.x)];
-    const int blk = blockIdx.x - J.start[kTickCols];
-    if (J.d.c_f32) {
-        if (J.d.w_f32) cols_job<float, float>(J, smem, blk);
-        else cols_job<float, double>(J, smem, blk);
-    } else {
-        if (J.d.w_f32) cols_job<double, float>(J, smem, blk);
-        else cols_job<double, double>(J, smem, blk);
+    __shared__ int pre[kMaxPoolJobs + 1];
+    const int items =
+        pool_prefix(njobs, [&](int j) { return *jobs[j].P.total * canon_cols_chunks(jobs[j].d.n); }, pre);
+    for (int g = blockIdx.x; g < items; g += gridDim.x) {
+        const int j = pool_job(pre, njobs, g);
+        const TickJob &J = jobs[j];
+        const int item = g - pre[j];
+        if (J.d.c_f32) {
+            if (J.d.w_f32) cols_item<float, float>(J, smem, item);
+            else cols_item<float, double>(J, smem, item);
+        } else {
+            if (J.d.w_f32) cols_item<double, float>(J, smem, item);
+            else cols_item<double, double>(J, smem, item);
+        }
     }
 }
 
 template <typename CT, typename WT>
-__device__ __forceinline__ void sums_job(const TickJob &J, char *smem, int blk)
+__device__ __forceinline__ void sums_item(const TickJob &J, char *smem, int tot, int item)
 {
     const DevPtrs &P = J.P;
     const Dims &d = J.d;
     const SelState S = make_sel_state(P, d);
-    canon_sums_body<CT, WT>(S, (const int32_t *)P.kidx, P.slot_r, P.slot_c, P.total, P.extra_r, P.extra_c, P.nextra,
-                            d.n, d.n_pad, (const CT *)P.C, (const WT *)P.W, P.O, P.D, P.tbuf, d.chi, d.alpha,
-                            d.delta, d.scale, P.cand_cost, P.cand_parts, smem, blk, J.blocks[kTickSums]);
+    canon_sums_item<CT, WT>(S, (const int32_t *)P.kidx, P.slot_r, P.slot_c, tot, P.extra_r, P.extra_c, d.n, d.n_pad,
+                            (const CT *)P.C, (const WT *)P.W, P.O, P.D, P.tbuf, d.chi, d.alpha, d.delta, d.scale,
+                            P.cand_cost, P.cand_parts, smem, item);
 }
 
 __global__ __launch_bounds__(256) void k_canon_sums_group(const TickJob *__restrict__ jobs, int njobs)
 {
     extern __shared__ __align__(16) char smem[];
-    const TickJob &J = jobs[tick_job(jobs, njobs, kTickSums, blockIdx.x)];
-    const int blk = blockIdx.x - J.start[kTickSums];
-    if (J.d.c_f32) {
-        if (J.d.w_f32) sums_job<float, float>(J, smem, blk);
-        else sums_job<float, double>(J, smem, blk);
-    } else {
-        if (J.d.w_f32) sums_job<double, float>(J, smem, blk);
-        else sums_job<double, double>(J, smem, blk);
+    __shared__ int pre[kMaxPoolJobs + 1];
+    const int items = pool_prefix(njobs, [&](int j) { return *jobs[j].P.total + *jobs[j].P.nextra; }, pre);
+    for (int g = blockIdx.x; g < items; g += gridDim.x) {
+        const int j = pool_job(pre, njobs, g);
+        const TickJob &J = jobs[j];
+        const int item = g - pre[j], tot = *J.P.total;
+        if (J.d.c_f32) {
+            if (J.d.w_f32) sums_item<float, float>(J, smem, tot, item);
+            else sums_item<float, double>(J, smem, tot, item);
+        } else {
+            if (J.d.w_f32) sums_item<double, float>(J, smem, tot, item);
+            else sums_item<double, double>(J, smem, tot, item);
+        }
     }
 }
 
@@ -537,9 +615,10 @@ hipError_t launch_recheck_group(const TickJob *jobs, int njobs, const int *block
 {
     if (njobs <= 0) return hipSuccess;
     hipError_t e;
-    k_canon_cols_group<<<blocks[kTickCols], 256, lds_cols, st>>>(jobs, njobs);
+    if (njobs > kMaxPoolJobs) return hipErrorInvalidValue;
+    k_canon_cols_group<<<kPoolColsBlocks, 256, lds_cols, st>>>(jobs, njobs);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    k_canon_sums_group<<<blocks[kTickSums], 256, lds_sums, st>>>(jobs, njobs);
+    k_canon_sums_group<<<kPoolSumsBlocks, 256, lds_sums, st>>>(jobs, njobs);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     k_select2_group<<<blocks[kTickSel2], 256, 0, st>>>(jobs, njobs);
     return hipGetLastError();

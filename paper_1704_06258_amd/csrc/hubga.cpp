@@ -843,7 +843,7 @@ ga_status ga_batch_set(ga_batch *b, ga_ctx *const *ctxs, int32_t count)
     std::vector<ga_ctx *> grouped, solo;
     for (int i = 0; i < count; ++i) {
         ga_ctx *c = ctxs[i];
-        if (c->d.prec == kSplitBF16 && mfma_groupable(c->d, b->cfg))
+        if (c->d.prec == kSplitBF16 && mfma_groupable(c->d, b->cfg) && (int)grouped.size() < kMaxPoolJobs)
             grouped.push_back(c);
         else
             solo.push_back(c);
@@ -875,8 +875,8 @@ ga_status ga_batch_set(ga_batch *b, ga_ctx *const *ctxs, int32_t count)
         J.blocks[kTickAlloc] = alloc_blocks(d.S);   // a multiple of 8: every context starts on XCD 0
         J.blocks[kTickFinal] = finalize_blocks(d.S);
         J.blocks[kTickSel1] = d.R;
-        J.blocks[kTickCols] = kTickColsBlocks;
-        J.blocks[kTickSums] = kTickSumsBlocks;
+        J.blocks[kTickCols] = 0;   // the re-evaluation draws from one pool of all contexts' items
+        J.blocks[kTickSums] = 0;
         J.blocks[kTickSel2] = d.R;
         for (int q = 0; q < kTickPhases; ++q) {
             J.start[q] = blocks[q];
