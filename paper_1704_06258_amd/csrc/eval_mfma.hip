@@ -377,11 +377,9 @@ __device__ __forceinline__ void mfma_pipe_tile(const MfmaJob &J, int tile, u32x4
     const u32x4 *__restrict__ Whsw = J.Whsw;
     const u32x4 *__restrict__ Wlsw = J.Wlsw;
     const uint16_t *__restrict__ kidx = J.kidx;
-    const float *__restrict__ Ch32 = J.Ch32;
-    double *__restrict__ partial = J.partial;
-    const int n = J.n, n_pad = J.n_pad, p = J.p, count = J.count, NS = J.NS, n_mt = J.n_mt, n_nt = J.n_nt;
+    const int n_pad = J.n_pad, p = J.p, count = J.count, NS = J.NS, n_nt = J.n_nt;
     const int mt = tile / n_nt, nt = tile % n_nt;
-    const int M0 = mt * MT, N0 = nt * NT;
+    const int N0 = nt * NT;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int half = lane >> 5, l32 = lane & 31;
     const int KS = n_pad / 16;

@@ -607,6 +607,56 @@ hipError_t launch_recheck(const DevPtrs &P, const Dims &d, const SelState &S, hi
     return recheck_launch<double, double>(P, d, S, st);
 }
 
+// The exact cost of the single solution in best (P0 of Sec. 4.1), column
+// parallel: one workgroup per 32-column chunk, then the sums in one workgroup;
+// the result is the sequential definition, bit for bit.  cand, slot_r and
+// slot_c are unused before the first generation; their first entries become
+// the one-slot index of best.
+__global__ void k_p0_index(int32_t *__restrict__ cand, int32_t *__restrict__ slot_r, int32_t *__restrict__ slot_c)
+{
+    if (threadIdx.x == 0) cand[0] = slot_r[0] = slot_c[0] = 0;
+}
+
+template <typename CT, typename WT>
+__global__ __launch_bounds__(256) void k_p0_cols(DevPtrs P, Dims d)
+{
+    extern __shared__ __align__(16) char smem[];
+    canon_cols_item<CT, WT>(P.best, P.kidx_one, P.cand, P.slot_r, P.slot_c, 1, d.n, d.n_pad, d.p, (const CT *)P.C,
+                            (const WT *)P.W, P.tbuf, smem, blockIdx.x);
+}
+
+template <typename CT, typename WT>
+__global__ __launch_bounds__(256) void k_p0_sums(DevPtrs P, Dims d)
+{
+    extern __shared__ __align__(16) char smem[];
+    SelState S = make_sel_state(P, d);
+    S.children = P.best;
+    S.m = 1;
+    canon_sums_item<CT, WT>(S, (const int32_t *)P.kidx_one, P.slot_r, P.slot_c, 1, P.extra_r, P.extra_c, d.n, d.n_pad,
+                            (const CT *)P.C, (const WT *)P.W, P.O, P.D, P.tbuf, d.chi, d.alpha, d.delta, d.scale,
+                            P.best_cost, P.best_cost + 1, smem, 0);
+}
+
+template <typename CT, typename WT>
+static hipError_t p0_launch(const DevPtrs &P, const Dims &d, hipStream_t st)
+{
+    hipError_t e;
+    k_p0_index<<<1, 64, 0, st>>>(P.cand, P.slot_r, P.slot_c);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_p0_cols<CT, WT><<<canon_cols_chunks(d.n), 256, canon_cols_smem(d.n, d.p), st>>>(P, d);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_p0_sums<CT, WT><<<1, 256, std::max((size_t)16 * d.n, exact_smem_bytes(d.n, d.p)), st>>>(P, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_p0_exact(const DevPtrs &P, const Dims &d, hipStream_t st)
+{
+    if (d.c_f32 && d.w_f32) return p0_launch<float, float>(P, d, st);
+    if (d.c_f32) return p0_launch<float, double>(P, d, st);
+    if (d.w_f32) return p0_launch<double, float>(P, d, st);
+    return p0_launch<double, double>(P, d, st);
+}
+
 size_t recheck_lds_cols(int n, int p) { return canon_cols_smem(n, p); }
 size_t recheck_lds_sums(int n, int p) { return std::max((size_t)16 * n, exact_smem_bytes(n, p)); }
 
@@ -663,7 +713,11 @@ hipError_t prepare_plain_kernels(int max_lds)
                          (const void *)k_canon_sums<double, double>, (const void *)k_canon_sums<double, float>,
                          (const void *)k_canon_sums<float, double>,  (const void *)k_canon_sums<float, float>,
                          (const void *)k_eval_fp32<double>,          (const void *)k_eval_fp32<float>,
-                         (const void *)k_canon_cols_group,           (const void *)k_canon_sums_group};
+                         (const void *)k_canon_cols_group,           (const void *)k_canon_sums_group,
+                         (const void *)k_p0_cols<double, double>,    (const void *)k_p0_cols<double, float>,
+                         (const void *)k_p0_cols<float, double>,     (const void *)k_p0_cols<float, float>,
+                         (const void *)k_p0_sums<double, double>,    (const void *)k_p0_sums<double, float>,
+                         (const void *)k_p0_sums<float, double>,     (const void *)k_p0_sums<float, float>};
     for (const void *f : fns) {
         hipFuncAttributes fa;
         hipError_t e = hipFuncGetAttributes(&fa, f);

@@ -135,7 +135,7 @@ Carve carve(const Dims &d, int c_symmetric)
     c.cand_parts = L.take((size_t)d.S * 24);
     c.kidx_one = L.take((size_t)d.n_pad * 2);
     c.scratch = L.take((size_t)d.n);
-    c.tbuf = d.prec == kFP64 ? (size_t)-1 : L.take((size_t)d.tot * d.n * 8);
+    c.tbuf = L.take((size_t)(d.prec == kFP64 ? 1 : d.tot) * d.n * 8);   // FP64: the column sums of P0
     c.slot_r = L.take((size_t)d.tot * 4);
     c.slot_c = L.take((size_t)d.tot * 4);
     c.handled = L.take((size_t)d.R * 4);
@@ -513,9 +513,7 @@ ga_status ga_init(const ga_params *q, const void *C, ga_dtype cdt, const void *W
             return dev_fail(he, "middle nodes");
         if ((he = launch_alloc(P, d, P.best, 1, P.kidx_one, 0, 0, ctx->st)) != hipSuccess)
             return dev_fail(he, "alloc P0");
-        if ((he = launch_eval_exact(P, d, P.best, P.kidx_one, 1, P.best_cost, P.best_cost + 1, nullptr, ctx->st)) !=
-            hipSuccess)
-            return dev_fail(he, "eval P0");
+        if ((he = launch_p0_exact(P, d, ctx->st)) != hipSuccess) return dev_fail(he, "eval P0");
         if ((he = launch_init_state(P, d, ctx->st)) != hipSuccess) return dev_fail(he, "init state");
         if ((he = hipStreamSynchronize(ctx->st)) != hipSuccess) return dev_fail(he, "sync");
         *out = ctx;

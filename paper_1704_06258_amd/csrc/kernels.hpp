@@ -23,6 +23,7 @@ hipError_t launch_eval_fp32(const DevPtrs &P, const Dims &d, const int32_t *hubs
                             hipStream_t st);
 hipError_t launch_recheck(const DevPtrs &P, const Dims &d, const SelState &S, hipStream_t st);
 double fp32_eps_bound(int n);
+hipError_t launch_p0_exact(const DevPtrs &P, const Dims &d, hipStream_t st);
 size_t recheck_lds_cols(int n, int p);
 size_t recheck_lds_sums(int n, int p);
 size_t recheck_group_lds_cap(int which);   // 0: column sums, 1: candidate sums

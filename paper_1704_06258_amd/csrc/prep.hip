@@ -7,27 +7,45 @@
 
 namespace hubga {
 
-template <typename T>
-__global__ void k_row_sums(const T *__restrict__ M, int n, double *__restrict__ out)
+// Sums of the rows (ROWS) or columns of M in binary64, each in ascending
+// index order, one output per lane of a 64-line workgroup: tiles of 64 x 64
+// are loaded coalesced by all 256 lanes (the next tile's loads are in flight
+// while the current one is summed) and each line's owner adds its 64 values
+// in order.
+template <typename T, bool ROWS>
+__global__ __launch_bounds__(256) void k_line_sums(const T *__restrict__ M, int n, double *__restrict__ out)
 {
 #pragma clang fp contract(off)
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const T *row = M + (size_t)i * n;
+    __shared__ double tile[64][65];
+    const int tid = threadIdx.x, base = blockIdx.x * 64;
+    const int nt = (n + 63) / 64;
+    T reg[16];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int e = tid + 256 * q, l = e / 64, k = e % 64;   // line l, index k within the tile
+            const int line = base + l, idx = k0 + k;
+            reg[q] = (line < n && idx < n) ? (ROWS ? M[(size_t)line * n + idx] : M[(size_t)idx * n + line]) : (T)0;
+        }
+    };
     double acc = 0.0;
-    for (int j = 0; j < n; ++j) acc = acc + (double)row[j];
-    out[i] = acc;
-}
-
-template <typename T>
-__global__ void k_col_sums(const T *__restrict__ M, int n, double *__restrict__ out)
-{
-#pragma clang fp contract(off)
-    int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
-    double acc = 0.0;
-    for (int i = 0; i < n; ++i) acc = acc + (double)M[(size_t)i * n + j];
-    out[j] = acc;
+    load(0);
+    for (int t = 0; t < nt; ++t) {
+        const int k0 = t * 64;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int e = tid + 256 * q;
+            tile[e / 64][e % 64] = (double)reg[q];
+        }
+        __syncthreads();
+        if (t + 1 < nt) load(k0 + 64);
+        if (tid < 64) {
+            const int cnt = min(64, n - k0);
+            for (int k = 0; k < cnt; ++k) acc = acc + tile[tid][k];
+        }
+        __syncthreads();
+    }
+    if (tid < 64 && base + tid < n) out[base + tid] = acc;
 }
 
 template <typename T>
@@ -186,17 +204,18 @@ hipError_t launch_prep(const DevPtrs &P, const Dims &d, hipStream_t st)
     const int n = d.n;
     const int tb = 256;
     const int nb = (n + tb - 1) / tb;
+    const int nl = (n + 63) / 64;   // 64 lines per workgroup
     if (d.w_f32) {
-        k_row_sums<float><<<nb, tb, 0, st>>>((const float *)P.W, n, P.O);
-        k_col_sums<float><<<nb, tb, 0, st>>>((const float *)P.W, n, P.D);
+        k_line_sums<float, true><<<nl, 256, 0, st>>>((const float *)P.W, n, P.O);
+        k_line_sums<float, false><<<nl, 256, 0, st>>>((const float *)P.W, n, P.D);
     } else {
-        k_row_sums<double><<<nb, tb, 0, st>>>((const double *)P.W, n, P.O);
-        k_col_sums<double><<<nb, tb, 0, st>>>((const double *)P.W, n, P.D);
+        k_line_sums<double, true><<<nl, 256, 0, st>>>((const double *)P.W, n, P.O);
+        k_line_sums<double, false><<<nl, 256, 0, st>>>((const double *)P.W, n, P.D);
     }
     if (d.c_f32)
-        k_row_sums<float><<<nb, tb, 0, st>>>((const float *)P.C, n, P.dsum);
+        k_line_sums<float, true><<<nl, 256, 0, st>>>((const float *)P.C, n, P.dsum);
     else
-        k_row_sums<double><<<nb, tb, 0, st>>>((const double *)P.C, n, P.dsum);
+        k_line_sums<double, true><<<nl, 256, 0, st>>>((const double *)P.C, n, P.dsum);
     if (P.Ct != P.C) {
         dim3 g((n + 31) / 32, (n + 31) / 32);
         if (d.c_f32)
