@@ -332,9 +332,12 @@ template <typename T>
 bool symmetric(const void *M, int n)
 {
     const T *x = (const T *)M;
-    for (int i = 0; i < n; ++i)
-        for (int j = i + 1; j < n; ++j)
-            if (x[(size_t)i * n + j] != x[(size_t)j * n + i]) return false;
+    constexpr int B = 64;   // blocks of B x B, so the transposed reads stay in cache
+    for (int bi = 0; bi < n; bi += B)
+        for (int bj = bi; bj < n; bj += B)
+            for (int i = bi; i < std::min(n, bi + B); ++i)
+                for (int j = std::max(bj, i + 1); j < std::min(n, bj + B); ++j)
+                    if (x[(size_t)i * n + j] != x[(size_t)j * n + i]) return false;
     return true;
 }
 

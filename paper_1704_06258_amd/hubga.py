@@ -169,7 +169,7 @@ class Solver:
     """One context: an instance resident on the GPU plus its GA state."""
 
     def __init__(self, C, W, p, *, chi, alpha, delta, scale=1.0, seed=1, population=64, island_size=None, n1=10,
-                 elitist=True, precision="fp64", kernel=None, stream=None, device=0):
+                 elitist=True, precision="fp64", kernel=None, stream=None, device=0, c_symmetric=None):
         import torch
         C = np.ascontiguousarray(C)
         W = np.ascontiguousarray(W)
@@ -177,7 +177,7 @@ class Solver:
         if C.shape != (n, n) or W.shape != (n, n):
             raise ValueError("C and W must be n x n")
         self.n, self.p = n, p
-        sym = bool(np.array_equal(C, C.T))
+        sym = bool(np.array_equal(C, C.T)) if c_symmetric is None else bool(c_symmetric)
         self.params = make_params(n, p, chi=chi, alpha=alpha, delta=delta, scale=scale, seed=seed,
                                   population=population, island_size=island_size, n1=n1, elitist=elitist,
                                   precision=precision, kernel=kernel, c_symmetric=sym)

@@ -66,11 +66,20 @@ class _Job:
     gens: int = 0
 
 
+def c_symmetric(req: SolveRequest) -> bool:
+    """Whether the request's C is symmetric (computed once per request)."""
+    sym = getattr(req, "_c_symmetric", None)
+    if sym is None:
+        sym = bool(np.array_equal(req.C, req.C.T))
+        req._c_symmetric = sym
+    return sym
+
+
 def workspace_bytes(req: SolveRequest) -> int:
     n = req.C.shape[0]
     q = hubga.make_params(n, req.p, chi=req.chi, alpha=req.alpha, delta=req.delta, seed=req.seed,
                           population=req.population, island_size=min(req.island_size, req.population), n1=req.n1,
-                          precision=req.precision, c_symmetric=bool(np.array_equal(req.C, req.C.T)))
+                          precision=req.precision, c_symmetric=c_symmetric(req))
     cdt = hubga.GA_DT_F32 if req.C.dtype == np.float32 else hubga.GA_DT_F64
     wdt = hubga.GA_DT_F32 if req.W.dtype == np.float32 else hubga.GA_DT_F64
     return hubga.ga_workspace_bytes(q, cdt, wdt)
@@ -88,7 +97,7 @@ class Server:
     So admissions and completions overlap the generations of the others."""
 
     def __init__(self, hbm_budget: int = 16 << 30, max_slots: int = 64, tile_config: int = 7, device: int = 0,
-                 workers: int = 4):
+                 workers: int = 8):
         self.budget = int(hbm_budget)
         self.max_slots = int(max_slots)
         self.batch = hubga.Batch(device=device, tile_config=tile_config)
@@ -116,7 +125,8 @@ class Server:
     def _admit(self, req: SolveRequest, now: float) -> _Job:
         solver = hubga.Solver(req.C, req.W, req.p, chi=req.chi, alpha=req.alpha, delta=req.delta, seed=req.seed,
                               population=req.population, island_size=min(req.island_size, req.population),
-                              n1=req.n1, precision=req.precision, stream=self._stream(), device=self.device)
+                              n1=req.n1, precision=req.precision, stream=self._stream(), device=self.device,
+                              c_symmetric=c_symmetric(req))
         return _Job(req, solver, solver.workspace_bytes, now)
 
     def _finish(self, job: _Job, t0: float, clock) -> SolveResult:
