@@ -87,16 +87,31 @@ __device__ __forceinline__ void ga_ops_body(const int32_t *__restrict__ anc, int
         pb.a[lane] = a[lane];
     }
     __builtin_amdgcn_wave_barrier();
+    // The child's first eight draws, one per lane (they are addressed by their
+    // counters, so drawing one that is not used changes nothing):
+    // 0, 1: perturbation of parent slots 2q, 2q+1; 2: crossover; 3: mutation;
+    // 4..7: corrections t = 0..3.
+    U64x4 mine;
+    {
+        const int k = lane & 7;
+        const uint64_t idx = k == 0 ? (uint64_t)(2 * q) : k == 1 ? (uint64_t)(2 * q + 1) : k == 2 ? (uint64_t)q
+                                                                                                  : (uint64_t)s;
+        const uint64_t op = k < 2 ? 0 : (k == 2 ? 1 : (k == 3 ? 2 : 3));
+        mine = ga_draw(seed, g, idx, op, k >= 4 ? (uint64_t)(k - 4) : 0);
+    }
+    auto word = [&](int k, int w) -> uint64_t {   // word w of draw k, from lane k
+        const uint64_t v = mine.x[w];
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, k);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), k);
+        return ((uint64_t)hi << 32) | lo;
+    };
     int ca = p, cb = p;
     if (p < n) {
-        U64x4 w = ga_draw(seed, g, (uint64_t)(2 * q), 0, 0);
-        wave_swap(n, pa, ca, w.x[0], w.x[1], lane);
-        w = ga_draw(seed, g, (uint64_t)(2 * q + 1), 0, 0);
-        wave_swap(n, pb, cb, w.x[0], w.x[1], lane);
+        wave_swap(n, pa, ca, word(0, 0), word(0, 1), lane);
+        wave_swap(n, pb, cb, word(1, 0), word(1, 1), lane);
     }
     // crossover: first parent's hubs below the cut, second parent's from it on
-    U64x4 w = ga_draw(seed, g, (uint64_t)q, 1, 0);
-    const int cut = 1 + uindex(w.x[0], n - 1);
+    const int cut = 1 + uindex(word(2, 0), n - 1);
     const WList &first = (s & 1) ? pb : pa;
     const WList &second = (s & 1) ? pa : pb;
     const int f = lane < p ? first.lo(lane) : 0x7FFFFFFF;
@@ -109,18 +124,16 @@ __device__ __forceinline__ void ga_ops_body(const int32_t *__restrict__ anc, int
     __builtin_amdgcn_wave_barrier();
     int cnt = nf + (p - ns_below);
     // mutation
-    w = ga_draw(seed, g, (uint64_t)s, 2, 0);
-    if (cnt > 0 && cnt < n) wave_swap(n, cx, cnt, w.x[0], w.x[1], lane);
+    if (cnt > 0 && cnt < n) wave_swap(n, cx, cnt, word(3, 0), word(3, 1), lane);
     // correction
-    uint64_t t = 0;
-    while (cnt > p) {
-        w = ga_draw(seed, g, (uint64_t)s, 3, t++);
-        wave_edit(cx, cnt, uindex(w.x[0], cnt), -1, lane);
-    }
-    while (cnt < p) {
-        w = ga_draw(seed, g, (uint64_t)s, 3, t++);
-        wave_edit(cx, cnt, -1, wave_nth_spoke(cx, cnt, uindex(w.x[0], n - cnt), lane), lane);
-    }
+    int t = 0;
+    auto corr = [&]() -> uint64_t {   // word 0 of correction draw t, then t + 1
+        const uint64_t w0 = t < 4 ? word(4 + t, 0) : ga_draw(seed, g, (uint64_t)s, 3, (uint64_t)t).x[0];
+        ++t;
+        return w0;
+    };
+    while (cnt > p) wave_edit(cx, cnt, uindex(corr(), cnt), -1, lane);
+    while (cnt < p) wave_edit(cx, cnt, -1, wave_nth_spoke(cx, cnt, uindex(corr(), n - cnt), lane), lane);
     if (lane < p) children[(size_t)s * p + lane] = cx.a[lane];
 }
 
