@@ -258,6 +258,16 @@ __device__ __forceinline__ void canon_cols_body(const int32_t *__restrict__ hubs
         canon_cols_item<CT, WT>(hubs, kidx, cand, slot_r, slot_c, m, n, n_pad, p, C, W, tbuf, smem, item);
 }
 
+// LDS of the candidate sums: three n-vectors when they fit (T, Cc and Dd are
+// then summed by three lanes at once), else two (Dd after T and Cc).
+__host__ __device__ inline bool sums_three(int n) { return (size_t)24 * n <= 96 * 1024; }
+__host__ __device__ inline size_t canon_sums_smem(int n, int p)
+{
+    const size_t vec = (size_t)(sums_three(n) ? 24 : 16) * n;
+    const size_t ex = exact_smem_bytes(n, p);
+    return vec > ex ? vec : ex;
+}
+
 // One item of the candidate sums (LDS: canon_sums_smem): item < total is a
 // slot with its column sums in tbuf, the others are extra candidates
 // evaluated whole.
@@ -275,7 +285,7 @@ __device__ __forceinline__ void canon_sums_item(const SelState &S, const int32_t
 #pragma clang fp contract(off)
     double *bufA = (double *)smem, *bufB = bufA + n;
     __shared__ int h[kMaxP];
-    __shared__ double sh_cc;
+    __shared__ double sh_cc, sh_dd;
     const int tid = threadIdx.x;
     const int p = S.p, m = S.m;
     const uint16_t *kid16 = (const uint16_t *)kidx;
@@ -288,19 +298,29 @@ __device__ __forceinline__ void canon_sums_item(const SelState &S, const int32_t
         const uint16_t *krow = kid16 + (size_t)s * n_pad;
         const double *t = tbuf + (size_t)slot * n;
         __syncthreads();
+        const bool three = sums_three(n);
+        double *bufC = three ? bufB + n : bufA;
         for (int i = tid; i < n; i += 256) {
+            const double ci = (double)C[(size_t)i * n + h[krow[i]]];
             bufA[i] = t[i];
-            bufB[i] = O[i] * (double)C[(size_t)i * n + h[krow[i]]];
+            bufB[i] = O[i] * ci;
+            if (three) bufC[i] = D[i] * ci;
         }
         __syncthreads();
-        double T = 0.0;
-        if (tid == 0) T = seq_sum(bufA, n);
+        double T = 0.0, Dd = 0.0;
+        if (tid == 0) T = seq_sum(bufA, n);   // three chains in three waves
         if (tid == 64) sh_cc = seq_sum(bufB, n);
+        if (three && tid == 128) sh_dd = seq_sum(bufC, n);
         __syncthreads();
-        for (int i = tid; i < n; i += 256) bufA[i] = D[i] * (double)C[(size_t)i * n + h[krow[i]]];
-        __syncthreads();
+        if (!three) {
+            for (int i = tid; i < n; i += 256) bufA[i] = D[i] * (double)C[(size_t)i * n + h[krow[i]]];
+            __syncthreads();
+            if (tid == 0) Dd = seq_sum(bufA, n);
+        } else {
+            Dd = sh_dd;
+        }
         if (tid == 0) {
-            const double Cc = sh_cc, Dd = seq_sum(bufA, n);
+            const double Cc = sh_cc;
             const size_t o = (size_t)r * m + c;
             cand_cost[o] = (((chi * Cc) + (alpha * T)) + (delta * Dd)) * scale;
             cand_parts[3 * o + 0] = Cc;
@@ -589,7 +609,7 @@ static hipError_t recheck_launch(const DevPtrs &P, const Dims &d, const SelState
     k_canon_cols<CT, WT><<<512, 256, smA, st>>>(P.hubs, P.kidx, P.cand, P.slot_r, P.slot_c, P.total, d.m, d.n,
                                                 d.n_pad, d.p, (const CT *)P.C, (const WT *)P.W, P.tbuf);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    const size_t smB = std::max((size_t)16 * d.n, exact_smem_bytes(d.n, d.p));
+    const size_t smB = canon_sums_smem(d.n, d.p);
     k_canon_sums<CT, WT><<<256, 256, smB, st>>>(S, (const int32_t *)P.kidx, P.slot_r, P.slot_c, P.total, P.extra_r,
                                                 P.extra_c, P.nextra, d.n, d.n_pad, (const CT *)P.C, (const WT *)P.W,
                                                 P.O, P.D, P.tbuf, d.chi, d.alpha, d.delta, d.scale, P.cand_cost,
@@ -645,7 +665,7 @@ static hipError_t p0_launch(const DevPtrs &P, const Dims &d, hipStream_t st)
     if ((e = hipGetLastError()) != hipSuccess) return e;
     k_p0_cols<CT, WT><<<canon_cols_chunks(d.n), 256, canon_cols_smem(d.n, d.p), st>>>(P, d);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    k_p0_sums<CT, WT><<<1, 256, std::max((size_t)16 * d.n, exact_smem_bytes(d.n, d.p)), st>>>(P, d);
+    k_p0_sums<CT, WT><<<1, 256, canon_sums_smem(d.n, d.p), st>>>(P, d);
     return hipGetLastError();
 }
 
@@ -658,7 +678,7 @@ hipError_t launch_p0_exact(const DevPtrs &P, const Dims &d, hipStream_t st)
 }
 
 size_t recheck_lds_cols(int n, int p) { return canon_cols_smem(n, p); }
-size_t recheck_lds_sums(int n, int p) { return std::max((size_t)16 * n, exact_smem_bytes(n, p)); }
+size_t recheck_lds_sums(int n, int p) { return canon_sums_smem(n, p); }
 
 hipError_t launch_recheck_group(const TickJob *jobs, int njobs, const int *blocks, size_t lds_cols, size_t lds_sums,
                                 hipStream_t st)
