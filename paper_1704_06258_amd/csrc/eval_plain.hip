@@ -216,22 +216,25 @@ __device__ __forceinline__ void canon_cols_item(const int32_t *__restrict__ hubs
         if (b + 2 < nb) load(b + 2, rg);
         if (owner) {
             const int rows = n - i0 < kCanonRows ? n - i0 : kCanonRows;
-            int ii = 0;
-            for (; ii + 8 <= rows; ii += 8) {
-                double v0 = tile[(ii + 0) * kCanonCols + tid], v1 = tile[(ii + 1) * kCanonCols + tid];
-                double v2 = tile[(ii + 2) * kCanonCols + tid], v3 = tile[(ii + 3) * kCanonCols + tid];
-                double v4 = tile[(ii + 4) * kCanonCols + tid], v5 = tile[(ii + 5) * kCanonCols + tid];
-                double v6 = tile[(ii + 6) * kCanonCols + tid], v7 = tile[(ii + 7) * kCanonCols + tid];
-                acc = acc + v0;
-                acc = acc + v1;
-                acc = acc + v2;
-                acc = acc + v3;
-                acc = acc + v4;
-                acc = acc + v5;
-                acc = acc + v6;
-                acc = acc + v7;
+            if (rows == kCanonRows) {
+                // reads of the next 16 rows in flight while the current 16 are added
+                double cur[16], nxt[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) cur[u] = tile[u * kCanonCols + tid];
+#pragma unroll
+                for (int c = 0; c < kCanonRows / 16; ++c) {
+                    if (c + 1 < kCanonRows / 16) {
+#pragma unroll
+                        for (int u = 0; u < 16; ++u) nxt[u] = tile[((c + 1) * 16 + u) * kCanonCols + tid];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) acc = acc + cur[u];
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) cur[u] = nxt[u];
+                }
+            } else {
+                for (int ii = 0; ii < rows; ++ii) acc = acc + tile[ii * kCanonCols + tid];
             }
-            for (; ii < rows; ++ii) acc = acc + tile[ii * kCanonCols + tid];
         }
         __syncthreads();
     };
