@@ -138,3 +138,30 @@ def test_set_stream_keeps_order_and_trajectory():
         b.set_stream(s2)
         b.step(4)
         assert same(state_of(b), ref)
+
+
+def test_many_contexts_share_the_reevaluation_pool():
+    """Two dozen split-bf16 contexts of different sizes in one batch: early
+    generations give them very different numbers of exactly re-evaluated
+    candidates, all drawn from one pool; each state must equal stepping alone."""
+    import torch
+    specs = [(60 + 37 * (k % 7), 3 + (k % 5), 128 * (1 + k % 3), 32) for k in range(24)]
+    insts = [I.uniform(seed=200 + k, n=n, p=p) for k, (n, p, S, m) in enumerate(specs)]
+    alone = []
+    for k, (inst, (n, p, S, m)) in enumerate(zip(insts, specs)):
+        with make(inst, population=S, island_size=m, n1=3, seed=40 + k, precision="split_bf16") as s:
+            s.step(5)
+            alone.append(state_of(s))
+    batch = hubga.Batch(tile_config=16)
+    members = [make(inst, population=S, island_size=m, n1=3, seed=40 + k, precision="split_bf16",
+                    stream=batch.stream) for k, (inst, (n, p, S, m)) in enumerate(zip(insts, specs))]
+    batch.set(members)
+    batch.step(5)
+    batch.synchronize()
+    assert sum(s.stats()["rechecks"] for s in members) > 0
+    for k, s in enumerate(members):
+        assert same(state_of(s), alone[k]), k
+    for s in members:
+        s.close()
+    batch.close()
+    torch.cuda.synchronize()
