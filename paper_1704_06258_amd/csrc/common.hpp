@@ -50,11 +50,15 @@ struct DevPtrs {
     uint8_t *scratch;   // n bytes (middle-node selection)
     double *tbuf;       // tot*n column sums t_j of candidates under exact re-evaluation
     int32_t *slot_r, *slot_c;   // tot candidate slots (island, candidate)
+    int32_t *slot_s;    // tot: the child of each slot
+    int32_t *slot_done; // tot: finished column items of each slot, zero between launches
     int32_t *handled;   // R: candidates of each island that got a slot
+    int32_t *choice;    // R: the child each island takes in the exact decision, or -1
     int32_t *total;     // 1: slots in use
     int32_t *extra_r, *extra_c;   // S: candidates beyond the slots
     int32_t *nextra;    // 1
-    int *sync;          // 2 grid counters (last-workgroup detection), zero between launches
+    int *sync;          // 2 grid counters (last workgroup of the selection, last unit of the
+                        // re-evaluation), zero between launches
 };
 
 struct Dims {
@@ -70,10 +74,9 @@ struct Dims {
 // One generation of several contexts with one launch per step: the grid is
 // the concatenation of the contexts' own grids, start[phase] being the first
 // workgroup of context j, so every workgroup serves exactly one context.
-enum TickPhase { kTickOps = 0, kTickAlloc, kTickFinal, kTickSel1, kTickCols, kTickSums, kTickSel2, kTickPhases };
+enum TickPhase { kTickOps = 0, kTickAlloc, kTickFinal, kTickSel1, kTickPhases };
 constexpr int kMaxPoolJobs = 256;      // grouped contexts per batch
-constexpr int kPoolColsBlocks = 1024;  // persistent workgroups of the grouped column sums (all contexts)
-constexpr int kPoolSumsBlocks = 512;   // ... and of the grouped candidate sums
+constexpr int kRecheckBlocks = 512;    // persistent workgroups of the exact re-evaluation (one context or all)
 
 struct TickJob {
     DevPtrs P;

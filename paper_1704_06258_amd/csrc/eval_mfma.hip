@@ -17,6 +17,7 @@
 // positions.  Tiles are assigned so that each XCD walks a contiguous range of
 // row tiles (row-tile major), keeping its row panel of W in its own L2.
 #include "kernels.hpp"
+#include "wave_sync.hpp"
 
 #include <type_traits>
 
@@ -223,15 +224,6 @@ __global__ __launch_bounds__(256, OCC) void k_eval_mfma(const uint16_t *__restri
 // whole pipeline before an LDS read.
 typedef __attribute__((address_space(3))) void lds_void;
 
-template <int N, typename F, int I = 0>
-__device__ __forceinline__ void static_for(F &&f)
-{
-    if constexpr (I < N) {
-        f(std::integral_constant<int, I>{});
-        static_for<N, F, I + 1>(static_cast<F &&>(f));
-    }
-}
-
 template <int OFF>
 __device__ __forceinline__ u32x4 ds_read16(uint32_t addr)
 {
@@ -239,31 +231,7 @@ __device__ __forceinline__ u32x4 ds_read16(uint32_t addr)
     asm volatile("ds_read_b128 %0, %1 offset:%2" : "=v"(v) : "v"(addr), "i"(OFF));
     return v;
 }
-__device__ __forceinline__ void lds_wait() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
-// Wait until at most N LDS reads of this wave are outstanding (they complete in
-// order; nothing else that counts here is in flight in the K loop).
-template <int N>
-__device__ __forceinline__ void lds_wait_n()
-{
-    static_assert(N >= 0 && N <= 15, "lgkmcnt range");
-    asm volatile("s_waitcnt lgkmcnt(%0)" ::"n"(N) : "memory");
-}
 __device__ __forceinline__ void pin(u32x4 &v) { asm volatile("" : "+v"(v)); }
-
-// s_waitcnt vmcnt(N), other counters untouched (gfx9 encoding).
-template <int N>
-__device__ __forceinline__ void vm_wait()
-{
-    static_assert(N >= 0 && N < 64, "vmcnt range");
-    __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
-}
-
-__device__ __forceinline__ void wg_barrier()
-{
-    asm volatile("" ::: "memory");
-    __builtin_amdgcn_s_barrier();
-    asm volatile("" ::: "memory");
-}
 
 // One context's operands for the batched kernel (also one entry of a grouped
 // launch over several contexts).

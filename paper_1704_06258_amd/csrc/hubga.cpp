@@ -89,7 +89,7 @@ Dims make_dims(const ga_params *q, ga_dtype cdt, ga_dtype wdt)
 // Offsets of every device buffer; the same walk sizes and carves.
 struct Carve {
     size_t C, Ct, Ct32, W, W32, Whi, Wlo, Whsw, Wlsw, O, D, dsum, hubs, kidx, cost, parts, eps, cmax, Ch32, partial, anc, anc_cost,
-        anc_parts, best, best_cost, gen, stats, cand, cand_cnt, cand_cost, cand_parts, kidx_one, scratch, tbuf, slot_r, slot_c, handled, total_slots, extra_r, extra_c, nextra, sync;
+        anc_parts, best, best_cost, gen, stats, cand, cand_cnt, cand_cost, cand_parts, kidx_one, scratch, tbuf, slot_r, slot_c, slot_s, slot_done, handled, choice, total_slots, extra_r, extra_c, nextra, sync;
     size_t total;
 };
 
@@ -138,7 +138,10 @@ Carve carve(const Dims &d, int c_symmetric)
     c.tbuf = L.take((size_t)(d.prec == kFP64 ? 1 : d.tot) * d.n * 8);   // FP64: the column sums of P0
     c.slot_r = L.take((size_t)d.tot * 4);
     c.slot_c = L.take((size_t)d.tot * 4);
+    c.slot_s = L.take((size_t)d.tot * 4);
+    c.slot_done = L.take((size_t)d.tot * 4);
     c.handled = L.take((size_t)d.R * 4);
+    c.choice = L.take((size_t)d.R * 4);
     c.total_slots = L.take(4);
     c.extra_r = L.take((size_t)d.S * 4);
     c.extra_c = L.take((size_t)d.S * 4);
@@ -194,7 +197,7 @@ struct ga_batch {
     size_t tab_cap = 0, tick_off = 0;
     int njobs = 0, total_tiles = 0, min_p = 0, sel_threads = 64;
     int blocks[kTickPhases] = {};
-    size_t lds_cols = 0, lds_sums = 0;
+    size_t lds_recheck = 0;
 };
 
 namespace {
@@ -416,6 +419,7 @@ ga_status ga_init(const ga_params *q, const void *C, ga_dtype cdt, const void *W
                 }
                 (void)hipGetLastError();
                 prep_err = prepare_plain_kernels(max_lds);
+                if (prep_err == hipSuccess) prep_err = prepare_recheck_kernels(max_lds);
             });
             if (prep_err != hipSuccess)
                 return fail(nullptr, GA_ERR_DEVICE, std::string("kernel attributes: ") + hipGetErrorString(prep_err));
@@ -429,7 +433,7 @@ ga_status ga_init(const ga_params *q, const void *C, ga_dtype cdt, const void *W
                     max_lds = optin;
             }
             (void)hipGetLastError();
-            const size_t need = std::max<size_t>((size_t)d.p * d.p * 8 + (size_t)d.n * 10 + 512, (size_t)16 * d.n);
+            const size_t need = recheck_lds(d.n, d.p) + 4096;   // + the kernels' static LDS
             if (need > (size_t)max_lds)
                 return fail(nullptr, GA_ERR_INVALID, "n too large for this device's LDS (exact kernels)");
         }
@@ -491,7 +495,10 @@ ga_status ga_init(const ga_params *q, const void *C, ga_dtype cdt, const void *W
         P.tbuf = at<double>(b, c.tbuf);
         P.slot_r = at<int32_t>(b, c.slot_r);
         P.slot_c = at<int32_t>(b, c.slot_c);
+        P.slot_s = at<int32_t>(b, c.slot_s);
+        P.slot_done = at<int32_t>(b, c.slot_done);
         P.handled = at<int32_t>(b, c.handled);
+        P.choice = at<int32_t>(b, c.choice);
         P.total = at<int32_t>(b, c.total_slots);
         P.extra_r = at<int32_t>(b, c.extra_r);
         P.extra_c = at<int32_t>(b, c.extra_c);
@@ -857,7 +864,7 @@ ga_status ga_batch_set(ga_batch *b, ga_ctx *const *ctxs, int32_t count)
     std::vector<TickJob> tj(njobs);
     int min_p = 1 << 30, sel_threads = 64;
     int blocks[kTickPhases] = {};
-    size_t lds_cols = 0, lds_sums = 0;
+    size_t lds_recheck = 0;
     for (int j = 0; j < njobs; ++j) {
         const ga_ctx *c = grouped[j];
         const Dims &d = c->d;
@@ -865,8 +872,7 @@ ga_status ga_batch_set(ga_batch *b, ga_ctx *const *ctxs, int32_t count)
         D.push_back(&c->d);
         min_p = std::min(min_p, d.p);
         sel_threads = std::max(sel_threads, select_threads(d.m));
-        lds_cols = std::max(lds_cols, recheck_lds_cols(d.n, d.p));
-        lds_sums = std::max(lds_sums, recheck_lds_sums(d.n, d.p));
+        lds_recheck = std::max(lds_recheck, recheck_lds(d.n, d.p));
         TickJob &J = tj[j];
         memset(&J, 0, sizeof(J));
         J.P = c->P;
@@ -875,16 +881,13 @@ ga_status ga_batch_set(ga_batch *b, ga_ctx *const *ctxs, int32_t count)
         J.blocks[kTickOps] = ga_ops_blocks(d);
         J.blocks[kTickAlloc] = alloc_blocks(d.S);   // a multiple of 8: every context starts on XCD 0
         J.blocks[kTickFinal] = finalize_blocks(d.S);
-        J.blocks[kTickSel1] = d.R;
-        J.blocks[kTickCols] = 0;   // the re-evaluation draws from one pool of all contexts' items
-        J.blocks[kTickSums] = 0;
-        J.blocks[kTickSel2] = d.R;
+        J.blocks[kTickSel1] = d.R;   // the re-evaluation draws from one pool of all contexts' items
         for (int q = 0; q < kTickPhases; ++q) {
             J.start[q] = blocks[q];
             blocks[q] += J.blocks[q];
         }
     }
-    if (njobs && (lds_cols > recheck_group_lds_cap(0) || lds_sums > recheck_group_lds_cap(1)))
+    if (njobs && lds_recheck > recheck_group_lds_cap())
         return fail(nullptr, GA_ERR_INVALID, "batch: re-evaluation LDS exceeds the device limit");
     // tables, copied in stream order after earlier generations
     const size_t mbytes = ((mfma_job_bytes() * std::max(1, njobs)) + 255) & ~(size_t)255;
@@ -922,8 +925,7 @@ ga_status ga_batch_set(ga_batch *b, ga_ctx *const *ctxs, int32_t count)
     b->njobs = njobs;
     b->min_p = min_p;
     b->sel_threads = sel_threads;
-    b->lds_cols = lds_cols;
-    b->lds_sums = lds_sums;
+    b->lds_recheck = lds_recheck;
     memcpy(b->blocks, blocks, sizeof(blocks));
     // side streams (default priority) for the contexts stepped alone
     const int nside = std::min((int)solo.size(), 16);
@@ -984,7 +986,7 @@ ga_status ga_batch_step(ga_batch *b, int32_t generations)
                 return dev_fail(e, "grouped cost assembly");
             if ((e = launch_select1_group(tjobs, nj, b->blocks[kTickSel1], b->sel_threads, b->st)) != hipSuccess)
                 return dev_fail(e, "grouped selection");
-            if ((e = launch_recheck_group(tjobs, nj, b->blocks, b->lds_cols, b->lds_sums, b->st)) != hipSuccess)
+            if ((e = launch_recheck_group(tjobs, nj, b->lds_recheck, b->st)) != hipSuccess)
                 return dev_fail(e, "grouped re-evaluation");
         }
         if (nsolo)   // join

@@ -21,15 +21,16 @@ hipError_t launch_eval_exact(const DevPtrs &P, const Dims &d, const int32_t *hub
                              double *cost, double *parts, double *eps, hipStream_t st);
 hipError_t launch_eval_fp32(const DevPtrs &P, const Dims &d, const int32_t *hubs, const uint16_t *kidx, int count,
                             hipStream_t st);
-hipError_t launch_recheck(const DevPtrs &P, const Dims &d, const SelState &S, hipStream_t st);
 double fp32_eps_bound(int n);
-hipError_t launch_p0_exact(const DevPtrs &P, const Dims &d, hipStream_t st);
-size_t recheck_lds_cols(int n, int p);
-size_t recheck_lds_sums(int n, int p);
-size_t recheck_group_lds_cap(int which);   // 0: column sums, 1: candidate sums
-hipError_t launch_recheck_group(const TickJob *jobs, int njobs, const int *blocks, size_t lds_cols, size_t lds_sums,
-                                hipStream_t st);
 hipError_t prepare_plain_kernels(int max_lds);
+
+// exact re-evaluation of candidates, island decisions, P0 (recheck.hip)
+hipError_t launch_recheck(const DevPtrs &P, const Dims &d, hipStream_t st);
+hipError_t launch_p0_exact(const DevPtrs &P, const Dims &d, hipStream_t st);
+size_t recheck_lds(int n, int p);
+size_t recheck_group_lds_cap();
+hipError_t launch_recheck_group(const TickJob *jobs, int njobs, size_t lds, hipStream_t st);
+hipError_t prepare_recheck_kernels(int max_lds);
 
 // batched matrix-core evaluation (eval_mfma.hip)
 hipError_t launch_eval_split(const DevPtrs &P, const Dims &d, const uint16_t *kidx, int count, hipStream_t st,

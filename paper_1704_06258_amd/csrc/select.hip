@@ -7,7 +7,7 @@
 // rigorous bound |f~ - f| <= eps f, hence f in [lb, ub] = f~(1 -+ eps').
 // Stage 1 keeps as candidates the children whose interval could hold the
 // island minimum (lb <= min ub) and could beat the ancestor (lb < f_anc);
-// their exact costs are recomputed (k_canon_cols / k_canon_sums) and the
+// their exact costs are recomputed (k_recheck) and the
 // decision is taken on exact values, so it is the one exact arithmetic takes.
 // The last workgroup of k_select1 lists the candidates for re-evaluation (or,
 // with exact costs, ends the generation).
@@ -17,10 +17,12 @@
 namespace hubga {
 
 // Candidate slots for the column-parallel re-evaluation, in island order, up
-// to `tot`; handled[r] candidates of island r get a slot and the rest form the
-// extra list (re-evaluated one workgroup each).  One workgroup.
-__device__ inline void compact_candidates(const int32_t *__restrict__ cand_cnt, int R, int tot,
-                                          int32_t *__restrict__ slot_r, int32_t *__restrict__ slot_c,
+// to `tot`, each with its island, its candidate number and its child;
+// handled[r] candidates of island r get a slot and the rest form the extra
+// list (re-evaluated one workgroup each).  One workgroup.
+__device__ inline void compact_candidates(const int32_t *__restrict__ cand, const int32_t *__restrict__ cand_cnt,
+                                          int R, int m, int tot, int32_t *__restrict__ slot_r,
+                                          int32_t *__restrict__ slot_c, int32_t *__restrict__ slot_s,
                                           int32_t *__restrict__ handled, int32_t *__restrict__ total,
                                           int32_t *__restrict__ extra_r, int32_t *__restrict__ extra_c,
                                           int32_t *__restrict__ nextra)
@@ -50,6 +52,7 @@ __device__ inline void compact_candidates(const int32_t *__restrict__ cand_cnt, 
         for (int c = 0; c < h; ++c) {
             slot_r[off + c] = r;
             slot_c[off + c] = c;
+            slot_s[off + c] = cand[(size_t)r * m + c];
         }
         handled[r] = h;
         off += cnt;
@@ -82,6 +85,7 @@ __device__ __forceinline__ void select1_body(const SelState &S, const double *__
                                              const double *__restrict__ eps, const double *__restrict__ parts,
                                              int32_t *__restrict__ cand, int32_t *__restrict__ cand_cnt, int tot,
                                              int32_t *__restrict__ slot_r, int32_t *__restrict__ slot_c,
+                                             int32_t *__restrict__ slot_s,
                                              int32_t *__restrict__ handled, int32_t *__restrict__ total,
                                              int32_t *__restrict__ extra_r, int32_t *__restrict__ extra_c,
                                              int32_t *__restrict__ nextra, int *__restrict__ sync, int blk, int nblk)
@@ -159,19 +163,21 @@ __device__ __forceinline__ void select1_body(const SelState &S, const double *__
     if (S.exact)
         global_step(S);
     else
-        compact_candidates(cand_cnt, S.R, tot, slot_r, slot_c, handled, total, extra_r, extra_c, nextra);
+        compact_candidates(cand, cand_cnt, S.R, m, tot, slot_r, slot_c, slot_s, handled, total, extra_r, extra_c,
+                           nextra);
 }
 
 __global__ __launch_bounds__(1024) void k_select1(SelState S, const double *__restrict__ cost,
                                                   const double *__restrict__ eps, const double *__restrict__ parts,
                                                   int32_t *__restrict__ cand, int32_t *__restrict__ cand_cnt, int tot,
                                                   int32_t *__restrict__ slot_r, int32_t *__restrict__ slot_c,
+                                                  int32_t *__restrict__ slot_s,
                                                   int32_t *__restrict__ handled, int32_t *__restrict__ total,
                                                   int32_t *__restrict__ extra_r, int32_t *__restrict__ extra_c,
                                                   int32_t *__restrict__ nextra, int *__restrict__ sync)
 {
-    select1_body(S, cost, eps, parts, cand, cand_cnt, tot, slot_r, slot_c, handled, total, extra_r, extra_c, nextra,
-                 sync, blockIdx.x, gridDim.x);
+    select1_body(S, cost, eps, parts, cand, cand_cnt, tot, slot_r, slot_c, slot_s, handled, total, extra_r, extra_c,
+                 nextra, sync, blockIdx.x, gridDim.x);
 }
 
 __global__ __launch_bounds__(1024) void k_select1_group(const TickJob *__restrict__ jobs, int njobs)
@@ -179,18 +185,21 @@ __global__ __launch_bounds__(1024) void k_select1_group(const TickJob *__restric
     const TickJob &J = jobs[tick_job(jobs, njobs, kTickSel1, blockIdx.x)];
     const DevPtrs &P = J.P;
     const SelState S = make_sel_state(P, J.d);
-    select1_body(S, P.cost, P.eps, P.parts, P.cand, P.cand_cnt, J.d.tot, P.slot_r, P.slot_c, P.handled, P.total,
-                 P.extra_r, P.extra_c, P.nextra, P.sync, blockIdx.x - J.start[kTickSel1], J.blocks[kTickSel1]);
+    select1_body(S, P.cost, P.eps, P.parts, P.cand, P.cand_cnt, J.d.tot, P.slot_r, P.slot_c, P.slot_s, P.handled,
+                 P.total, P.extra_r, P.extra_c, P.nextra, P.sync, blockIdx.x - J.start[kTickSel1],
+                 J.blocks[kTickSel1]);
 }
 
 // Every island ancestor <- the single solution in best / best_cost (the
-// evaluated P0 of Sec. 4.1); generation, counters and grid counters reset.
-__global__ void k_init_state(int R, int p, int32_t *__restrict__ anc, double *__restrict__ anc_cost,
+// evaluated P0 of Sec. 4.1); generation, counters, grid and slot counters
+// reset.
+__global__ void k_init_state(int R, int p, int tot, int32_t *__restrict__ anc, double *__restrict__ anc_cost,
                              double *__restrict__ anc_parts, const int32_t *__restrict__ best,
                              const double *__restrict__ best_cost, int64_t *__restrict__ gen,
-                             int64_t *__restrict__ stats, int *__restrict__ sync)
+                             int64_t *__restrict__ stats, int *__restrict__ sync, int32_t *__restrict__ slot_done)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < tot) slot_done[t] = 0;
     if (t < R * p) anc[t] = best[t % p];
     if (t < R) {
         anc_cost[t] = best_cost[0];
@@ -205,9 +214,10 @@ __global__ void k_init_state(int R, int p, int32_t *__restrict__ anc, double *__
 
 hipError_t launch_init_state(const DevPtrs &P, const Dims &d, hipStream_t st)
 {
-    int tot = d.R * d.p > d.R ? d.R * d.p : d.R;
-    k_init_state<<<(tot + 255) / 256, 256, 0, st>>>(d.R, d.p, P.anc, P.anc_cost, P.anc_parts, P.best, P.best_cost,
-                                                    P.gen, P.stats, P.sync);
+    int span = d.R * d.p > d.R ? d.R * d.p : d.R;
+    span = span > d.tot ? span : d.tot;
+    k_init_state<<<(span + 255) / 256, 256, 0, st>>>(d.R, d.p, d.tot, P.anc, P.anc_cost, P.anc_parts, P.best,
+                                                     P.best_cost, P.gen, P.stats, P.sync, P.slot_done);
     return hipGetLastError();
 }
 
@@ -220,16 +230,17 @@ int select_threads(int m)
 }
 
 // Selection and the end of the generation: k_select1 (with the global step
-// for exact costs), else k_select1 -> k_canon_cols -> k_canon_sums -> k_select2.
+// for exact costs), else k_select1 -> k_recheck (exact re-evaluation of the
+// candidates, island decisions, global step).
 hipError_t launch_select(const DevPtrs &P, const Dims &d, int exact, hipStream_t st)
 {
     const int bt = select_threads(d.m);
     const SelState S = make_sel_state(P, d);
     k_select1<<<d.R, bt, 0, st>>>(S, P.cost, P.eps, P.parts, P.cand, P.cand_cnt, d.tot, P.slot_r, P.slot_c,
-                                  P.handled, P.total, P.extra_r, P.extra_c, P.nextra, P.sync);
+                                  P.slot_s, P.handled, P.total, P.extra_r, P.extra_c, P.nextra, P.sync);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || exact) return e;
-    return launch_recheck(P, d, S, st);
+    return launch_recheck(P, d, st);
 }
 
 hipError_t launch_select1_group(const TickJob *jobs, int njobs, int blocks, int threads, hipStream_t st)

@@ -30,7 +30,7 @@ __device__ inline bool last_block(int *counter, int nblocks)
     return is_last != 0;
 }
 
-// LDS of the block-wide reductions (one instance per kernel).
+// LDS of the island reduction of the first selection stage.
 struct ArgminScratch {
     double v[1024];
     int i[1024];
@@ -42,13 +42,14 @@ __device__ inline ArgminScratch &argmin_scratch()
 }
 
 // Block-wide (value, index) argmin over v[0..count) read through f(i);
-// returns the index (-1 if count == 0).  Ties go to the lower index.
+// returns the index (-1 if count == 0).  Ties go to the lower index; any
+// workgroup size up to 1024.  (value, index) pairs are totally ordered, so the
+// order of the lane and wave merges does not change the result.
 template <typename F>
 __device__ inline int block_argmin(int count, F f, double *out_value)
 {
-    ArgminScratch &sc = argmin_scratch();
-    double *sv = sc.v;
-    int *si = sc.i;
+    __shared__ double wv[16];
+    __shared__ int wi[16];
     const int tid = threadIdx.x, nt = blockDim.x;
     double bv = 0.0;
     int bi = -1;
@@ -59,19 +60,32 @@ __device__ inline int block_argmin(int count, F f, double *out_value)
             bi = i;
         }
     }
-    __syncthreads();
-    sv[tid] = bv;
-    si[tid] = bi;
-    __syncthreads();
-    for (int w = nt / 2; w > 0; w >>= 1) {
-        if (tid < w && si[tid + w] >= 0 && better(sv[tid + w], si[tid + w], sv[tid], si[tid])) {
-            sv[tid] = sv[tid + w];
-            si[tid] = si[tid + w];
+    for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(bv, off);
+        const int oi = __shfl_xor(bi, off);
+        if (oi >= 0 && better(ov, oi, bv, bi)) {
+            bv = ov;
+            bi = oi;
         }
-        __syncthreads();
     }
-    const int r = si[0];
-    if (out_value) *out_value = sv[0];
+    __syncthreads();   // wv / wi free from a previous call
+    if ((tid & 63) == 0) {
+        wv[tid >> 6] = bv;
+        wi[tid >> 6] = bi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        for (int w = 1; w < (nt + 63) / 64; ++w)
+            if (wi[w] >= 0 && better(wv[w], wi[w], bv, bi)) {
+                bv = wv[w];
+                bi = wi[w];
+            }
+        wv[0] = bv;
+        wi[0] = bi;
+    }
+    __syncthreads();
+    const int r = wi[0];
+    if (out_value) *out_value = wv[0];
     __syncthreads();
     return r;
 }
@@ -111,25 +125,6 @@ __host__ __device__ inline SelState make_sel_state(const DevPtrs &P, const Dims 
     S.cand_cost = P.cand_cost;
     S.cand_parts = P.cand_parts;
     return S;
-}
-
-// Island r: the exactly re-evaluated candidates decide (ties to the lower
-// candidate, i.e. the lower child index); elitist mode keeps the ancestor
-// unless strictly beaten.
-__device__ inline void select_island_exact(const SelState &S, int r)
-{
-    const int cnt = S.cand_cnt[r];
-    if (cnt == 0) return;
-    double v;
-    const int c = block_argmin(cnt, [&](int i) { return S.cand_cost[(size_t)r * S.m + i]; }, &v);
-    if (S.elitist && !(v < S.anc_cost[r])) return;
-    const int sb = S.cand[(size_t)r * S.m + c];
-    for (int k = threadIdx.x; k < S.p; k += blockDim.x) S.anc[(size_t)r * S.p + k] = S.children[(size_t)sb * S.p + k];
-    if (threadIdx.x == 0) {
-        S.anc_cost[r] = v;
-        for (int q = 0; q < 3; ++q) S.anc_parts[3 * (size_t)r + q] = S.cand_parts[3 * ((size_t)r * S.m + c) + q];
-    }
-    __syncthreads();
 }
 
 // End of a generation (one workgroup): counters, the global step every n1
@@ -181,6 +176,135 @@ __device__ inline void global_step(const SelState &S)
         S.stats[0] = g + 1;
         S.stats[1] += sc;
         S.stats[2] += sr;
+        S.stats[3] += S.S;
+    }
+    __syncthreads();
+}
+
+// Every island decided on the exact costs of its candidates (ties to the
+// lower candidate, i.e. the lower child index; elitist mode keeps the ancestor
+// unless strictly beaten), then the end of the generation -- counters, the
+// global step every n1 generations (the best island, ties to the lowest,
+// replaces all), best so far, g <- g + 1 -- in one pass over the islands.
+// The best island and the source of its hub list and parts come out of the
+// pass itself, so nothing written in it is read back.  One workgroup of any
+// size up to 1024; choice: R ints of scratch.
+__device__ inline void decide_generation(const SelState &S, int32_t *__restrict__ choice)
+{
+    __shared__ double wv[16];
+    __shared__ int wi[16], wsb[16], wo[16], wcc[16], wcr[16];
+    __shared__ double sh_parts[3];
+    const int tid = threadIdx.x, nt = blockDim.x, m = S.m, p = S.p;
+    const int64_t g = *S.gen;
+    const double best0 = S.best_cost[0];
+    const bool gstep = (g + 1) % S.n1 == 0;
+    double bv = 0.0;
+    int bi = -1, bsb = -1, bo = -1, cc = 0, cr = 0;
+    for (int r = tid; r < S.R; r += nt) {
+        const int cnt = S.cand_cnt[r];
+        const double fa = S.anc_cost[r];
+        double v = 0.0;
+        int c = -1;
+        for (int i0 = 0; i0 < cnt; i0 += 4) {   // four loads in flight
+            double x[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) x[u] = i0 + u < cnt ? S.cand_cost[(size_t)r * m + i0 + u] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (i0 + u < cnt && (c < 0 || x[u] < v)) {
+                    v = x[u];
+                    c = i0 + u;
+                }
+        }
+        const bool take = c >= 0 && (!S.elitist || v < fa);
+        const int o = take ? r * m + c : -1;
+        const int sb = take ? S.cand[o] : -1;
+        const double fr = take ? v : fa;
+        choice[r] = sb;
+        if (take) {
+            S.anc_cost[r] = v;
+            for (int q = 0; q < 3; ++q) S.anc_parts[3 * (size_t)r + q] = S.cand_parts[3 * (size_t)o + q];
+        }
+        cc += cnt;
+        cr += cnt > 0;
+        if (better(fr, r, bv, bi)) {
+            bv = fr;
+            bi = r;
+            bsb = sb;
+            bo = o;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(bv, off);
+        const int oi = __shfl_xor(bi, off), osb = __shfl_xor(bsb, off), oo = __shfl_xor(bo, off);
+        if (oi >= 0 && better(ov, oi, bv, bi)) {
+            bv = ov;
+            bi = oi;
+            bsb = osb;
+            bo = oo;
+        }
+        cc += __shfl_xor(cc, off);
+        cr += __shfl_xor(cr, off);
+    }
+    if ((tid & 63) == 0) {
+        wv[tid >> 6] = bv;
+        wi[tid >> 6] = bi;
+        wsb[tid >> 6] = bsb;
+        wo[tid >> 6] = bo;
+        wcc[tid >> 6] = cc;
+        wcr[tid >> 6] = cr;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        for (int w = 1; w < (nt + 63) / 64; ++w) {
+            if (wi[w] >= 0 && better(wv[w], wi[w], bv, bi)) {
+                bv = wv[w];
+                bi = wi[w];
+                bsb = wsb[w];
+                bo = wo[w];
+            }
+            cc += wcc[w];
+            cr += wcr[w];
+        }
+        wv[0] = bv;
+        wi[0] = bi;
+        wsb[0] = bsb;
+        wo[0] = bo;
+        for (int q = 0; q < 3; ++q)
+            sh_parts[q] = bo >= 0 ? S.cand_parts[3 * (size_t)bo + q] : S.anc_parts[3 * (size_t)bi + q];
+    }
+    __syncthreads();
+    const int rs = wi[0], sbs = wsb[0];
+    const double vs = wv[0];
+    auto hub_of_rs = [&](int k) { return sbs >= 0 ? S.children[(size_t)sbs * p + k] : S.anc[(size_t)rs * p + k]; };
+    // hub lists: the global step gives every other island rs's; else each island its choice
+    for (int e = tid; e < S.R * p; e += nt) {
+        const int r = e / p, k = e - r * p;
+        if (gstep && r != rs) {
+            S.anc[e] = hub_of_rs(k);
+        } else {
+            const int sb = choice[r];
+            if (sb >= 0) S.anc[e] = S.children[(size_t)sb * p + k];
+        }
+    }
+    if (gstep)
+        for (int r = tid; r < S.R; r += nt)
+            if (r != rs) {
+                S.anc_cost[r] = vs;
+                for (int q = 0; q < 3; ++q) S.anc_parts[3 * (size_t)r + q] = sh_parts[q];
+            }
+    if (vs < best0) {
+        for (int k = tid; k < p; k += nt) S.best[k] = hub_of_rs(k);
+        if (tid == 0) {
+            S.best_cost[0] = vs;
+            for (int q = 0; q < 3; ++q) S.best_cost[1 + q] = sh_parts[q];
+        }
+    }
+    if (tid == 0) {
+        *S.gen = g + 1;
+        S.stats[0] = g + 1;
+        S.stats[1] += cc;
+        S.stats[2] += cr;
         S.stats[3] += S.S;
     }
     __syncthreads();
