@@ -7,19 +7,22 @@
 // Outputs per individual s: kidx[s][i] = hub position (kNoHub in the padding
 // up to n_pad), the largest cluster size, and (when asked) the collection and
 // distribution sums Cc = sum_i O_i c_i, Dd = sum_i D_i c_i with c_i =
-// C[i][a_i] in binary64 (fixed tree order), and the FP32 hub-to-hub table
+// C[i][a_i] in binary64 (a fixed summation order), and the FP32 hub-to-hub table
 // Ch32[s][k][l] = C[h_k][h_l] used by the batched kernel's epilogue.
 #include "kernels.hpp"
 
 namespace hubga {
 
-constexpr int kScanChunk = 16;   // hub distances loaded together by one lane
+constexpr int kScanHubs = 4;    // hubs per scan chunk
+constexpr int kScanNodes = 4;   // nodes per lane scanned together
 
 // Workgroup blk (of a grid of alloc_blocks(count)) of one context: individual
-// s = the workgroup's place in XCD-major order.  The hub ids are read with
-// scalar loads (the same for every lane), so each distance load needs no
-// per-lane address arithmetic and no LDS round trip; a node-to-position table
-// in LDS answers "is node i a hub" with one read.
+// s = the workgroup's place in XCD-major order.  A lane takes kScanNodes nodes
+// i = g0 + t*256 + tid at once and scans the hubs in chunks of kScanHubs: the
+// chunk's distances for all its nodes are loaded together, then merged (loads
+// past n re-read valid addresses and are not used).  Few registers, so many
+// workgroups share a CU and hide each other's load latency.  A
+// node-to-position table in LDS answers "is node i a hub" with one read.
 template <typename CT>
 __device__ __forceinline__ void alloc_body(const int32_t *__restrict__ hubs, int count, int n, int n_pad, int p,
                                            const CT *__restrict__ Ct, const float *__restrict__ Ct32,
@@ -29,11 +32,12 @@ __device__ __forceinline__ void alloc_body(const int32_t *__restrict__ hubs, int
                                            int blk)
 {
 #pragma clang fp contract(off)
+    constexpr int T = kScanNodes, H = kScanHubs;
     __shared__ int sh_h[kMaxP];
     __shared__ __align__(16) int sh_off[kMaxP];   // row offsets h*n in the FP32 copy; padding: row n (+inf)
     __shared__ int sh_cnt[kMaxP];
     __shared__ uint8_t sh_pos[kMaxN];   // position of node i in the hub list, 0xFF for spokes
-    __shared__ double red_c[256], red_d[256];
+    __shared__ double red_c[4], red_d[4];
     // XCD-major order: consecutive individuals (children of one island) run
     // on the same XCD (workgroup index % 8; a grouped launch starts every
     // context on a multiple of 8) and share its L2.
@@ -52,94 +56,137 @@ __device__ __forceinline__ void alloc_body(const int32_t *__restrict__ hubs, int
     }
     if (tid < kMaxP) sh_off[tid] = (tid < p ? hrow[tid] : n) * n;
     __syncthreads();
-    const int p16 = (p + kScanChunk - 1) / kScanChunk * kScanChunk;
+    const int nchunks = (p + H - 1) / H;
     double pc = 0.0, pd = 0.0;
     uint16_t *krow = kidx + (size_t)s * n_pad;
-    for (int i = tid; i < n_pad; i += 256) {
-        if (i >= n) {
-            krow[i] = kNoHub;
-            continue;
+    for (int g0 = 0; g0 < n_pad; g0 += 256 * T) {
+        int ii[T], ic[T];   // nodes, and the same clamped to a valid row position
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            ii[t] = g0 + t * 256 + tid;
+            ic[t] = ii[t] < n ? ii[t] : n - 1;
         }
-        int best;
-        const int self = sh_pos[i];
-        if (self != 0xFF) {   // a hub keeps itself
-            best = self;
-        } else {
-            // Scan in FP32: rounding to FP32 is monotone, so a unique FP32
-            // minimum is also the unique minimum of the instance values.  When
-            // several hubs share the FP32 minimum, rescan in the instance
-            // dtype (strict <, ties to the smaller hub id).
-            // Branch-free: per chunk its minimum, first position and number of
-            // hubs at it; merged over chunks (selects, no per-hub branches).
-            best = 0;
-            float bd = __builtin_huge_valf();
-            int at_min = 0;   // hubs at the FP32 minimum so far
-            for (int k0 = 0; k0 < p16; k0 += kScanChunk) {
-                float v[kScanChunk];
+        // FP32 scan: rounding to FP32 is monotone, so a unique FP32 minimum is
+        // also the unique minimum of the instance values.  Per node: the
+        // running minimum, its first hub position and how many hubs are at it.
+        float bd[T];
+        int best[T], at_min[T];
 #pragma unroll
-                for (int u = 0; u < kScanChunk; ++u) v[u] = Ct32[sh_off[k0 + u] + i];   // padding reads +inf
-                float m = v[0];
+        for (int t = 0; t < T; ++t) {
+            bd[t] = __builtin_huge_valf();
+            best[t] = 0;
+            at_min[t] = 0;
+        }
+        float A[T][H];
+        auto load = [&](float(&X)[T][H], int c) {
+            const int4 o = *(const int4 *)(sh_off + c * H);
+            const int off[H] = {o.x, o.y, o.z, o.w};
 #pragma unroll
-                for (int u = 1; u < kScanChunk; ++u) m = fminf(m, v[u]);
-                int first = kScanChunk - 1, cnt = 0;
+            for (int t = 0; t < T; ++t)
 #pragma unroll
-                for (int u = kScanChunk - 1; u >= 0; --u) {
-                    const int eq = v[u] == m ? 1 : 0;
+                for (int u = 0; u < H; ++u) X[t][u] = Ct32[off[u] + ic[t]];   // padding hubs read +inf
+        };
+        auto merge = [&](const float(&X)[T][H], int c) {
+#pragma unroll
+            for (int t = 0; t < T; ++t) {
+                float m = X[t][0];
+#pragma unroll
+                for (int u = 1; u < H; ++u) m = fminf(m, X[t][u]);
+                int first = H - 1, cnt = 0;
+#pragma unroll
+                for (int u = H - 1; u >= 0; --u) {
+                    const int eq = X[t][u] == m ? 1 : 0;
                     first = eq ? u : first;
                     cnt += eq;
                 }
-                const bool lt = m < bd, same = m == bd;
-                at_min = lt ? cnt : (same ? at_min + cnt : at_min);
-                best = lt ? k0 + first : best;
-                bd = lt ? m : bd;
+                const bool lt = m < bd[t], same = m == bd[t];
+                at_min[t] = lt ? cnt : (same ? at_min[t] + cnt : at_min[t]);
+                best[t] = lt ? c * H + first : best[t];
+                bd[t] = lt ? m : bd[t];
             }
-            const bool tie = at_min > 1;   // (+inf padding ties only when every distance is +inf: rescanned)
-            if (tie) {
-                best = 0;
+        };
+        for (int c = 0; c < nchunks; ++c) {
+            load(A, c);
+            merge(A, c);
+        }
+        // hubs keep themselves; FP32 ties are rescanned in the instance dtype
+        // (strict <, ties to the smaller hub id; +inf padding ties only when
+        // every distance is +inf: rescanned too)
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            const int i = ii[t];
+            if (i >= n) continue;
+            const int self = sh_pos[i];
+            if (self != 0xFF) {
+                best[t] = self;
+            } else if (at_min[t] > 1) {
+                int b = 0;
                 CT be = Ct[(size_t)hrow[0] * n + i];
                 for (int k = 1; k < p; ++k) {
                     const CT v = Ct[(size_t)hrow[k] * n + i];
                     if (v < be) {
                         be = v;
-                        best = k;
+                        b = k;
                     }
+                }
+                best[t] = b;
+            }
+        }
+        // outputs, two nodes at a time (few registers): position, cluster
+        // count, and the binary64 terms O_i c_i and D_i c_i in node order
+#pragma unroll
+        for (int t0 = 0; t0 < T; t0 += 2) {
+            double cv[2], ov[2], dv[2];
+            if (want_sums) {
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int t = t0 + u;
+                    cv[u] = (double)Ct[(size_t)sh_h[best[t]] * n + ic[t]];
+                    ov[u] = O[ic[t]];
+                    dv[u] = D[ic[t]];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int t = t0 + u, i = ii[t];
+                if (i >= n_pad) continue;
+                if (i >= n) {
+                    krow[i] = kNoHub;
+                    continue;
+                }
+                krow[i] = (uint16_t)best[t];
+                atomicAdd(&sh_cnt[best[t]], 1);
+                if (want_sums) {
+                    pc = pc + ov[u] * cv[u];
+                    pd = pd + dv[u] * cv[u];
                 }
             }
         }
-        krow[i] = (uint16_t)best;
-        atomicAdd(&sh_cnt[best], 1);
-        if (want_sums) {
-            const double ci = (double)Ct[(size_t)sh_h[best] * n + i];
-            pc = pc + O[i] * ci;
-            pd = pd + D[i] * ci;
-        }
     }
-    if (Ch32)
-        for (int e = tid; e < p * p; e += 256) {
-            const int k = e / p, l = e % p;
-            Ch32[(size_t)s * p * p + e] = (float)Ct[(size_t)sh_h[l] * n + sh_h[k]];   // C[h_k][h_l]
-        }
+    if (Ch32)   // the hub-to-hub table C[h_k][h_l] in FP32
+        for (int e = tid; e < p * p; e += 256)
+            Ch32[(size_t)s * p * p + e] = (float)Ct[(size_t)sh_h[e % p] * n + sh_h[e / p]];
+    // Cc and Dd: each wave's lanes merged by halving distance, then the four
+    // waves in order (a fixed order)
     if (want_sums) {
-        red_c[tid] = pc;
-        red_d[tid] = pd;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            pc = pc + __shfl_xor(pc, off);
+            pd = pd + __shfl_xor(pd, off);
+        }
+        if ((tid & 63) == 0) {
+            red_c[tid >> 6] = pc;
+            red_d[tid >> 6] = pd;
+        }
     }
     __syncthreads();
-    if (want_sums) {
-        for (int w = 128; w > 0; w >>= 1) {
-            if (tid < w) {
-                red_c[tid] = red_c[tid] + red_c[tid + w];
-                red_d[tid] = red_d[tid] + red_d[tid + w];
-            }
-            __syncthreads();
-        }
-    }
     if (tid == 0) {
         int mx = 0;
         for (int k = 0; k < p; ++k) mx = sh_cnt[k] > mx ? sh_cnt[k] : mx;
         cmax[s] = mx;
         if (want_sums) {
-            parts[3 * (size_t)s + 0] = red_c[0];
-            parts[3 * (size_t)s + 2] = red_d[0];
+            parts[3 * (size_t)s + 0] = ((red_c[0] + red_c[1]) + red_c[2]) + red_c[3];
+            parts[3 * (size_t)s + 2] = ((red_d[0] + red_d[1]) + red_d[2]) + red_d[3];
         }
     }
 }
@@ -163,7 +210,7 @@ hipError_t launch_copy_clamp(const int32_t *src, int32_t *dst, int total, int n,
 }
 
 template <typename CT>
-__global__ __launch_bounds__(256) void k_alloc(const int32_t *__restrict__ hubs, int count, int n, int n_pad, int p,
+__global__ __launch_bounds__(256, 8) void k_alloc(const int32_t *__restrict__ hubs, int count, int n, int n_pad, int p,
                                                const CT *__restrict__ Ct, const float *__restrict__ Ct32,
                                                const double *__restrict__ O, const double *__restrict__ D,
                                                uint16_t *__restrict__ kidx, double *__restrict__ parts,
@@ -174,7 +221,7 @@ __global__ __launch_bounds__(256) void k_alloc(const int32_t *__restrict__ hubs,
 
 // Grouped: the children of every context, with their sums and hub tables
 // (the split-bf16 generation).
-__global__ __launch_bounds__(256) void k_alloc_group(const TickJob *__restrict__ jobs, int njobs)
+__global__ __launch_bounds__(256, 8) void k_alloc_group(const TickJob *__restrict__ jobs, int njobs)
 {
     const TickJob &J = jobs[tick_job(jobs, njobs, kTickAlloc, blockIdx.x)];
     const int blk = blockIdx.x - J.start[kTickAlloc];
