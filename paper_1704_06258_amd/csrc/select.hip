@@ -96,21 +96,29 @@ __device__ __forceinline__ void select1_body(const SelState &S, const double *__
     const int r = blk, tid = threadIdx.x, nt = blockDim.x;
     const int s = r * m + tid;
     const bool live = tid < m;
+    __shared__ int sh_anc[kMaxP];
+    if (!S.exact && tid < p) sh_anc[tid] = S.anc[(size_t)r * p + tid];
     const double fa = S.anc_cost[r];
     double f = live ? cost[s] : 0.0;
     double lb = f, ub = f;
     bool same_as_anc = false;
+    if (!S.exact) __syncthreads();   // sh_anc
     if (!S.exact && live) {
         double e = 2.0 * eps[s] + 8.881784197001252e-16;   // + 2^-50 for the interval arithmetic itself
         lb = f * (1.0 - e);
         ub = f * (1.0 + e);
-        // a child identical to the ancestor has the ancestor's exact cost
-        same_as_anc = true;
-        for (int k = 0; k < p; ++k)
-            if (S.children[(size_t)s * p + k] != S.anc[(size_t)r * p + k]) {
-                same_as_anc = false;
-                break;
-            }
+        // a child identical to the ancestor has the ancestor's exact cost;
+        // its hub list is compared 16 ids at a time, all loads in flight
+        int diff = 0;
+        for (int k0 = 0; k0 < p; k0 += 16) {
+            int h[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) h[u] = k0 + u < p ? S.children[(size_t)s * p + k0 + u] : 0;
+#pragma unroll
+            for (int u = 0; u < 16; ++u)
+                if (k0 + u < p) diff |= h[u] ^ sh_anc[k0 + u];
+        }
+        same_as_anc = diff == 0;
         if (same_as_anc) lb = ub = fa;
     }
     // (min ub, index) over the island; exact mode: (min f, lowest j)
