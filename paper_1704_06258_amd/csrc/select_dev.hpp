@@ -203,27 +203,50 @@ __device__ inline void decide_generation(const SelState &S, int32_t *__restrict_
     for (int r = tid; r < S.R; r += nt) {
         const int cnt = S.cand_cnt[r];
         const double fa = S.anc_cost[r];
-        double v = 0.0;
-        int c = -1;
-        for (int i0 = 0; i0 < cnt; i0 += 4) {   // four loads in flight
-            double x[4];
+        // the first four candidates' costs, children and parts are read
+        // together (valid addresses whatever cnt is), the rest in a loop
+        constexpr int Q = 4;
+        double x[Q], xp[Q][3];
+        int xc[Q];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) x[u] = i0 + u < cnt ? S.cand_cost[(size_t)r * m + i0 + u] : 0.0;
+        for (int u = 0; u < Q; ++u) {
+            const size_t o = (size_t)r * m + (u < m ? u : m - 1);
+            x[u] = S.cand_cost[o];
+            xc[u] = S.cand[o];
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (i0 + u < cnt && (c < 0 || x[u] < v)) {
-                    v = x[u];
-                    c = i0 + u;
-                }
+            for (int q = 0; q < 3; ++q) xp[u][q] = S.cand_parts[3 * o + q];
+        }
+        double v = 0.0, vp[3] = {0.0, 0.0, 0.0};
+        int c = -1, sb = -1;
+#pragma unroll
+        for (int u = 0; u < Q; ++u)
+            if (u < cnt && (c < 0 || x[u] < v)) {
+                v = x[u];
+                c = u;
+                sb = xc[u];
+#pragma unroll
+                for (int q = 0; q < 3; ++q) vp[q] = xp[u][q];
+            }
+        for (int i = Q; i < cnt; ++i) {
+            const double y = S.cand_cost[(size_t)r * m + i];
+            if (y < v) {
+                v = y;
+                c = i;
+            }
+        }
+        if (c >= Q) {
+            const size_t o = (size_t)r * m + c;
+            sb = S.cand[o];
+            for (int q = 0; q < 3; ++q) vp[q] = S.cand_parts[3 * o + q];
         }
         const bool take = c >= 0 && (!S.elitist || v < fa);
         const int o = take ? r * m + c : -1;
-        const int sb = take ? S.cand[o] : -1;
+        if (!take) sb = -1;
         const double fr = take ? v : fa;
         choice[r] = sb;
         if (take) {
             S.anc_cost[r] = v;
-            for (int q = 0; q < 3; ++q) S.anc_parts[3 * (size_t)r + q] = S.cand_parts[3 * (size_t)o + q];
+            for (int q = 0; q < 3; ++q) S.anc_parts[3 * (size_t)r + q] = vp[q];
         }
         cc += cnt;
         cr += cnt > 0;
