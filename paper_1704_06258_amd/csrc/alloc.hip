@@ -46,17 +46,27 @@ __device__ __forceinline__ void alloc_body(const int32_t *__restrict__ hubs, int
     if (s >= count) return;
     const int tid = threadIdx.x;
     const int32_t *__restrict__ hrow = hubs + (size_t)s * p;
+    const int hk = tid < p ? hrow[tid] : n;   // in flight while LDS is cleared
     for (int e = tid; e < n; e += 256) sh_pos[e] = 0xFF;
     if (tid < kMaxP) sh_cnt[tid] = 0;
     __syncthreads();
     if (tid < p) {
-        const int h = hrow[tid];
-        sh_h[tid] = h;
-        sh_pos[h] = (uint8_t)tid;
+        sh_h[tid] = hk;
+        sh_pos[hk] = (uint8_t)tid;
     }
-    if (tid < kMaxP) sh_off[tid] = (tid < p ? hrow[tid] : n) * n;
+    if (tid < kMaxP) sh_off[tid] = hk * n;
     __syncthreads();
     const int nchunks = (p + H - 1) / H;
+    // the hub-to-hub table C[h_k][h_l] in FP32: its first 512 entries are
+    // gathered now, in flight during the scan, and stored at the end
+    float chv[2];
+    if (Ch32) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int e = tid + q * 256;
+            chv[q] = e < p * p ? (float)Ct[(size_t)sh_h[e % p] * n + sh_h[e / p]] : 0.0f;
+        }
+    }
     double pc = 0.0, pd = 0.0;
     uint16_t *krow = kidx + (size_t)s * n_pad;
     for (int g0 = 0; g0 < n_pad; g0 += 256 * T) {
@@ -163,9 +173,15 @@ __device__ __forceinline__ void alloc_body(const int32_t *__restrict__ hubs, int
             }
         }
     }
-    if (Ch32)   // the hub-to-hub table C[h_k][h_l] in FP32
-        for (int e = tid; e < p * p; e += 256)
+    if (Ch32) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int e = tid + q * 256;
+            if (e < p * p) Ch32[(size_t)s * p * p + e] = chv[q];
+        }
+        for (int e = tid + 512; e < p * p; e += 256)
             Ch32[(size_t)s * p * p + e] = (float)Ct[(size_t)sh_h[e % p] * n + sh_h[e / p]];
+    }
     // Cc and Dd: each wave's lanes merged by halving distance, then the four
     // waves in order (a fixed order)
     if (want_sums) {

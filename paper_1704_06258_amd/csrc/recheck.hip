@@ -357,10 +357,16 @@ __device__ __forceinline__ void rc_finish_slot(const DevPtrs &P, const Dims &d, 
 #pragma clang fp contract(off)
     __shared__ double sums[3];
     const RcLds L = rc_lds(smem, d.p);
+    size_t o = 0;
+    double Cc = 0.0, Dd = 0.0;
+    if (threadIdx.x == 0) {   // read while T is summed
+        o = (size_t)P.slot_r[slot] * V.m + P.slot_c[slot];
+        Cc = V.parts_out[3 * o + 0];
+        Dd = V.parts_out[3 * o + 2];
+    }
     rc_sums<CT, 1>(P, d, slot, L, sh_h, sums);
     if (threadIdx.x == 0) {
-        const size_t o = (size_t)P.slot_r[slot] * V.m + P.slot_c[slot];
-        const double T = sums[0], Cc = V.parts_out[3 * o + 0], Dd = V.parts_out[3 * o + 2];
+        const double T = sums[0];
         V.cost_out[o] = (((d.chi * Cc) + (d.alpha * T)) + (d.delta * Dd)) * d.scale;
         V.parts_out[3 * o + 1] = T;
     }
