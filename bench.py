@@ -42,9 +42,10 @@ MFMA_SRC = os.path.join(ROOT, "paper_1704_06258_amd", "csrc", "eval_mfma.hip")
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "eval_mfma_clustered_n1000_p20_traffic.md")
 
 
-def flops_per_eval(n, p):
-    """Matrix-core flops per individual: two passes (hi, lo) of an n x n by n x p product."""
-    return 2 * 2 * n * n * p
+def flops_per_eval(n, p, folded=False):
+    """Matrix-core flops per individual: two passes (hi, lo) of an n x n by n x p
+    product, or, folded (C symmetric), of its upper triangle with the diagonal."""
+    return 2 * p * n * (n + 1) if folded else 2 * 2 * n * n * p
 
 
 def traffic_from_profile():
@@ -200,7 +201,8 @@ def main():
     ms_per_step = 1e3 * dt / args.steps
     value = S * args.steps / dt
     k_avg_ms = kms / max(launches, 1)
-    flop_launch = flops_per_eval(N, P) * S
+    folded = solver.folded()
+    flop_launch = flops_per_eval(N, P, folded) * S
     achieved = flop_launch / (k_avg_ms * 1e-3) / 1e12
     stats = solver.stats()
     out = {
@@ -223,7 +225,8 @@ def main():
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_BF16_TFLOPS, "traffic": traffic_from_profile(),
                      "kernel": "k_eval_mfma", "avg_launch_ms": k_avg_ms, "launches": launches,
-                     "flop_per_launch": flop_launch, "tile_config": tile_cfg,
+                     "flop_per_launch": flop_launch, "folded": folded,
+                     "unfolded_flop_per_launch": flops_per_eval(N, P) * S, "tile_config": tile_cfg,
                      "tile": hubga.tile_configs()[tile_cfg],
                      "autotune_ms": tune["ms"] if tune else None},
         "recheck_per_generation": stats["rechecks"] / max(stats["generations"], 1),

@@ -191,11 +191,24 @@ ga_status ga_set_stream(ga_ctx *ctx, void *hip_stream);
  * gives rows and columns of W x [A_1..A_S] per workgroup tile and the K depth
  * staged per step.  ga_set_tile_config selects one for the context's later
  * batched evaluations (results agree to the returned error bounds in every
- * configuration; the default is 0).  Pipelined configurations (those with a
- * K depth of 32 staged through an LDS ring) are the ones batches take. */
+ * configuration; the default is 0).  Pipelined configurations (the K tiles
+ * staged through an LDS ring: 6 and above) are the ones batches take. */
 int32_t ga_tile_config_count(void);
 ga_status ga_tile_config_info(int32_t config, int32_t *rows, int32_t *cols, int32_t *ktile);
 ga_status ga_set_tile_config(ga_ctx *ctx, int32_t config);
+
+/* Folded evaluation of the inter-hub term T of objective (1) (Sec. 3, each
+ * node allocated to one hub a(i)): when C is symmetric,
+ * sum_{i,j} W_ij C[a(i)][a(j)] equals the same sum over the folded matrix
+ * W_ij + W_ji (j > i), W_ii (j = i), 0 (j < i).  The pipelined configurations
+ * with a K depth of 64 then multiply only the K tiles on and above each row
+ * tile's diagonal block, about half the matrix-core work; results keep their
+ * error bounds (W >= 0, so the folded entries carry the same relative split
+ * error).  *folded is set to 1 when the context's current tile configuration
+ * does this (split-bf16 precision, c_symmetric set, a K-64 pipelined
+ * configuration, at least 3 hubs), else 0.  GA_ERR_INVALID for a NULL
+ * argument. */
+ga_status ga_evaluation_folded(ga_ctx *ctx, int32_t *folded);
 
 /* Batches: several contexts advanced together, generation by generation (the
  * islands of every context run the steps of ga_step).  Split-bf16 contexts

@@ -25,6 +25,8 @@ struct DevPtrs {
     uint16_t *Wlo;
     uint16_t *Whsw;     // W hi/lo in fragment order: 16-byte chunk (row r, k 8c..8c+7) at
     uint16_t *Wlsw;     //   ((r/64 * n_pad/16 + k/16)*2 + (k/8)%2)*64 + r%64
+    uint16_t *Wfhsw;    // the same layout of the folded W (C symmetric): W_rk + W_kr above the
+    uint16_t *Wflsw;    //   diagonal, W_rr on it, zero below; else null
     double *O, *D, *dsum;
     int32_t *hubs;      // S*p current batch / children (sorted)
     uint16_t *kidx;     // S*n_pad hub positions (kNoHub in the padding)
@@ -66,6 +68,7 @@ struct Dims {
     int tot;            // candidate slots of the column-parallel exact re-evaluation
     int mfma_cfg;       // tile configuration of the batched kernel
     int c_f32, w_f32;   // instance dtypes (1 = FP32)
+    int sym;            // C == C^T: the batched K-64 configurations use the folded W
     double chi, alpha, delta, scale;
     uint64_t seed;
 };

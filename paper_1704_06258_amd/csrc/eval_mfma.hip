@@ -235,12 +235,14 @@ __device__ __forceinline__ void pin(u32x4 &v) { asm volatile("" : "+v"(v)); }
 
 // One context's operands for the batched kernel (also one entry of a grouped
 // launch over several contexts).
+// n_rt row tiles by n_nt column tiles are the work units; n_mt is the number
+// of partials per column (one per row tile: n_mt == n_rt).
 struct MfmaJob {
-    const u32x4 *Whsw, *Wlsw;
+    const u32x4 *Whsw, *Wlsw;   // W in fragment order, the folded W when fold is set
     const uint16_t *kidx;
     const float *Ch32;
     double *partial;
-    int n, n_pad, p, count, NS, n_mt, n_nt, tile_start;
+    int n, n_pad, p, count, NS, n_mt, n_nt, tile_start, n_rt, fold;
 };
 
 // Ring size in 16-byte chunks; MODE 2 stages K tiles of 64 (the rest 32).
@@ -257,7 +259,7 @@ constexpr int pipe_ring_chunks()
 template <int ROWB, int COLB>
 __device__ __forceinline__ void pipe_epilogue(const MfmaJob &J, f32x16 (&acc)[ROWB][COLB], const int (&col)[COLB],
                                               const uint32_t (&lq)[COLB], int mt, int nt, u32x4 *ring,
-                                              int ring_chunks)
+                                              int ring_chunks, int slot)
 {
     constexpr int MT = 32 * ROWB, NT = 128 * COLB;
     const uint16_t *__restrict__ kidx = J.kidx;
@@ -326,7 +328,7 @@ __device__ __forceinline__ void pipe_epilogue(const MfmaJob &J, f32x16 (&acc)[RO
         }
         double sum = (part[0] + part[1]) + (part[2] + part[3]);
         sum += __shfl_xor(sum, 32);
-        if (half == 0 && col[b] < NS) partial[(size_t)col[b] * n_mt + mt] = sum;
+        if (half == 0 && col[b] < NS) partial[(size_t)col[b] * n_mt + slot] = sum;
     }
 }
 
@@ -472,7 +474,7 @@ __device__ __forceinline__ void mfma_pipe_tile(const MfmaJob &J, int tile, u32x4
         });
     }
 
-    pipe_epilogue<ROWB, COLB>(J, acc, col, lq, mt, nt, ring, NST * STAGE);
+    pipe_epilogue<ROWB, COLB>(J, acc, col, lq, mt, nt, ring, NST * STAGE, mt);
 }
 
 // K tiles of 64 (four 16-deep k-steps between barriers) with a rolling
@@ -481,8 +483,11 @@ __device__ __forceinline__ void mfma_pipe_tile(const MfmaJob &J, int tile, u32x4
 // between the products of the first, and the barrier that hands over the
 // next K tile is taken before the last step's products, whose operands are
 // already in registers.
+// K tiles kb..ke-1 (ke > kb) of row tile mt and column tile nt, summed into
+// partial slot `slot` of each column.
 template <int ROWB, int COLB, int NST, int KINS>
-__device__ __forceinline__ void mfma_pipe_tile64(const MfmaJob &J, int tile, u32x4 *ring)
+__device__ __forceinline__ void mfma_pipe_piece64(const MfmaJob &J, int mt, int nt, int kb, int ke, int slot,
+                                                  u32x4 *ring)
 {
     constexpr int MT = 32 * ROWB, NT = 128 * COLB, KTILE = 64, KSTEPS = KTILE / 16, KH = 2;
     constexpr int A_CHUNKS = 2 * KSTEPS * 2 * MT;   // [hi/lo][kk][half][row] 16-byte chunks per stage
@@ -496,10 +501,10 @@ __device__ __forceinline__ void mfma_pipe_tile64(const MfmaJob &J, int tile, u32
     const u32x4 *__restrict__ Whsw = J.Whsw;
     const u32x4 *__restrict__ Wlsw = J.Wlsw;
     const uint16_t *__restrict__ kidx = J.kidx;
-    const int n_pad = J.n_pad, p = J.p, count = J.count, NS = J.NS, n_nt = J.n_nt;
-    const int mt = tile / n_nt, nt = tile % n_nt;
+    const int n_pad = J.n_pad, p = J.p, count = J.count, NS = J.NS;
     const int N0 = nt * NT;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: addresses stay scalar
     const int half = lane >> 5, l32 = lane & 31;
     const int KS = n_pad / 16;
 
@@ -524,14 +529,15 @@ __device__ __forceinline__ void mfma_pipe_tile64(const MfmaJob &J, int tile, u32
     const OneHotK ohk = onehot_consts();
 
     const uint32_t ring_addr = (uint32_t)(uintptr_t)(lds_void *)ring;
-    auto issue = [&](int kt) {
+    auto issue = [&](int kt) {   // K tile kb + kt
         u32x4 *stage = ring + (kt % NST) * STAGE;
+        const int ka = kb + kt;
 #pragma unroll
         for (int q = 0; q < A_INS; ++q) {
             const int ins = wave + 4 * q;                    // ((mat*KSTEPS + kk)*2 + h)*(MT/64) + gl
             const int gl = ins % (MT / 64), t = ins / (MT / 64);
             const int h = t & 1, kk = (t >> 1) % KSTEPS, mat = (t >> 1) / KSTEPS;
-            const size_t gchunk = (((size_t)(mt * (MT / 64) + gl) * KS + kt * KSTEPS + kk) * 2 + h) * 64;
+            const size_t gchunk = (((size_t)(mt * (MT / 64) + gl) * KS + ka * KSTEPS + kk) * 2 + h) * 64;
             const u32x4 *src = (mat ? Wlsw : Whsw) + gchunk + lane;
             __builtin_amdgcn_global_load_lds((const void *)src, (lds_void *)(stage + ins * 64), 16, 0, 0);
         }
@@ -540,7 +546,7 @@ __device__ __forceinline__ void mfma_pipe_tile64(const MfmaJob &J, int tile, u32
             const int si = min(s_first + q * 16 + (lane >> 2), count - 1);
 #pragma unroll
             for (int kh = 0; kh < KH; ++kh) {
-                const uint16_t *src = kidx + (size_t)si * n_pad + kt * KTILE + kh * 32 + (lane & 3) * 8;
+                const uint16_t *src = kidx + (size_t)si * n_pad + ka * KTILE + kh * 32 + (lane & 3) * 8;
                 __builtin_amdgcn_global_load_lds((const void *)src,
                                                  (lds_void *)(stage + A_CHUNKS + ((wave * KINS + q) * KH + kh) * 64),
                                                  16, 0, 0);
@@ -548,7 +554,7 @@ __device__ __forceinline__ void mfma_pipe_tile64(const MfmaJob &J, int tile, u32
         }
     };
     auto wait_tile = [&](int kt) {   // this wave's transfers of tile kt have landed
-        const int younger = min(NST - 2, (n_pad / KTILE) - 1 - kt);
+        const int younger = min(NST - 2, ke - kb - 1 - kt);
         static_for<NST - 1>([&](auto Y) {
             if (younger == Y.value) vm_wait<Y.value * LPT>();
         });
@@ -581,7 +587,7 @@ __device__ __forceinline__ void mfma_pipe_tile64(const MfmaJob &J, int tile, u32
         });
     };
 
-    const int ktiles = n_pad / KTILE;
+    const int ktiles = ke - kb;
 #pragma unroll
     for (int t = 0; t < NST - 1; ++t)
         if (t < ktiles) issue(t);
@@ -645,33 +651,57 @@ __device__ __forceinline__ void mfma_pipe_tile64(const MfmaJob &J, int tile, u32
         });
     }
 
-    pipe_epilogue<ROWB, COLB>(J, acc, col, lq, mt, nt, ring, NST * STAGE);
+    pipe_epilogue<ROWB, COLB>(J, acc, col, lq, mt, nt, ring, NST * STAGE, slot);
+}
+
+// Work unit `tile` (row-tile major over the column tiles) of the K-64
+// product: row tile mt over K tiles 0..KT-1, or, on the folded W (C
+// symmetric; zero below the diagonal), over K tiles KPR*mt..KT-1 only (KPR K
+// tiles per row tile).  Folded units shrink with mt, so the row-tile-major
+// order hands them out longest first.
+template <int ROWB, int COLB, int NST, int KINS>
+__device__ __forceinline__ void mfma_pipe_unit64(const MfmaJob &J, int tile, u32x4 *ring)
+{
+    constexpr int KPR = 32 * ROWB / 64;
+    const int mt = tile / J.n_nt, nt = tile % J.n_nt;
+    mfma_pipe_piece64<ROWB, COLB, NST, KINS>(J, mt, nt, J.fold ? KPR * mt : 0, J.n_pad / 64, mt, ring);
+}
+
+// Workgroup -> tile.  XCD-major (blockIdx % 8 picks the XCD, which walks a
+// contiguous range of tiles, so its L2 keeps its own W row panels) for equal
+// tiles; round robin (consecutive tiles on consecutive XCDs, every XCD
+// stepping through the row tiles together) for the folded product, whose
+// tiles shrink along the list.
+__device__ __forceinline__ int pipe_tile_of_block(int tiles, bool round_robin)
+{
+    if (round_robin) return blockIdx.x;
+    const int per = (tiles + 7) / 8;
+    return (blockIdx.x & 7) * per + (blockIdx.x >> 3);
 }
 
 template <int ROWB, int COLB, int NST, int KINS, int OCC, int EARLY>
 __global__ __launch_bounds__(256, OCC) void k_eval_mfma_pipe(MfmaJob J)
 {
     __shared__ __align__(16) u32x4 ring[pipe_ring_chunks<ROWB, COLB, NST, KINS, EARLY>()];
-    const int tiles = J.n_mt * J.n_nt;
-    const int per = (tiles + 7) / 8;
-    const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    const int tiles = J.n_rt * J.n_nt;
+    const int tile = pipe_tile_of_block(tiles, J.fold);
     if (tile >= tiles) return;
     if constexpr (EARLY == 2)
-        mfma_pipe_tile64<ROWB, COLB, NST, KINS>(J, tile, ring);
+        mfma_pipe_unit64<ROWB, COLB, NST, KINS>(J, tile, ring);
     else
         mfma_pipe_tile<ROWB, COLB, NST, KINS, EARLY>(J, tile, ring);
 }
 
 // One launch over the tiles of several contexts: the concatenated tile list
 // (each context row-tile major) is split into 8 contiguous ranges, one per
-// XCD (blockIdx % 8), so every XCD walks whole row panels.
+// XCD (blockIdx % 8), so every XCD walks whole row panels; round robin when
+// a context is folded.
 template <int ROWB, int COLB, int NST, int KINS, int OCC, int EARLY>
 __global__ __launch_bounds__(256, OCC) void k_eval_mfma_pipe_group(const MfmaJob *__restrict__ jobs, int njobs,
-                                                                   int total_tiles)
+                                                                   int total_tiles, int round_robin)
 {
     __shared__ __align__(16) u32x4 ring[pipe_ring_chunks<ROWB, COLB, NST, KINS, EARLY>()];
-    const int per = (total_tiles + 7) / 8;
-    const int t = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    const int t = pipe_tile_of_block(total_tiles, round_robin);
     if (t >= total_tiles) return;
     int lo = 0, hi = njobs - 1;   // last job with tile_start <= t
     while (lo < hi) {
@@ -683,7 +713,7 @@ __global__ __launch_bounds__(256, OCC) void k_eval_mfma_pipe_group(const MfmaJob
     }
     const MfmaJob J = jobs[lo];
     if constexpr (EARLY == 2)
-        mfma_pipe_tile64<ROWB, COLB, NST, KINS>(J, t - J.tile_start, ring);
+        mfma_pipe_unit64<ROWB, COLB, NST, KINS>(J, t - J.tile_start, ring);
     else
         mfma_pipe_tile<ROWB, COLB, NST, KINS, EARLY>(J, t - J.tile_start, ring);
 }
@@ -758,8 +788,9 @@ static hipError_t pipe_launch(const DevPtrs &P, const Dims &d, const uint16_t *k
     const int n_nt = (NS + NT - 1) / NT;
     const int tiles = n_mt * n_nt;
     const int per = (tiles + 7) / 8;
-    MfmaJob J{(const u32x4 *)P.Whsw, (const u32x4 *)P.Wlsw, kidx, P.Ch32, P.partial, d.n, d.n_pad, d.p, count,
-              NS, n_mt, n_nt, 0};
+    const int fold = EARLY == 2 && d.sym;
+    MfmaJob J{(const u32x4 *)(fold ? P.Wfhsw : P.Whsw), (const u32x4 *)(fold ? P.Wflsw : P.Wlsw), kidx, P.Ch32,
+              P.partial, d.n, d.n_pad, d.p, count, NS, n_mt, n_nt, 0, n_mt, fold};
     k_eval_mfma_pipe<ROWB, COLB, NST, KINS, OCC, EARLY><<<per * 8, 256, 0, st>>>(J);
     return hipGetLastError();
 }
@@ -830,6 +861,14 @@ hipError_t launch_mfma(const DevPtrs &P, const Dims &d, const uint16_t *kidx, in
     }
 }
 
+// Whether configuration cfg evaluates a context on the folded W: the K-64
+// pipelined kernels do when C is symmetric.
+bool mfma_folds(const Dims &d, int cfg)
+{
+    const MfmaCfg &c = kMfmaCfgs[cfg];
+    return d.sym && c.nst > 0 && c.kt == 64 && kidx_transfers(c.colb, d.p) <= 2;
+}
+
 // Row tiles the partials of configuration cfg use for p hubs.
 int mfma_partial_tiles(const Dims &d, int cfg)
 {
@@ -884,52 +923,55 @@ int mfma_fill_jobs(const DevPtrs *const *P, const Dims *const *d, int njobs, int
     int start = 0;
     for (int j = 0; j < njobs; ++j) {
         const int NS = d[j]->S * d[j]->p;
-        const int n_mt = d[j]->n_pad / MT, n_nt = (NS + NT - 1) / NT;
-        J[j] = MfmaJob{(const u32x4 *)P[j]->Whsw, (const u32x4 *)P[j]->Wlsw, P[j]->kidx, P[j]->Ch32, P[j]->partial,
-                       d[j]->n, d[j]->n_pad, d[j]->p, d[j]->S, NS, n_mt, n_nt, start};
-        start += n_mt * n_nt;
+        const int n_rt = d[j]->n_pad / MT, n_nt = (NS + NT - 1) / NT;
+        const int fold = mfma_folds(*d[j], cfg);
+        J[j] = MfmaJob{(const u32x4 *)(fold ? P[j]->Wfhsw : P[j]->Whsw), (const u32x4 *)(fold ? P[j]->Wflsw : P[j]->Wlsw),
+                       P[j]->kidx, P[j]->Ch32, P[j]->partial, d[j]->n, d[j]->n_pad, d[j]->p, d[j]->S, NS,
+                       n_rt, n_nt, start, n_rt, fold};
+        start += n_rt * n_nt;
     }
     return start;
 }
 
 template <int ROWB, int COLB, int NST, int KINS, int OCC, int EARLY>
-static hipError_t group_launch(const void *d_jobs, int njobs, int total, hipStream_t st)
+static hipError_t group_launch(const void *d_jobs, int njobs, int total, int rr, hipStream_t st)
 {
     const int per = (total + 7) / 8;
     k_eval_mfma_pipe_group<ROWB, COLB, NST, KINS, OCC, EARLY><<<per * 8, 256, 0, st>>>((const MfmaJob *)d_jobs,
-                                                                                      njobs, total);
+                                                                                      njobs, total, rr);
     return hipGetLastError();
 }
 
 template <int ROWB, int COLB, int NST, int OCC, int EARLY = 0>
-static hipError_t group_dispatch(int kins, const void *d_jobs, int njobs, int total, hipStream_t st)
+static hipError_t group_dispatch(int kins, const void *d_jobs, int njobs, int total, int rr, hipStream_t st)
 {
-    if (kins <= 1) return group_launch<ROWB, COLB, NST, 1, OCC, EARLY>(d_jobs, njobs, total, st);
-    return group_launch<ROWB, COLB, NST, 2, OCC, EARLY>(d_jobs, njobs, total, st);
+    if (kins <= 1) return group_launch<ROWB, COLB, NST, 1, OCC, EARLY>(d_jobs, njobs, total, rr, st);
+    return group_launch<ROWB, COLB, NST, 2, OCC, EARLY>(d_jobs, njobs, total, rr, st);
 }
 
-hipError_t launch_mfma_group(const void *d_jobs, int njobs, int total, int cfg, int min_p, hipStream_t st)
+hipError_t launch_mfma_group(const void *d_jobs, int njobs, int total, int cfg, int min_p, int rr,
+                             hipStream_t st)
 {
     if (njobs <= 0 || total <= 0) return hipSuccess;
     const int kins = kidx_transfers(kMfmaCfgs[cfg].colb, min_p);
     if (kins > 2) return hipErrorInvalidValue;
     switch (cfg) {
-    case 6: return group_dispatch<4, 2, 4, 1>(kins, d_jobs, njobs, total, st);
-    case 7: return group_dispatch<4, 2, 3, 2>(kins, d_jobs, njobs, total, st);
-    case 8: return group_dispatch<4, 4, 4, 1>(kins, d_jobs, njobs, total, st);
-    case 9: return group_dispatch<4, 4, 3, 1>(kins, d_jobs, njobs, total, st);
-    case 10: return group_dispatch<2, 4, 4, 2>(kins, d_jobs, njobs, total, st);
-    case 11: return group_dispatch<4, 2, 3, 2, 1>(kins, d_jobs, njobs, total, st);
-    case 12: return group_dispatch<4, 2, 4, 1, 1>(kins, d_jobs, njobs, total, st);
-    case 13: return group_dispatch<2, 4, 4, 2, 1>(kins, d_jobs, njobs, total, st);
-    case 14: return group_dispatch<4, 2, 4, 2>(kins, d_jobs, njobs, total, st);
-    case 15: return group_dispatch<4, 2, 4, 2, 1>(kins, d_jobs, njobs, total, st);
-    case 16: return group_dispatch<4, 2, 2, 2, 2>(kins, d_jobs, njobs, total, st);
-    case 17: return group_dispatch<4, 2, 3, 1, 2>(kins, d_jobs, njobs, total, st);
-    case 18: return group_dispatch<4, 4, 3, 1, 2>(kins, d_jobs, njobs, total, st);
-    case 19: return group_dispatch<4, 4, 2, 1, 2>(kins, d_jobs, njobs, total, st);
-    case 20: return group_dispatch<2, 4, 3, 2, 2>(kins, d_jobs, njobs, total, st);
-    case 21: return group_dispatch<2, 4, 2, 2, 2>(kins, d_jobs, njobs, total, st);
+    case 6: return group_dispatch<4, 2, 4, 1>(kins, d_jobs, njobs, total, rr, st);
+    case 7: return group_dispatch<4, 2, 3, 2>(kins, d_jobs, njobs, total, rr, st);
+    case 8: return group_dispatch<4, 4, 4, 1>(kins, d_jobs, njobs, total, rr, st);
+    case 9: return group_dispatch<4, 4, 3, 1>(kins, d_jobs, njobs, total, rr, st);
+    case 10: return group_dispatch<2, 4, 4, 2>(kins, d_jobs, njobs, total, rr, st);
+    case 11: return group_dispatch<4, 2, 3, 2, 1>(kins, d_jobs, njobs, total, rr, st);
+    case 12: return group_dispatch<4, 2, 4, 1, 1>(kins, d_jobs, njobs, total, rr, st);
+    case 13: return group_dispatch<2, 4, 4, 2, 1>(kins, d_jobs, njobs, total, rr, st);
+    case 14: return group_dispatch<4, 2, 4, 2>(kins, d_jobs, njobs, total, rr, st);
+    case 15: return group_dispatch<4, 2, 4, 2, 1>(kins, d_jobs, njobs, total, rr, st);
+    case 16: return group_dispatch<4, 2, 2, 2, 2>(kins, d_jobs, njobs, total, rr, st);
+    case 17: return group_dispatch<4, 2, 3, 1, 2>(kins, d_jobs, njobs, total, rr, st);
+    case 18: return group_dispatch<4, 4, 3, 1, 2>(kins, d_jobs, njobs, total, rr, st);
+    case 19: return group_dispatch<4, 4, 2, 1, 2>(kins, d_jobs, njobs, total, rr, st);
+    case 20: return group_dispatch<2, 4, 3, 2, 2>(kins, d_jobs, njobs, total, rr, st);
+    case 21: return group_dispatch<2, 4, 2, 2, 2>(kins, d_jobs, njobs, total, rr, st);
     default: return hipErrorInvalidValue;
     }
 }

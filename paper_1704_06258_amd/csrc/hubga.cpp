@@ -77,6 +77,7 @@ Dims make_dims(const ga_params *q, ga_dtype cdt, ga_dtype wdt)
     d.elitist = q->elitist;
     d.prec = q->precision;
     d.c_f32 = cdt == GA_DT_F32;
+    d.sym = q->c_symmetric;
     d.w_f32 = wdt == GA_DT_F32;
     d.chi = q->chi;
     d.alpha = q->alpha;
@@ -88,7 +89,7 @@ Dims make_dims(const ga_params *q, ga_dtype cdt, ga_dtype wdt)
 
 // Offsets of every device buffer; the same walk sizes and carves.
 struct Carve {
-    size_t C, Ct, Ct32, W, W32, Whi, Wlo, Whsw, Wlsw, O, D, dsum, hubs, kidx, cost, parts, eps, cmax, Ch32, partial, anc, anc_cost,
+    size_t C, Ct, Ct32, W, W32, Whi, Wlo, Whsw, Wlsw, Wfhsw, Wflsw, O, D, dsum, hubs, kidx, cost, parts, eps, cmax, Ch32, partial, anc, anc_cost,
         anc_parts, best, best_cost, gen, stats, cand, cand_cnt, cand_cost, cand_parts, kidx_one, scratch, tbuf, slot_r, slot_c, slot_s, slot_done, handled, choice, total_slots, extra_r, extra_c, nextra, sync;
     size_t total;
 };
@@ -111,6 +112,8 @@ Carve carve(const Dims &d, int c_symmetric)
     c.Wlo = split ? L.take(np2 * 2) : (size_t)-1;
     c.Whsw = split ? L.take(np2 * 2) : (size_t)-1;
     c.Wlsw = split ? L.take(np2 * 2) : (size_t)-1;
+    c.Wfhsw = split && d.sym ? L.take(np2 * 2) : (size_t)-1;
+    c.Wflsw = split && d.sym ? L.take(np2 * 2) : (size_t)-1;
     c.O = L.take((size_t)d.n * 8);
     c.D = L.take((size_t)d.n * 8);
     c.dsum = L.take((size_t)d.n * 8);
@@ -196,6 +199,7 @@ struct ga_batch {
     int stage = 0;
     size_t tab_cap = 0, tick_off = 0;
     int njobs = 0, total_tiles = 0, min_p = 0, sel_threads = 64;
+    int round_robin = 0;   // some context is folded: tiles go round robin over the XCDs
     int blocks[kTickPhases] = {};
     size_t lds_recheck = 0;
 };
@@ -468,6 +472,8 @@ ga_status ga_init(const ga_params *q, const void *C, ga_dtype cdt, const void *W
         P.Wlo = at<uint16_t>(b, c.Wlo);
         P.Whsw = at<uint16_t>(b, c.Whsw);
         P.Wlsw = at<uint16_t>(b, c.Wlsw);
+        P.Wfhsw = at<uint16_t>(b, c.Wfhsw);
+        P.Wflsw = at<uint16_t>(b, c.Wflsw);
         P.O = at<double>(b, c.O);
         P.D = at<double>(b, c.D);
         P.dsum = at<double>(b, c.dsum);
@@ -809,6 +815,14 @@ ga_status ga_set_tile_config(ga_ctx *ctx, int32_t cfg)
     return GA_OK;
 }
 
+ga_status ga_evaluation_folded(ga_ctx *ctx, int32_t *folded)
+{
+    CTXCHK(ctx);
+    if (!folded) return fail(ctx, GA_ERR_INVALID, "folded is NULL");
+    *folded = ctx->d.prec == kSplitBF16 && mfma_folds(ctx->d, ctx->d.mfma_cfg);
+    return GA_OK;
+}
+
 }  // extern "C"
 
 // ------------------------------------------------------------- batches --
@@ -862,7 +876,7 @@ ga_status ga_batch_set(ga_batch *b, ga_ctx *const *ctxs, int32_t count)
     std::vector<const DevPtrs *> P;
     std::vector<const Dims *> D;
     std::vector<TickJob> tj(njobs);
-    int min_p = 1 << 30, sel_threads = 64;
+    int min_p = 1 << 30, sel_threads = 64, round_robin = 0;
     int blocks[kTickPhases] = {};
     size_t lds_recheck = 0;
     for (int j = 0; j < njobs; ++j) {
@@ -871,6 +885,7 @@ ga_status ga_batch_set(ga_batch *b, ga_ctx *const *ctxs, int32_t count)
         P.push_back(&c->P);
         D.push_back(&c->d);
         min_p = std::min(min_p, d.p);
+        round_robin |= (int)mfma_folds(d, b->cfg);
         sel_threads = std::max(sel_threads, select_threads(d.m));
         lds_recheck = std::max(lds_recheck, recheck_lds(d.n, d.p));
         TickJob &J = tj[j];
@@ -924,6 +939,7 @@ ga_status ga_batch_set(ga_batch *b, ga_ctx *const *ctxs, int32_t count)
     b->tick_off = mbytes;
     b->njobs = njobs;
     b->min_p = min_p;
+    b->round_robin = round_robin;
     b->sel_threads = sel_threads;
     b->lds_recheck = lds_recheck;
     memcpy(b->blocks, blocks, sizeof(blocks));
@@ -980,7 +996,7 @@ ga_status ga_batch_step(ga_batch *b, int32_t generations)
                 return dev_fail(e, "grouped operators");
             if ((e = launch_alloc_group(tjobs, nj, b->blocks[kTickAlloc], b->st)) != hipSuccess)
                 return dev_fail(e, "grouped allocation");
-            if ((e = launch_mfma_group(mjobs, nj, b->total_tiles, b->cfg, b->min_p, b->st)) != hipSuccess)
+            if ((e = launch_mfma_group(mjobs, nj, b->total_tiles, b->cfg, b->min_p, b->round_robin, b->st)) != hipSuccess)
                 return dev_fail(e, "grouped matrix-core evaluation");
             if ((e = launch_finalize_group(tjobs, nj, b->blocks[kTickFinal], b->st)) != hipSuccess)
                 return dev_fail(e, "grouped cost assembly");

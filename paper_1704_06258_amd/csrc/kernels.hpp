@@ -38,12 +38,14 @@ hipError_t launch_eval_split(const DevPtrs &P, const Dims &d, const uint16_t *ki
 hipError_t launch_mfma(const DevPtrs &P, const Dims &d, const uint16_t *kidx, int count, hipStream_t st);
 hipError_t launch_finalize(const DevPtrs &P, const Dims &d, int count, int cfg, hipStream_t st);
 int mfma_partial_tiles(const Dims &d, int cfg);
+bool mfma_folds(const Dims &d, int cfg);
 int finalize_blocks(int count);
 hipError_t launch_finalize_group(const TickJob *jobs, int njobs, int blocks, hipStream_t st);
 bool mfma_groupable(const Dims &d, int cfg);
 size_t mfma_job_bytes();
 int mfma_fill_jobs(const DevPtrs *const *P, const Dims *const *d, int njobs, int cfg, void *jobs_host);
-hipError_t launch_mfma_group(const void *d_jobs, int njobs, int total, int cfg, int min_p, hipStream_t st);
+hipError_t launch_mfma_group(const void *d_jobs, int njobs, int total, int cfg, int min_p, int round_robin,
+                             hipStream_t st);
 int mfma_pipelined(int cfg);
 int mfma_num_configs();
 int mfma_rows_per_tile(int cfg);

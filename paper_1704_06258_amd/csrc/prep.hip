@@ -104,8 +104,12 @@ __global__ void k_split_bf16(const T *__restrict__ W, int n, int n_pad, uint16_t
 
 // The same split written in fragment order: one thread per 16-byte chunk of
 // 8 consecutive k of one row; chunk ((g*KS + ks)*2 + h)*64 + rl holds row
-// g*64 + rl, k = ks*16 + h*8 .. +7 (KS = n_pad/16).
-template <typename T>
+// g*64 + rl, k = ks*16 + h*8 .. +7 (KS = n_pad/16).  FOLD splits the folded
+// matrix instead: W_rk + W_kr (one binary64 rounding) for k > r, W_rr for
+// k = r, zero for k < r.  With C symmetric, sum_{r,k} W_rk C[a(r)][a(k)] is
+// the same sum over the folded matrix, whose non-zeros lie on and above the
+// diagonal.
+template <typename T, bool FOLD = false>
 __global__ void k_split_bf16_swz(const T *__restrict__ W, int n, int n_pad, uint16_t *__restrict__ hi,
                                  uint16_t *__restrict__ lo)
 {
@@ -125,8 +129,9 @@ __global__ void k_split_bf16_swz(const T *__restrict__ W, int n, int n_pad, uint
     for (int e = 0; e < 8; ++e) {
         const int k = k0 + e;
         uint16_t a = 0, b = 0;
-        if (r < n && k < n) {
+        if (r < n && k < n && (!FOLD || k >= r)) {
             double x = (double)W[(size_t)r * n + k];
+            if (FOLD && k > r) x = x + (double)W[(size_t)k * n + r];
             a = bf16_rne_bits(x);
             b = bf16_rne_bits(x - bf16_to_double(a));
         }
@@ -244,6 +249,13 @@ hipError_t launch_prep(const DevPtrs &P, const Dims &d, hipStream_t st)
             k_split_bf16_swz<float><<<gs, tb, 0, st>>>((const float *)P.W, n, d.n_pad, P.Whsw, P.Wlsw);
         else
             k_split_bf16_swz<double><<<gs, tb, 0, st>>>((const double *)P.W, n, d.n_pad, P.Whsw, P.Wlsw);
+        if (P.Wfhsw) {
+            if (d.w_f32)
+                k_split_bf16_swz<float, true><<<gs, tb, 0, st>>>((const float *)P.W, n, d.n_pad, P.Wfhsw, P.Wflsw);
+            else
+                k_split_bf16_swz<double, true><<<gs, tb, 0, st>>>((const double *)P.W, n, d.n_pad, P.Wfhsw,
+                                                                  P.Wflsw);
+        }
     }
     return hipGetLastError();
 }

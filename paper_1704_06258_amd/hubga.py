@@ -28,7 +28,7 @@ DEFAULT_KERNEL = {GA_PREC_FP64: GA_KERN_PLAIN, GA_PREC_FP32: GA_KERN_PLAIN, GA_P
 EXPORTS = ("ga_params_default", "ga_workspace_bytes", "ga_init", "ga_evaluate", "ga_evaluate_dev", "ga_step",
            "ga_best", "ga_solve", "ga_population", "ga_ancestors", "ga_get_state", "ga_set_state", "ga_stats",
            "ga_profile_enable", "ga_profile_read", "ga_tile_config_count", "ga_tile_config_info",
-           "ga_set_tile_config", "ga_set_stream", "ga_batch_create", "ga_batch_set", "ga_batch_step", "ga_batch_free",
+           "ga_set_tile_config", "ga_evaluation_folded", "ga_set_stream", "ga_batch_create", "ga_batch_set", "ga_batch_step", "ga_batch_free",
            "ga_status_str", "ga_last_error", "ga_free")
 
 
@@ -90,6 +90,8 @@ def lib():
         L.ga_set_stream.restype = ct.c_int
         L.ga_set_tile_config.argtypes = [vp, i32]
         L.ga_set_tile_config.restype = ct.c_int
+        L.ga_evaluation_folded.argtypes = [vp, ct.POINTER(i32)]
+        L.ga_evaluation_folded.restype = ct.c_int
         L.ga_batch_create.argtypes = [vp, i32, ct.POINTER(vp)]
         L.ga_batch_create.restype = ct.c_int
         L.ga_batch_set.argtypes = [vp, ct.POINTER(vp), i32]
@@ -289,6 +291,12 @@ class Solver:
 
     def set_tile_config(self, config: int):
         _check(lib().ga_set_tile_config(self.ctx, int(config)), self.ctx)
+
+    def folded(self) -> bool:
+        """True when the batched evaluation multiplies the folded W (symmetric C)."""
+        f = ct.c_int32(0)
+        _check(lib().ga_evaluation_folded(self.ctx, ct.byref(f)), self.ctx)
+        return bool(f.value)
 
     def profile_enable(self, on=True):
         _check(lib().ga_profile_enable(self.ctx, int(bool(on))), self.ctx)

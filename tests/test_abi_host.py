@@ -52,9 +52,14 @@ def test_workspace_bytes(L):
     b = hubga.ga_workspace_bytes(q)
     # C and W (binary64) plus the bf16 hi/lo copies padded to 1024 dominate
     assert b > 2 * 8 * 1000 * 1000 + 2 * 2 * 1024 * 1024
-    assert b < 64 * 2**20
+    assert b < 80 * 2**20
     q.c_symmetric = 0
-    assert hubga.ga_workspace_bytes(q) >= b + 8 * 1000 * 1000
+    # an asymmetric C keeps its transpose (binary64, one row more); a symmetric
+    # one the folded W's hi/lo copies
+    ct_bytes = 8 * (1000 * 1000 + 1000)
+    fold_bytes = 2 * 2 * 1024 * 1024
+    diff = hubga.ga_workspace_bytes(q) - b
+    assert abs(diff - (ct_bytes - fold_bytes)) < 64 * 1024, diff
     assert hubga.ga_workspace_bytes(q, hubga.GA_DT_F32, hubga.GA_DT_F32) < hubga.ga_workspace_bytes(q)
 
 

@@ -327,6 +327,56 @@ def test_pipelined_configs_all_hub_counts(p):
         assert np.all(err <= out["eps"]), (cfg, err.max())
 
 
+def k64_configs():
+    return [c for c, (_, _, kt) in enumerate(hubga.tile_configs()) if kt == 64]
+
+
+# n -> row tiles of 128 (of 64): 100 -> 1 (2), 200 -> 2 (4), 300 -> 3 (6), 700 -> 6 (12), 830 -> 7 (14)
+@pytest.mark.parametrize("n,p", [(100, 5), (200, 7), (300, 11), (700, 20), (830, 13)])
+def test_folded_product_matches_full_and_oracle(n, p):
+    """Symmetric C: the K-64 configurations multiply the folded W (upper
+    triangle of W + W^T).  Costs stay within their bounds of the oracle, agree
+    with the unfolded product to those bounds, and GA trajectories are
+    unchanged; odd and even row-tile counts and the one-row-tile case."""
+    inst = I.uniform(seed=80 + n, n=n, p=p)
+    assert np.array_equal(inst.C, inst.C.T)
+    hubs = I.random_hub_sets(11, n, p, 150)
+    ref_c, _ = ref_eval(inst, hubs)
+    st = oracle_trajectory(inst, 4, S=256, m=32, n1=2, seed=5)
+    n_folded = 0
+    for cfg in k64_configs():
+        outs = {}
+        for sym in (True, False):
+            with make(inst, population=256, island_size=32, n1=2, seed=5, precision="split_bf16",
+                      c_symmetric=sym) as s:
+                s.set_tile_config(cfg)
+                # the pipelined K-64 configurations fold; the register-staged ones do not
+                assert sym or not s.folded()
+                n_folded += s.folded()
+                out = s.evaluate(hubs)
+                err = np.abs(out["cost"] - ref_c) / ref_c
+                assert np.all(err <= out["eps"]), (cfg, sym, err.max())
+                outs[sym] = out
+                s.step(4)
+                assert_same_state(s, st)
+        a, b = outs[True]["cost"], outs[False]["cost"]
+        assert np.all(np.abs(a - b) <= (outs[True]["eps"] + outs[False]["eps"]) * ref_c)
+    assert n_folded >= 4
+
+
+def test_asymmetric_c_is_never_folded():
+    inst = I.random_asymmetric(seed=25, n=260, p=9)
+    hubs = I.random_hub_sets(12, inst.n, inst.p, 64)
+    ref_c, _ = ref_eval(inst, hubs)
+    for cfg in k64_configs():
+        with make(inst, population=64, island_size=32, precision="split_bf16") as s:
+            s.set_tile_config(cfg)
+            assert not s.folded()
+            out = s.evaluate(hubs)
+        err = np.abs(out["cost"] - ref_c) / ref_c
+        assert np.all(err <= out["eps"]), (cfg, err.max())
+
+
 # ---------------------------------------------------- full-size workloads --
 
 def test_headline_workload_full_population_two_generations():
