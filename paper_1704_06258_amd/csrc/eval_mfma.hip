@@ -253,44 +253,107 @@ constexpr int pipe_ring_chunks()
     return NST * (2 * (2 * KH) * 2 * 32 * ROWB + 4 * KINS * KH * 64);
 }
 
+// Individuals [s_lo, s_lo + nind) whose columns column tile nt touches.
+template <int NT>
+__device__ __forceinline__ int2 tile_individuals(const MfmaJob &J, int nt)
+{
+    const int N0 = nt * NT;
+    const int s_lo = min(N0, J.NS - 1) / J.p, s_hi = min(N0 + NT - 1, J.NS - 1) / J.p;
+    return make_int2(s_lo, s_hi - s_lo + 1);
+}
+
+// LDS bytes of a tile's staged epilogue operands: the hub positions of its MT
+// rows for each of its individuals ([ind][row], 16-bit), then their FP32
+// hub-distance tables ([ind][k][l]).
+template <int MT, int NT>
+__device__ __forceinline__ int epi_stage_bytes(const MfmaJob &J, int nt)
+{
+    const int nind = tile_individuals<NT>(J, nt).y;
+    return nind * MT * 2 + nind * J.p * J.p * 4;
+}
+
+// Moves those operands global -> LDS at dst with the waves' direct loads
+// (no register round trip; completion is each wave's vmcnt).  The hub
+// positions go in 16-byte pieces of MT/8 per individual; the tables in
+// 16-byte pieces when p*p is a multiple of 4 (every piece then starts
+// aligned and ends inside the last individual's table), else in 4-byte ones.
+template <int MT, int NT>
+__device__ __forceinline__ void epi_stage_issue(const MfmaJob &J, int mt, int nt, u32x4 *dst)
+{
+    const int2 ind = tile_individuals<NT>(J, nt);
+    const int s_lo = ind.x, nind = ind.y, pp = J.p * J.p;
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    constexpr int CPI = MT / 8;   // 16-byte pieces of hub positions per individual
+    const int nk = nind * CPI;
+    for (int b = wave * 64; b < nk; b += 256) {
+        const int c = b + lane;
+        if (c < nk)
+            __builtin_amdgcn_global_load_lds(
+                (const void *)(J.kidx + (size_t)(s_lo + c / CPI) * J.n_pad + mt * MT + (c % CPI) * 8),
+                (lds_void *)(dst + b), 16, 0, 0);
+    }
+    const float *src = J.Ch32 + (size_t)s_lo * pp;
+    if (pp % 4 == 0) {
+        const int nc = nind * pp / 4;
+        for (int b = wave * 64; b < nc; b += 256) {
+            const int c = b + lane;
+            if (c < nc)
+                __builtin_amdgcn_global_load_lds((const void *)(src + 4 * c), (lds_void *)(dst + nk + b), 16, 0, 0);
+        }
+    } else {
+        uint32_t *dl = (uint32_t *)(dst + nk);
+        const int nc = nind * pp;
+        for (int b = wave * 64; b < nc; b += 256) {
+            const int c = b + lane;
+            if (c < nc) __builtin_amdgcn_global_load_lds((const void *)(src + c), (lds_void *)(dl + b), 4, 0, 0);
+        }
+    }
+}
+
 // Epilogue of a pipelined tile: sum_i G[i][(s,l)] * C[h_k(i)][h_l] over the
-// tile's rows in binary64, one partial per (column, row tile).  The ring
-// (ring_chunks 16-byte chunks) is free once every wave has left the K loop.
+// tile's rows in binary64, one partial per column in slot `slot`.  The
+// operands are staged in LDS so the gathers hit LDS: at pre when the K loop
+// already issued them there, else into the ring (ring_chunks 16-byte chunks,
+// free once every wave has left the K loop) if they fit, else the gathers go
+// to global memory.
 template <int ROWB, int COLB>
 __device__ __forceinline__ void pipe_epilogue(const MfmaJob &J, f32x16 (&acc)[ROWB][COLB], const int (&col)[COLB],
                                               const uint32_t (&lq)[COLB], int mt, int nt, u32x4 *ring,
-                                              int ring_chunks, int slot)
+                                              int ring_chunks, int slot, u32x4 *pre)
 {
     constexpr int MT = 32 * ROWB, NT = 128 * COLB;
     const uint16_t *__restrict__ kidx = J.kidx;
     const float *__restrict__ Ch32 = J.Ch32;
     double *__restrict__ partial = J.partial;
     const int n = J.n, n_pad = J.n_pad, p = J.p, NS = J.NS, n_mt = J.n_mt;
-    const int M0 = mt * MT, N0 = nt * NT;
+    const int M0 = mt * MT;
     const int tid = threadIdx.x, half = (tid & 63) >> 5;
-    // The ring takes the hub positions of the tile's rows and the FP32
-    // hub-distance tables of the workgroup's individuals, so the gathers hit
-    // LDS.  Accumulator v of a 32x32 block holds row 8*(v/4) + 4*half + (v%4).
-    wg_barrier();
-    const int s_lo = min(N0, NS - 1) / p, s_hi = min(N0 + NT - 1, NS - 1) / p;
-    const int nind = s_hi - s_lo + 1;
-    const size_t need = (size_t)nind * MT * 2 + (size_t)nind * p * p * 4;
-    const bool staged = need <= sizeof(u32x4) * (size_t)ring_chunks;
+    // Accumulator v of a 32x32 block holds row 8*(v/4) + 4*half + (v%4).
+    wg_barrier();   // every wave has left the K loop
+    const int2 ti = tile_individuals<NT>(J, nt);
+    const int s_lo = ti.x, nind = ti.y;
+    u32x4 *sd = pre;
+    if (!sd && epi_stage_bytes<MT, NT>(J, nt) <= (int)sizeof(u32x4) * ring_chunks) {
+        epi_stage_issue<MT, NT>(J, mt, nt, ring);
+        sd = ring;
+    }
+    const bool staged = sd != nullptr;
     // Indices into the staged arrays are offsets from their start (never a
     // pointer moved before it): LDS pointer arithmetic is 32-bit, and a
     // negative intermediate would leave the LDS aperture of a flat address.
-    uint16_t *lk = (uint16_t *)ring;                                              // [ind][row - M0]
-    float *lch = (float *)(ring + (nind * MT * 2 + 15) / 16);                     // [ind][k][l]
+    uint16_t *lk = (uint16_t *)sd;                       // [ind][row - M0]
+    float *lch = (float *)(sd + nind * (MT / 8));        // [ind][k][l]
     if (staged) {
-        for (int e = tid; e < nind * MT; e += 256) {
-            const int ind = e / MT, row = e % MT;
-            // rows past n get position 0: their products are exactly zero (W is
-            // zero-padded), which keeps the sum below free of branches
-            lk[e] = M0 + row < n ? kidx[(size_t)(s_lo + ind) * n_pad + M0 + row] : 0;
+        vm_wait<0>();
+        wg_barrier();   // every wave's copies have landed
+        if (M0 + MT > n) {
+            // rows past n (kNoHub in kidx) get position 0: their products are
+            // exactly zero (W is zero-padded), which keeps the sum below free
+            // of branches
+            for (int e = tid; e < nind * MT; e += 256)
+                if (M0 + e % MT >= n) lk[e] = 0;
+            __syncthreads();
         }
-        const int pp = p * p;
-        for (int e = tid; e < nind * pp; e += 256) lch[e] = Ch32[(size_t)s_lo * pp + e];
-        __syncthreads();
     }
 #pragma unroll
     for (int b = 0; b < COLB; ++b) {
@@ -474,7 +537,7 @@ __device__ __forceinline__ void mfma_pipe_tile(const MfmaJob &J, int tile, u32x4
         });
     }
 
-    pipe_epilogue<ROWB, COLB>(J, acc, col, lq, mt, nt, ring, NST * STAGE, mt);
+    pipe_epilogue<ROWB, COLB>(J, acc, col, lq, mt, nt, ring, NST * STAGE, mt, nullptr);
 }
 
 // K tiles of 64 (four 16-deep k-steps between barriers) with a rolling
@@ -594,6 +657,12 @@ __device__ __forceinline__ void mfma_pipe_piece64(const MfmaJob &J, int mt, int 
     wait_tile(0);
     wg_barrier();
     if (NST - 1 < ktiles) issue(NST - 1);
+    // The epilogue's operands go to the stage after the last K tile's, free
+    // from the hand-over before the last tile on (from the start if there are
+    // fewer K tiles than stages), and land while the last tile's products run.
+    const bool early = epi_stage_bytes<MT, NT>(J, nt) <= (int)sizeof(u32x4) * STAGE;
+    u32x4 *const pre = ring + (ktiles % NST) * STAGE;
+    if (early && ktiles < NST) epi_stage_issue<MT, NT>(J, mt, nt, pre);
     reads(std::integral_constant<int, 0>{}, std::integral_constant<int, 0>{}, 0u);
 
     for (int kt = 0; kt < ktiles; ++kt) {
@@ -608,7 +677,10 @@ __device__ __forceinline__ void mfma_pipe_piece64(const MfmaJob &J, int mt, int 
                 if (kt + 1 < ktiles) {
                     wait_tile(kt + 1);
                     wg_barrier();   // tile kt+1 visible to all waves; tile kt's stage is free
-                    if (kt + NST < ktiles) issue(kt + NST);
+                    if (kt + NST < ktiles)
+                        issue(kt + NST);
+                    else if (early && kt + NST == ktiles)
+                        epi_stage_issue<MT, NT>(J, mt, nt, pre);
                     reads(std::integral_constant<int, 0>{}, std::integral_constant<int, 0>{},
                           (uint32_t)(((kt + 1) % NST) * STAGE * 16));
                 }
@@ -651,7 +723,7 @@ __device__ __forceinline__ void mfma_pipe_piece64(const MfmaJob &J, int mt, int 
         });
     }
 
-    pipe_epilogue<ROWB, COLB>(J, acc, col, lq, mt, nt, ring, NST * STAGE, slot);
+    pipe_epilogue<ROWB, COLB>(J, acc, col, lq, mt, nt, ring, NST * STAGE, slot, early ? pre : nullptr);
 }
 
 // Work unit `tile` (row-tile major over the column tiles) of the K-64
