@@ -223,7 +223,9 @@ def main():
                    "precision": "W = bf16 hi + lo, FP32 accumulate, FP64 epilogue and selection",
                    "instance_sha256": inst.sha256()},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_BF16_TFLOPS, "traffic": traffic_from_profile(),
+                     "frac": achieved / PEAK_BF16_TFLOPS,
+                     # the committed counter summary covers the clustered workload only
+                     "traffic": traffic_from_profile() if args.workload == "clustered" else None,
                      "kernel": "k_eval_mfma", "avg_launch_ms": k_avg_ms, "launches": launches,
                      "flop_per_launch": flop_launch, "folded": folded,
                      "unfolded_flop_per_launch": flops_per_eval(N, P) * S, "tile_config": tile_cfg,

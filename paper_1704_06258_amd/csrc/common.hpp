@@ -35,7 +35,7 @@ struct DevPtrs {
     double *eps;        // S relative error bounds
     int32_t *cmax;      // S largest cluster size
     float *Ch32;        // S*p*p hub-to-hub distances (split mode)
-    double *partial;    // S*p*(n_pad/64) epilogue partials (split mode), [column][row tile]
+    double *partial;    // S*p*(n_pad/64) epilogue partials (split mode), [row tile][column]
     // GA state
     int32_t *anc;       // R*p
     double *anc_cost;   // R

@@ -207,7 +207,7 @@ __global__ __launch_bounds__(256, OCC) void k_eval_mfma(const uint16_t *__restri
             }
         }
         sum += __shfl_xor(sum, 32);
-        if (half == 0 && col[b] < NS) partial[(size_t)col[b] * n_mt + mt] = sum;
+        if (half == 0 && col[b] < NS) partial[(size_t)mt * NS + col[b]] = sum;
     }
 }
 
@@ -391,7 +391,7 @@ __device__ __forceinline__ void pipe_epilogue(const MfmaJob &J, f32x16 (&acc)[RO
         }
         double sum = (part[0] + part[1]) + (part[2] + part[3]);
         sum += __shfl_xor(sum, 32);
-        if (half == 0 && col[b] < NS) partial[(size_t)col[b] * n_mt + slot] = sum;
+        if (half == 0 && col[b] < NS) partial[(size_t)slot * NS + col[b]] = sum;
     }
 }
 
@@ -790,8 +790,9 @@ __global__ __launch_bounds__(256, OCC) void k_eval_mfma_pipe_group(const MfmaJob
         mfma_pipe_tile<ROWB, COLB, NST, KINS, EARLY>(J, t - J.tile_start, ring);
 }
 
-// T_s = sum of the individual's p*n_mt partials (contiguous), one wave per
-// individual with a fixed reduction order; cost assembly
+// T_s = sum of the individual's p*n_mt partials (partial[t][column], row tile
+// t, the individual's p columns contiguous in each), one wave per individual
+// with a fixed reduction order; cost assembly
 // f = ((chi*Cc) + (alpha*T)) + (delta*Dd) and its relative error bound.
 __device__ __forceinline__ void finalize_body(const double *__restrict__ partial, const int32_t *__restrict__ cmax,
                                               int count, int p, int n_mt, int n, int c_f32, double chi, double alpha,
@@ -802,9 +803,10 @@ __device__ __forceinline__ void finalize_body(const double *__restrict__ partial
     const int lane = threadIdx.x & 63;
     if (s >= count) return;
     const int len = p * n_mt;
-    const double *ps = partial + (size_t)s * len;   // [l][row tile]
+    const size_t NS = (size_t)count * p;
+    const double *ps = partial + (size_t)s * p;
     double v = 0.0;
-    for (int e = lane; e < len; e += 64) v += ps[e];
+    for (int e = lane; e < len; e += 64) v += ps[(size_t)(e / p) * NS + e % p];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
     if (lane == 0) {
