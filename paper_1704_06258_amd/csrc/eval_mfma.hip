@@ -325,7 +325,7 @@ __device__ __forceinline__ void pipe_epilogue(const MfmaJob &J, f32x16 (&acc)[RO
     const uint16_t *__restrict__ kidx = J.kidx;
     const float *__restrict__ Ch32 = J.Ch32;
     double *__restrict__ partial = J.partial;
-    const int n = J.n, n_pad = J.n_pad, p = J.p, NS = J.NS, n_mt = J.n_mt;
+    const int n = J.n, n_pad = J.n_pad, p = J.p, NS = J.NS;
     const int M0 = mt * MT;
     const int tid = threadIdx.x, half = (tid & 63) >> 5;
     // Accumulator v of a 32x32 block holds row 8*(v/4) + 4*half + (v%4).

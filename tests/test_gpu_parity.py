@@ -384,7 +384,7 @@ def test_headline_workload_full_population_two_generations():
     benchmark's configuration: the trajectory equals the oracle's."""
     inst = I.clustered()
     st = oracle_trajectory(inst, 2, S=4096, m=64, n1=10, seed=1)
-    for cfg in (0, 7, 14, 16, 18):
+    for cfg in (0, 7, 14, 16, 18, 21):   # 16, 18 and 21 multiply the folded W (C is symmetric)
         with make(inst, population=4096, island_size=64, n1=10, seed=1, precision="split_bf16") as s:
             s.set_tile_config(cfg)
             s.step(2)
@@ -395,13 +395,17 @@ def test_headline_workload_full_population_two_generations():
         assert err.max() <= 1e-6
 
 
-def test_large_workload_sampled():
-    """n=6000, p=50, population 2048 (FP32 instance): generation-0 children
-    equal the oracle's, sampled costs are within their bounds, and the new
-    ancestors carry their exact costs."""
+@pytest.mark.parametrize("cfg", [0, 16])
+def test_large_workload_sampled(cfg):
+    """n=6000, p=50, population 2048 (FP32 instance), in the default tile
+    configuration and in the folded one the benchmark's autotuner picks:
+    generation-0 children equal the oracle's, sampled costs are within their
+    bounds, and the new ancestors carry their exact costs."""
     inst = I.large()
     C64, W64 = inst.C64(), inst.W64()
     with make(inst, population=2048, island_size=64, n1=10, seed=1, precision="split_bf16") as s:
+        s.set_tile_config(cfg)
+        assert s.folded() == (cfg == 16)
         anc0, _ = s.ancestors()
         s.step(1)
         hubs, cost = s.population()
