@@ -63,7 +63,7 @@ MIX = [  # (instance, population, island, precision)
 ]
 
 
-@pytest.mark.parametrize("cfg", [7, 6, 10, 14, 16, 18])
+@pytest.mark.parametrize("cfg", [7, 6, 10, 14, 16, 17, 18])
 def test_batch_equals_alone(cfg):
     import torch
     insts = [(mk(), S, m, prec) for mk, S, m, prec in MIX]

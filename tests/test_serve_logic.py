@@ -33,7 +33,7 @@ class FakeSolver:
 
 
 class FakeBatch:
-    def __init__(self, device=0, tile_config=7):
+    def __init__(self, device=0, tile_config=16):
         self.members = []
         self.history = []
 
