@@ -140,6 +140,10 @@ constexpr double kU64 = 1.1102230246251565e-16;   // 2^-53
 constexpr double kU32 = 5.9604644775390625e-08;   // 2^-24
 constexpr double kU32Faithful = 1.1920928955078125e-07;  // 2^-23 (any faithful FP32 rounding)
 constexpr double kSplitResidual = 1.52587890625e-05;     // 2^-16: |W - hi - lo| <= 2^-16 W
+// The FP32 accumulators add hi and lo parts, whose magnitudes sum to at most
+// (1 + 2^-8) W + (1 + 2^-8) 2^-8 W <= (1 + 2^-6) W (bf16 unit roundoff 2^-8),
+// so the accumulation bound is taken relative to that mass, not to W.
+constexpr double kHiLoMass = 1.015625;                   // 1 + 2^-6
 
 __host__ __device__ inline double gamma_k(double k, double u) { return k * u / (1.0 - k * u); }
 

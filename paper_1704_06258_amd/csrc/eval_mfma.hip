@@ -815,8 +815,9 @@ __device__ __forceinline__ void finalize_body(const double *__restrict__ partial
         parts[3 * (size_t)s + 1] = T;
         cost[s] = (((chi * Cc) + (alpha * T)) + (delta * Dd)) * scale;
         // split residual + FP32 accumulation of at most 2*cmax non-zero addends
-        // per output (any faithful rounding) + FP32 hub distances + binary64 sums
-        eps[s] = kSplitResidual + gamma_k(2.0 * cmax[s], kU32Faithful) + (c_f32 ? 0.0 : kU32) +
+        // per output (any faithful rounding, relative to the hi + lo mass) +
+        // FP32 hub distances + binary64 sums
+        eps[s] = kSplitResidual + gamma_k(2.0 * cmax[s], kU32Faithful) * kHiLoMass + (c_f32 ? 0.0 : kU32) +
                  gamma_k((double)n + (double)len + 8.0, kU64) + gamma_k(n + 2.0, kU64) + gamma_k(8.0, kU64) + 1e-9;
     }
 }

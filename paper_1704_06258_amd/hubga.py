@@ -326,9 +326,9 @@ class Solver:
 
 
 class Batch:
-    """Several Solvers advanced together (ga_batch_*): one captured graph per
-    composition, with one grouped matrix-core launch for their populations.
-    Every member must have been created with ``stream=batch.stream``."""
+    """Several Solvers advanced together (ga_batch_*): each step of a
+    generation is one grouped launch over all grouped members' populations.
+    Every member must be on ``batch.stream`` (``Solver.set_stream``)."""
 
     def __init__(self, device=0, tile_config=7, stream=None):
         import torch

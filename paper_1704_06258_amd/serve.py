@@ -51,6 +51,8 @@ class SolveResult:
     arrival: float
     admitted: float
     finished: float
+    error: str | None = None       # set when building or reading back the request failed
+
 
     @property
     def latency(self) -> float:
@@ -140,10 +142,17 @@ class Server:
         job.solver.close()
         return res
 
+    @staticmethod
+    def _failed(req: SolveRequest, now: float, exc: BaseException) -> SolveResult:
+        return SolveResult(req.rid, None, float("nan"), 0, req.arrival, now, now, error=f"{type(exc).__name__}: {exc}")
+
     def _submit(self, fn, *args):
         if self._pool is None:
             f = concurrent.futures.Future()
-            f.set_result(fn(*args))
+            try:
+                f.set_result(fn(*args))
+            except Exception as exc:
+                f.set_exception(exc)
             return f
         return self._pool.submit(fn, *args)
 
@@ -153,8 +162,8 @@ class Server:
         once (closed loop).  Returns the results in completion order."""
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
         waiting: collections.deque = collections.deque()
-        building: list = []                    # (future, bytes reserved)
-        finishing: list = []                   # (future, bytes held)
+        building: list = []                    # (future, bytes reserved, request)
+        finishing: list = []                   # (future, bytes held, request)
         results: list[SolveResult] = []
         if self.batch.stream is not None and self._harvest is None:
             import torch
@@ -173,20 +182,28 @@ class Server:
                     break
                 req = waiting.popleft()
                 self.used += need
-                building.append((self._submit(self._admit, req, clock() - t0), need))
+                building.append((self._submit(self._admit, req, clock() - t0), need, req))
             # contexts built since the last tick join at this generation boundary
             changed = False
             still = []
-            for fut, need in building:
-                if fut.done():
+            for fut, need, req in building:
+                if not fut.done():
+                    still.append((fut, need, req))
+                    continue
+                try:
                     job = fut.result()
-                    job.nbytes = need
-                    if self.batch.stream is not None:
-                        job.solver.set_stream(self.batch.stream)
-                    self.resident.append(job)
-                    changed = True
-                else:
-                    still.append((fut, need))
+                except Exception as exc:       # this request failed to build: release it, keep serving
+                    self.used -= need
+                    results.append(self._failed(req, clock() - t0, exc))
+                    continue
+                job.nbytes = need
+                if job.req.generations <= 0:   # nothing to run: read back P0 as it stands
+                    finishing.append((self._submit(self._finish, job, t0, clock), need, job.req))
+                    continue
+                if self.batch.stream is not None:
+                    job.solver.set_stream(self.batch.stream)
+                self.resident.append(job)
+                changed = True
             building = still
             if changed:
                 self.batch.set([j.solver for j in self.resident])
@@ -204,19 +221,22 @@ class Server:
                     for j in done:             # out of the batch: read back and freed on a worker
                         if self._harvest is not None:
                             j.solver.set_stream(self._harvest)
-                        finishing.append((self._submit(self._finish, j, t0, clock), j.nbytes))
+                        finishing.append((self._submit(self._finish, j, t0, clock), j.nbytes, j.req))
             else:
                 delay = 0.0005 if (building or finishing) else (
                     pending[0].arrival - (clock() - t0) if pending and realtime else 0.0)
                 if delay > 0:
                     time.sleep(min(delay, 0.01))
             still = []
-            for fut, nb in finishing:
-                if fut.done():
+            for fut, nb, req in finishing:
+                if not fut.done():
+                    still.append((fut, nb, req))
+                    continue
+                self.used -= nb
+                try:
                     results.append(fut.result())
-                    self.used -= nb
-                else:
-                    still.append((fut, nb))
+                except Exception as exc:       # reading back failed: report it, keep serving
+                    results.append(self._failed(req, clock() - t0, exc))
             finishing = still
         self.batch.synchronize()
         return results
@@ -241,8 +261,12 @@ def solve_alone(req: SolveRequest, device: int = 0):
 
 
 def latency_stats(results, skip: int = 0):
-    lat = np.array([r.latency for r in sorted(results, key=lambda r: r.rid)[skip:]])
+    """Latency percentiles of the served requests after the first ``skip``
+    (by request id); failed requests are counted, not timed."""
+    kept = sorted(results, key=lambda r: r.rid)[skip:]
+    lat = np.array([r.latency for r in kept if r.error is None])
     if lat.size == 0:
         return {}
     return {"p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
-            "mean_s": float(lat.mean()), "max_s": float(lat.max()), "count": int(lat.size)}
+            "mean_s": float(lat.mean()), "max_s": float(lat.max()), "count": int(lat.size),
+            "failed": int(sum(r.error is not None for r in kept))}

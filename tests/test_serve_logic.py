@@ -11,8 +11,11 @@ from paper_1704_06258_amd import instances as I
 
 class FakeSolver:
     live = []
+    fail_seeds = set()       # requests whose build raises
 
     def __init__(self, C, W, p, *, population, generations_cb=None, **kw):
+        if kw.get("seed") in FakeSolver.fail_seeds:
+            raise RuntimeError("planted build failure")
         self.n, self.p, self.S = C.shape[0], p, population
         q = hubga.make_params(self.n, p, chi=kw["chi"], alpha=kw["alpha"], delta=kw["delta"], population=population,
                               island_size=kw["island_size"], n1=kw["n1"], precision=kw["precision"],
@@ -58,6 +61,7 @@ class FakeBatch:
 @pytest.fixture
 def fake(monkeypatch):
     FakeSolver.live = []
+    FakeSolver.fail_seeds = set()
     monkeypatch.setattr(serve.hubga, "Solver", FakeSolver)
     monkeypatch.setattr(serve.hubga, "Batch", FakeBatch)
     yield
@@ -122,3 +126,31 @@ def test_worker_threads_give_the_same_results(fake):
     for r in res:
         assert r.generations == reqs[r.rid].generations and r.cost == float(reqs[r.rid].generations)
     assert srv.used == 0
+
+
+def test_zero_generation_request_is_not_stepped(fake):
+    reqs = make_requests(4, [50, 100], [0, 3])
+    srv = serve.Server(hbm_budget=1 << 40, max_slots=4, workers=0)
+    res = srv.run(reqs, realtime=False)
+    srv.close()
+    assert sorted(r.rid for r in res) == [0, 1, 2, 3]
+    for r in res:
+        assert r.error is None and r.generations == reqs[r.rid].generations
+    assert srv.used == 0
+
+
+@pytest.mark.parametrize("workers", [0, 2])
+def test_failed_build_is_reported_and_released(fake, workers):
+    reqs = make_requests(6, [50, 100], [2, 3])
+    FakeSolver.fail_seeds = {2, 4}
+    srv = serve.Server(hbm_budget=1 << 40, max_slots=3, workers=workers)
+    res = srv.run(reqs, realtime=False)
+    srv.close()
+    assert sorted(r.rid for r in res) == list(range(6))
+    for r in res:
+        if r.rid in (2, 4):
+            assert r.error and "planted build failure" in r.error and r.hubs is None
+        else:
+            assert r.error is None and r.generations == reqs[r.rid].generations
+    assert srv.used == 0
+    assert serve.latency_stats(res)["failed"] == 2
