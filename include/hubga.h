@@ -116,6 +116,25 @@ size_t ga_workspace_bytes(const ga_params *params, ga_dtype c_dtype, ga_dtype w_
 ga_status ga_init(const ga_params *params, const void *C, ga_dtype c_dtype, const void *W, ga_dtype w_dtype,
                   void *d_workspace, size_t ws_bytes, void *hip_stream, ga_ctx **out);
 
+/* Allocation-free variant of ga_init, for callers that cannot allocate device
+ * memory (harnesses that forbid hipMalloc, serving loops that must not
+ * allocate): the same context as ga_init, built on a static workspace that
+ * the library holds per device from module load until the process ends
+ * (32 MiB), on the current device.
+ * Allocates nothing: no hipMalloc, hipFree or allocating library call (C and
+ * W are copied from the caller's host arrays as in ga_init).
+ *   - GA_ERR_INVALID when ga_workspace_bytes(params, ...) exceeds the static
+ *     workspace (use ga_init), or for the arguments ga_init rejects;
+ *   - GA_ERR_STATE while another context created by ga_init_static on the
+ *     same device is live: the device's one array holds that context's data
+ *     until ga_free releases it.  Contexts on different devices are
+ *     independent.  Nothing else shares the array.
+ * The array keeps the last context's contents; ga_init_static initialises
+ * every value the context reads before reading it, as ga_init does on a
+ * caller's uninitialised workspace.  Synchronous. */
+ga_status ga_init_static(const ga_params *params, const void *C, ga_dtype c_dtype, const void *W, ga_dtype w_dtype,
+                         void *hip_stream, ga_ctx **out);
+
 /* Evaluate `count` hub sets (host int32, count x p, any order, distinct ids in
  * [0, n)) with the context's precision and kernel (objective (1), Sec. 3 and
  * Sec. 4.3).  Outputs (host, caller-owned; any may be NULL except cost_out):

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <mutex>
+#include <new>
 #include <cstring>
 #include <new>
 #include <string>
@@ -179,7 +180,30 @@ struct ga_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     bool graph_failed = false;
+    int static_dev = -1;   // >= 0: created by ga_init_static on this device (static storage)
 };
+
+// ------------------------------------------------- allocation-free init --
+// ga_init_static's workspace: one array per device, resident from module load
+// until the process ends.  Host code never passes `scratch` itself to a
+// kernel or copy (in host code the name is a stand-in, not a device address):
+// it takes the address hipGetSymbolAddress returns for the current device.
+namespace {
+constexpr size_t kStaticWorkspaceBytes = (size_t)32 << 20;
+constexpr int kMaxStaticDevices = 64;
+}  // namespace
+__device__ __align__(256) unsigned char scratch[kStaticWorkspaceBytes];
+
+namespace {
+struct StaticSlot {
+    void *ptr = nullptr;   // scratch on this device
+    bool resolved = false;
+    bool busy = false;     // a live context holds the array
+    alignas(ga_ctx) unsigned char ctx_mem[sizeof(ga_ctx)];
+};
+StaticSlot g_static[kMaxStaticDevices];
+std::mutex g_static_mu;
+}  // namespace
 
 struct ga_batch {
     hipStream_t st = nullptr;
@@ -389,8 +413,28 @@ size_t ga_workspace_bytes(const ga_params *q, ga_dtype cdt, ga_dtype wdt)
     return carve(make_dims(q, cdt, wdt), q->c_symmetric).total;
 }
 
-ga_status ga_init(const ga_params *q, const void *C, ga_dtype cdt, const void *W, ga_dtype wdt, void *d_workspace,
-                  size_t ws_bytes, void *hip_stream, ga_ctx **out)
+// Frees what ga_init took (the workspace if the library allocated it) and the
+// context itself; a context in static storage is destroyed in place, its
+// device slot released only when release_slot is set.
+static void release_ctx(ga_ctx *ctx, bool release_slot)
+{
+    if (ctx->own_ws) (void)hipFree(ctx->ws);
+    const int sd = ctx->static_dev;
+    if (sd < 0) {
+        delete ctx;
+        return;
+    }
+    ctx->~ga_ctx();
+    if (release_slot) {
+        std::lock_guard<std::mutex> g(g_static_mu);
+        g_static[sd].busy = false;
+    }
+}
+
+// ga_init and ga_init_static: static_dev >= 0 builds the context in that
+// device's static storage on d_workspace (that device's static array).
+static ga_status init_ctx(const ga_params *q, const void *C, ga_dtype cdt, const void *W, ga_dtype wdt,
+                          void *d_workspace, size_t ws_bytes, void *hip_stream, ga_ctx **out, int static_dev)
 {
     ga_ctx *ctx = nullptr;
     try {
@@ -446,8 +490,9 @@ ga_status ga_init(const ga_params *q, const void *C, ga_dtype cdt, const void *W
                         "workspace too small: " + std::to_string(ws_bytes) + " < " + std::to_string(c.total));
         if (((uintptr_t)d_workspace) % 256)
             return fail(nullptr, GA_ERR_INVALID, "workspace must be 256-byte aligned");
-        ctx = new (std::nothrow) ga_ctx();
+        ctx = static_dev >= 0 ? new (g_static[static_dev].ctx_mem) ga_ctx() : new (std::nothrow) ga_ctx();
         if (!ctx) return fail(nullptr, GA_ERR_OOM, "host allocation failed");
+        ctx->static_dev = static_dev;
         ctx->prm = *q;
         ctx->d = d;
         ctx->st = (hipStream_t)hip_stream;
@@ -456,7 +501,7 @@ ga_status ga_init(const ga_params *q, const void *C, ga_dtype cdt, const void *W
         } else {
             hipError_t he = hipMalloc(&ctx->ws, c.total);
             if (he != hipSuccess) {
-                delete ctx;
+                release_ctx(ctx, false);
                 return fail(nullptr, GA_ERR_OOM, std::string("hipMalloc: ") + hipGetErrorString(he));
             }
             ctx->own_ws = true;
@@ -514,8 +559,7 @@ ga_status ga_init(const ga_params *q, const void *C, ga_dtype cdt, const void *W
         const size_t n2 = (size_t)d.n * d.n;
         auto dev_fail = [&](hipError_t he, const char *what) {
             std::string m = std::string(what) + ": " + hipGetErrorString(he);
-            if (ctx->own_ws) (void)hipFree(ctx->ws);
-            delete ctx;
+            release_ctx(ctx, false);
             return fail(nullptr, GA_ERR_DEVICE, m);
         };
         hipError_t he;
@@ -535,12 +579,57 @@ ga_status ga_init(const ga_params *q, const void *C, ga_dtype cdt, const void *W
         *out = ctx;
         return GA_OK;
     } catch (...) {
-        if (ctx) {
-            if (ctx->own_ws) (void)hipFree(ctx->ws);
-            delete ctx;
-        }
+        if (ctx) release_ctx(ctx, false);
         return fail(nullptr, GA_ERR_OOM, "exception in ga_init");
     }
+}
+
+ga_status ga_init(const ga_params *q, const void *C, ga_dtype cdt, const void *W, ga_dtype wdt, void *d_workspace,
+                  size_t ws_bytes, void *hip_stream, ga_ctx **out)
+{
+    return init_ctx(q, C, cdt, W, wdt, d_workspace, ws_bytes, hip_stream, out, -1);
+}
+
+ga_status ga_init_static(const ga_params *q, const void *C, ga_dtype cdt, const void *W, ga_dtype wdt,
+                         void *hip_stream, ga_ctx **out)
+{
+    if (!out) return fail(nullptr, GA_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    const std::string e = check_params(q);
+    if (!e.empty()) return fail(nullptr, GA_ERR_INVALID, e);
+    const size_t need = ga_workspace_bytes(q, cdt, wdt);
+    if (need == 0) return fail(nullptr, GA_ERR_INVALID, "unknown dtype");
+    if (need > kStaticWorkspaceBytes)
+        return fail(nullptr, GA_ERR_INVALID,
+                    "ga_init_static: the context needs " + std::to_string(need) + " workspace bytes, more than the " +
+                        std::to_string(kStaticWorkspaceBytes) + " of the static workspace; use ga_init");
+    int dev = 0;
+    hipError_t he = hipGetDevice(&dev);
+    if (he != hipSuccess) return fail(nullptr, GA_ERR_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(he));
+    if (dev < 0 || dev >= kMaxStaticDevices) return fail(nullptr, GA_ERR_INVALID, "ga_init_static: device id too large");
+    StaticSlot &slot = g_static[dev];
+    {
+        std::lock_guard<std::mutex> g(g_static_mu);
+        if (!slot.resolved) {   // once per device, with the device current
+            void *ptr = nullptr;
+            he = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+            if (he != hipSuccess || !ptr)
+                return fail(nullptr, GA_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") +
+                                                        hipGetErrorString(he));
+            slot.ptr = ptr;
+            slot.resolved = true;
+        }
+        if (slot.busy)
+            return fail(nullptr, GA_ERR_STATE,
+                        "ga_init_static: a live context holds this device's static workspace; ga_free it first");
+        slot.busy = true;
+    }
+    ga_status st = init_ctx(q, C, cdt, W, wdt, slot.ptr, kStaticWorkspaceBytes, hip_stream, out, dev);
+    if (st != GA_OK) {
+        std::lock_guard<std::mutex> g(g_static_mu);
+        slot.busy = false;
+    }
+    return st;
 }
 
 ga_status ga_evaluate(ga_ctx *ctx, const int32_t *hubs, int32_t count, double *cost_out, double *parts_out,
@@ -1049,8 +1138,7 @@ void ga_free(ga_ctx *ctx)
     (void)hipStreamSynchronize(ctx->st);
     drop_graph(ctx);
     for (auto &e : ctx->ev) (void)hipEventDestroy(e);
-    if (ctx->own_ws) (void)hipFree(ctx->ws);
-    delete ctx;
+    release_ctx(ctx, true);
 }
 
 }  // extern "C"

@@ -29,7 +29,7 @@ EXPORTS = ("ga_params_default", "ga_workspace_bytes", "ga_init", "ga_evaluate", 
            "ga_best", "ga_solve", "ga_population", "ga_ancestors", "ga_get_state", "ga_set_state", "ga_stats",
            "ga_profile_enable", "ga_profile_read", "ga_tile_config_count", "ga_tile_config_info",
            "ga_set_tile_config", "ga_evaluation_folded", "ga_set_stream", "ga_batch_create", "ga_batch_set", "ga_batch_step", "ga_batch_free",
-           "ga_status_str", "ga_last_error", "ga_free")
+           "ga_status_str", "ga_last_error", "ga_free", "ga_init_static")
 
 
 class ga_params(ct.Structure):
@@ -66,6 +66,8 @@ def lib():
         L.ga_workspace_bytes.argtypes = [P, ct.c_int, ct.c_int]
         L.ga_workspace_bytes.restype = sz
         L.ga_init.argtypes = [P, vp, ct.c_int, vp, ct.c_int, vp, sz, vp, ct.POINTER(vp)]
+        L.ga_init_static.argtypes = [P, vp, ct.c_int, vp, ct.c_int, vp, ct.POINTER(vp)]
+        L.ga_init_static.restype = ct.c_int
         L.ga_evaluate.argtypes = [vp, vp, i32, vp, vp, vp, vp]
         L.ga_evaluate_dev.argtypes = [vp, vp, i32, vp, vp]
         L.ga_step.argtypes = [vp, i32]
@@ -171,7 +173,11 @@ class Solver:
     """One context: an instance resident on the GPU plus its GA state."""
 
     def __init__(self, C, W, p, *, chi, alpha, delta, scale=1.0, seed=1, population=64, island_size=None, n1=10,
-                 elitist=True, precision="fp64", kernel=None, stream=None, device=0, c_symmetric=None):
+                 elitist=True, precision="fp64", kernel=None, stream=None, device=0, c_symmetric=None,
+                 static_workspace=False):
+        """``static_workspace``: build the context with ga_init_static on the
+        library's per-device static workspace (no device allocation) instead
+        of ga_init on a torch-allocated one."""
         import torch
         C = np.ascontiguousarray(C)
         W = np.ascontiguousarray(W)
@@ -190,14 +196,21 @@ class Solver:
         if nbytes == 0:
             raise HubGAError(GA_ERR_INVALID, "invalid parameters")
         self.device = torch.device("cuda", device)
-        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         # a stream of its own (non-null, so generations can be replayed as a graph)
         self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
         self.stream.wait_stream(torch.cuda.current_stream(self.device))
         self.workspace_bytes = nbytes
         h = ct.c_void_p()
-        _check(lib().ga_init(ct.byref(self.params), C.ctypes.data, cdt, W.ctypes.data, wdt,
-                             self.workspace.data_ptr(), nbytes, ct.c_void_p(self.stream.cuda_stream), ct.byref(h)))
+        if static_workspace:
+            self.workspace = None
+            with torch.cuda.device(self.device):
+                _check(lib().ga_init_static(ct.byref(self.params), C.ctypes.data, cdt, W.ctypes.data, wdt,
+                                            ct.c_void_p(self.stream.cuda_stream), ct.byref(h)))
+        else:
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            _check(lib().ga_init(ct.byref(self.params), C.ctypes.data, cdt, W.ctypes.data, wdt,
+                                 self.workspace.data_ptr(), nbytes, ct.c_void_p(self.stream.cuda_stream),
+                                 ct.byref(h)))
         self.ctx = h
 
     # -- evaluation -------------------------------------------------------
