@@ -14,12 +14,16 @@ Each wrapper names the passage of the paper it follows:
   (Sec. 4.1, Sec. 5);
 * ``middle_nodes`` -- the initial solution from the p middle nodes (Sec. 4.1);
 * ``ga_children`` / ``ga_run`` -- the island GA of Sec. 4.2 and Sec. 5;
+* ``enumerate_best`` -- exhaustive search of the nearest-hub solution space,
+  the optimum of Sec. 6.2's comparisons over the GA's search space;
 * ``philox`` -- Philox4x64-10 (Salmon et al., SC'11), the counter-based
   generator that both sides implement from its published definition.
 """
 from __future__ import annotations
 
 import ctypes as ct
+import itertools
+import math
 import os
 import subprocess
 import threading
@@ -186,6 +190,23 @@ def evaluate(C, W, hubs, chi, alpha, delta, scale=1.0, want_alloc=False):
     if rc:
         raise ValueError("invalid hub set (out of range or repeated)")
     return (cost, parts, alloc) if want_alloc else (cost, parts)
+
+
+def enumerate_best(C, W, p, chi, alpha, delta, scale=1.0, first=0, count=None):
+    """Exhaustive search of the nearest-hub solution space (the optimum the
+    GA is compared with in Sec. 6.2; allocation rule of Sec. 4.1 and 5): the
+    p-subsets of range(n) of lexicographic ranks [first, first + count), each
+    evaluated as ``evaluate`` does.  Returns (cost, hubs, rank, costs): the
+    smallest cost, the first set (lowest rank) attaining it, its rank, and
+    every cost in rank order."""
+    C = _f64(C)
+    n = C.shape[0]
+    total = math.comb(n, p)
+    count = total - first if count is None else count
+    sets = np.array(list(itertools.islice(itertools.combinations(range(n), p), first, first + count)), np.int32)
+    costs, _ = evaluate(C, W, sets, chi, alpha, delta, scale)
+    j = int(np.argmin(costs))          # first occurrence: the lowest rank among equal costs
+    return float(costs[j]), sets[j].copy(), first + j, costs
 
 
 # --------------------------------------------------------------- GA ops ----

@@ -413,3 +413,56 @@ def test_ga_global_step_synchronises_islands():
     oracle.ga_run(C, W, st, 4, **kw)      # g = 0..3, the global step runs after g = 3
     assert np.all(st.anc == st.anc[0]) and np.all(st.anc_cost == st.anc_cost[0])
     assert st.anc_cost[0] == st.best_cost[0]
+
+
+# ------------------------------------------------------- exhaustive search --
+
+def nearest_allocation(C, hubs):
+    """Nearest hub per node by numpy argmin over the hub columns (first
+    minimum: the smaller hub id, hubs ascending), hubs to themselves."""
+    hubs = np.asarray(hubs)
+    a = hubs[np.argmin(C[:, hubs], axis=1)]
+    a[hubs] = hubs
+    return a
+
+
+def test_enumeration_optimum_against_per_path_brute_force():
+    inst = I.random_asymmetric(seed=43, n=9, p=3)
+    C, W = inst.C64(), inst.W64()
+    best, hubs, rank, costs = oracle.enumerate_best(C, W, 3, inst.chi, inst.alpha, inst.delta)
+    sets = list(itertools.combinations(range(9), 3))
+    assert len(costs) == len(sets) == 84
+    ref = [per_path_cost(C, W, nearest_allocation(C, h), inst.chi, inst.alpha, inst.delta) for h in sets]
+    assert np.allclose(costs, ref, rtol=1e-12, atol=0)
+    assert abs(best - min(ref)) <= 1e-12 * min(ref)
+    assert tuple(hubs) == sets[int(np.argmin(ref))] == sets[rank]
+
+
+def test_enumeration_order_is_lexicographic_and_ranges_compose():
+    inst = I.uniform(seed=44, n=11, p=4)
+    C, W = inst.C64(), inst.W64()
+    _, _, _, full = oracle.enumerate_best(C, W, 4, inst.chi, inst.alpha, inst.delta)
+    assert len(full) == 330
+    # rank r is the r-th subset when subsets are ordered as sorted tuples
+    sets = sorted({tuple(sorted(s)) for s in itertools.permutations(range(11), 4)})
+    direct, _ = oracle.evaluate(C, W, np.array(sets, np.int32), inst.chi, inst.alpha, inst.delta)
+    assert np.array_equal(full, direct)
+    best, hubs, rank, part = oracle.enumerate_best(C, W, 4, inst.chi, inst.alpha, inst.delta, first=100, count=50)
+    assert np.array_equal(part, full[100:150]) and 100 <= rank < 150 and best == part.min()
+
+
+def test_enumeration_p1_closed_form_and_ties_to_lower_rank():
+    inst = I.random_asymmetric(seed=45, n=12, p=1)
+    C, W = inst.C64(), inst.W64()
+    O, D = W.sum(axis=1), W.sum(axis=0)
+    closed = inst.chi * (O @ C) + inst.alpha * W.sum() * np.diag(C) + inst.delta * (D @ C)
+    best, hubs, rank, _ = oracle.enumerate_best(C, W, 1, inst.chi, inst.alpha, inst.delta)
+    assert rank == hubs[0] == int(np.argmin(closed)) and abs(best - closed.min()) <= 1e-12 * closed.min()
+    # a ring with unit flows: rotations of a hub set cost exactly the same
+    n = 10
+    i = np.arange(n)
+    d = np.abs(i[:, None] - i[None, :])
+    C = np.minimum(d, n - d).astype(np.float64)
+    W = np.ones((n, n)) - np.eye(n)
+    best, hubs, rank, costs = oracle.enumerate_best(C, W, 2, 1.0, 0.5, 1.0)
+    assert np.sum(costs == best) > 1 and np.all(costs[:rank] > best)
