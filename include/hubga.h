@@ -154,6 +154,28 @@ ga_status ga_evaluate(ga_ctx *ctx, const int32_t *hubs, int32_t count, double *c
  * d_cost: count doubles (scaled cost). */
 ga_status ga_evaluate_dev(ga_ctx *ctx, const int32_t *d_hubs, int32_t count, uint16_t *d_kidx, double *d_cost);
 
+/* Exhaustive search of the nearest-hub solution space (the optimum the GA's
+ * results are compared with in Sec. 6.2, Tables 1 and 3, restricted to the
+ * allocation rule of Sec. 4.1 and 5): the hub sets of lexicographic ranks
+ * [first, first + count) among all C(n, p) p-subsets of the nodes (rank 0 =
+ * {0, 1, ..., p-1}; count = -1: through the last) are evaluated with the
+ * context's precision and kernels, in chunks of the population size, and the
+ * set of smallest exact cost is returned (ties to the lower rank).  In the
+ * approximate modes every set whose error interval could hold the minimum is
+ * re-evaluated exactly in binary64 (canonical order), so the result is the
+ * exact argmin.  Outputs (host, caller-owned, any may be NULL):
+ *   hubs_out[p], cost_out (exact scaled cost), parts_out[3] {Cc, T, Dd},
+ *   rank_out (its rank);
+ *   costs_all[count], eps_all[count]: every set's cost as evaluated and its
+ *   relative error bound, in rank order (these copies wait per chunk);
+ *   rechecks_out: sets re-evaluated exactly.
+ * GA_ERR_INVALID when C(n, p) >= 2^62 or the range is empty or outside
+ * [0, C(n, p)).  Overwrites the population buffers (ga_population) but not
+ * the GA state.  Synchronous. */
+ga_status ga_enumerate(ga_ctx *ctx, int64_t first, int64_t count, int32_t *hubs_out, double *cost_out,
+                       double *parts_out, int64_t *rank_out, double *costs_all, double *eps_all,
+                       int64_t *rechecks_out);
+
 /* Advance the GA by `generations` generations (Sec. 4.2 and 5): per island,
  * every child is a perturbation of the island ancestor, crossed with its pair
  * partner, mutated, corrected to p hubs, allocated to nearest hubs and

@@ -18,7 +18,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhubga.so")
-SOURCES = ["prep.hip", "alloc.hip", "eval_plain.hip", "recheck.hip", "eval_mfma.hip", "ga_ops.hip", "select.hip", "hubga.cpp"]
+SOURCES = ["prep.hip", "alloc.hip", "eval_plain.hip", "recheck.hip", "eval_mfma.hip", "ga_ops.hip", "select.hip",
+           "enumerate.hip", "hubga.cpp"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 

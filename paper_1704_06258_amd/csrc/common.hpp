@@ -14,6 +14,16 @@ constexpr int kPad = 128;               // n is padded to a multiple of this for
 
 enum Precision { kFP64 = 0, kFP32 = 1, kSplitBF16 = 2 };
 
+// Running state of an exhaustive search (enumerate.hip).
+struct EnumState {
+    double best_cost;       // exact scaled cost of the best set so far (+inf before any)
+    double best_parts[3];   // its {Cc, T, Dd}
+    int64_t best_rank;      // its lexicographic rank (-1 before any)
+    int64_t rechecks;       // sets re-evaluated exactly
+    int cand_count;         // sets listed for exact re-evaluation in the current chunk
+    int pad;
+};
+
 // Device pointers of one context, carved out of the workspace.
 struct DevPtrs {
     void *C;            // n*n, instance dtype
@@ -61,6 +71,10 @@ struct DevPtrs {
     int32_t *nextra;    // 1
     int *sync;          // 2 grid counters (last workgroup of the selection, last unit of the
                         // re-evaluation), zero between launches
+    // exhaustive search
+    EnumState *enum_state;
+    int32_t *enum_best; // p: hub set of the best so far
+    uint64_t *binom;    // (n+1)*(p+1): C(m, j) at [m*(p+1) + j], saturated at 2^63
 };
 
 struct Dims {

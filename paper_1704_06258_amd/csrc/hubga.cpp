@@ -91,7 +91,8 @@ Dims make_dims(const ga_params *q, ga_dtype cdt, ga_dtype wdt)
 // Offsets of every device buffer; the same walk sizes and carves.
 struct Carve {
     size_t C, Ct, Ct32, W, W32, Whi, Wlo, Whsw, Wlsw, Wfhsw, Wflsw, O, D, dsum, hubs, kidx, cost, parts, eps, cmax, Ch32, partial, anc, anc_cost,
-        anc_parts, best, best_cost, gen, stats, cand, cand_cnt, cand_cost, cand_parts, kidx_one, scratch, tbuf, slot_r, slot_c, slot_s, slot_done, handled, choice, total_slots, extra_r, extra_c, nextra, sync;
+        anc_parts, best, best_cost, gen, stats, cand, cand_cnt, cand_cost, cand_parts, kidx_one, scratch, tbuf, slot_r, slot_c, slot_s, slot_done, handled, choice, total_slots, extra_r, extra_c, nextra, sync,
+        enum_state, enum_best, binom;
     size_t total;
 };
 
@@ -151,6 +152,9 @@ Carve carve(const Dims &d, int c_symmetric)
     c.extra_c = L.take((size_t)d.S * 4);
     c.nextra = L.take(4);
     c.sync = L.take(8);
+    c.enum_state = L.take(sizeof(EnumState));
+    c.enum_best = L.take((size_t)d.p * 4);
+    c.binom = L.take((size_t)(d.n + 1) * (d.p + 1) * 8);
     c.total = L.total;
     return c;
 }
@@ -181,6 +185,9 @@ struct ga_ctx {
     hipGraphExec_t gexec = nullptr;
     bool graph_failed = false;
     int static_dev = -1;   // >= 0: created by ga_init_static on this device (static storage)
+    // exhaustive search: the binomial table is copied to the device on first use
+    bool binom_ready = false;
+    uint64_t nsets = 0;    // C(n, p), saturated at 2^63
 };
 
 // ------------------------------------------------- allocation-free init --
@@ -468,6 +475,7 @@ static ga_status init_ctx(const ga_params *q, const void *C, ga_dtype cdt, const
                 (void)hipGetLastError();
                 prep_err = prepare_plain_kernels(max_lds);
                 if (prep_err == hipSuccess) prep_err = prepare_recheck_kernels(max_lds);
+                if (prep_err == hipSuccess) prep_err = prepare_enum_kernels(max_lds);
             });
             if (prep_err != hipSuccess)
                 return fail(nullptr, GA_ERR_DEVICE, std::string("kernel attributes: ") + hipGetErrorString(prep_err));
@@ -555,6 +563,9 @@ static ga_status init_ctx(const ga_params *q, const void *C, ga_dtype cdt, const
         P.extra_c = at<int32_t>(b, c.extra_c);
         P.nextra = at<int32_t>(b, c.nextra);
         P.sync = at<int>(b, c.sync);
+        P.enum_state = at<EnumState>(b, c.enum_state);
+        P.enum_best = at<int32_t>(b, c.enum_best);
+        P.binom = at<uint64_t>(b, c.binom);
 
         const size_t n2 = (size_t)d.n * d.n;
         auto dev_fail = [&](hipError_t he, const char *what) {
@@ -692,6 +703,63 @@ ga_status ga_evaluate_dev(ga_ctx *ctx, const int32_t *d_hubs, int32_t count, uin
         HIPCHK(hipMemcpy2DAsync(d_kidx, 2 * (size_t)d.n, ctx->P.kidx, 2 * (size_t)d.n_pad, 2 * (size_t)d.n, count,
                                 hipMemcpyDeviceToDevice, ctx->st));
     return GA_OK;
+}
+
+ga_status ga_enumerate(ga_ctx *ctx, int64_t first, int64_t count, int32_t *hubs_out, double *cost_out,
+                       double *parts_out, int64_t *rank_out, double *costs_all, double *eps_all, int64_t *rechecks_out)
+{
+    CTXCHK(ctx);
+    try {
+        const Dims &d = ctx->d;
+        const DevPtrs &P = ctx->P;
+        constexpr uint64_t kSat = 1ull << 63;
+        if (!ctx->binom_ready) {   // Pascal's triangle, saturating
+            const int w = d.p + 1;
+            std::vector<uint64_t> t((size_t)(d.n + 1) * w, 0);
+            for (int m = 0; m <= d.n; ++m) {
+                t[(size_t)m * w] = 1;
+                for (int j = 1; j <= std::min(m, d.p); ++j) {
+                    const uint64_t a = t[(size_t)(m - 1) * w + j - 1], b = t[(size_t)(m - 1) * w + j];
+                    t[(size_t)m * w + j] = (a >= kSat || b >= kSat || a + b >= kSat) ? kSat : a + b;
+                }
+            }
+            HIPCHK(hipMemcpyAsync(P.binom, t.data(), t.size() * 8, hipMemcpyHostToDevice, ctx->st));
+            HIPCHK(hipStreamSynchronize(ctx->st));
+            ctx->nsets = t[(size_t)d.n * w + d.p];
+            ctx->binom_ready = true;
+        }
+        const uint64_t total = ctx->nsets;
+        if (total >= (1ull << 62)) return fail(ctx, GA_ERR_INVALID, "C(n, p) is 2^62 or more: too many hub sets");
+        if (first < 0 || (uint64_t)first >= total) return fail(ctx, GA_ERR_INVALID, "first must be in [0, C(n, p))");
+        if (count < 0) count = (int64_t)(total - (uint64_t)first);
+        if (count == 0 || (uint64_t)count > total - (uint64_t)first)
+            return fail(ctx, GA_ERR_INVALID, "count must be in [1, C(n, p) - first], or -1");
+        HIPCHK(launch_enum_init(P, ctx->st));
+        for (int64_t off = 0; off < count; off += d.S) {
+            const int cnt = (int)std::min<int64_t>(d.S, count - off);
+            HIPCHK(launch_enum_unrank(P, d, first + off, cnt, ctx->st));
+            ga_status st = run_eval(ctx, P.hubs, cnt, P.kidx);
+            if (st != GA_OK) return st;
+            HIPCHK(launch_enum_select(P, d, first + off, cnt, ctx->st));
+            if (costs_all)
+                HIPCHK(hipMemcpyAsync(costs_all + off, P.cost, 8 * (size_t)cnt, hipMemcpyDeviceToHost, ctx->st));
+            if (eps_all)
+                HIPCHK(hipMemcpyAsync(eps_all + off, P.eps, 8 * (size_t)cnt, hipMemcpyDeviceToHost, ctx->st));
+        }
+        EnumState es;
+        std::vector<int32_t> h(d.p);
+        HIPCHK(hipMemcpyAsync(&es, P.enum_state, sizeof(es), hipMemcpyDeviceToHost, ctx->st));
+        HIPCHK(hipMemcpyAsync(h.data(), P.enum_best, 4 * (size_t)d.p, hipMemcpyDeviceToHost, ctx->st));
+        HIPCHK(hipStreamSynchronize(ctx->st));
+        if (hubs_out) std::memcpy(hubs_out, h.data(), 4 * (size_t)d.p);
+        if (cost_out) *cost_out = es.best_cost;
+        if (parts_out) std::memcpy(parts_out, es.best_parts, 24);
+        if (rank_out) *rank_out = es.best_rank;
+        if (rechecks_out) *rechecks_out = es.rechecks;
+        return GA_OK;
+    } catch (...) {
+        return fail(ctx, GA_ERR_OOM, "host allocation failed in ga_enumerate");
+    }
 }
 
 ga_status ga_step(ga_ctx *ctx, int32_t generations)

@@ -52,6 +52,12 @@ int mfma_rows_per_tile(int cfg);
 int mfma_cols_per_tile(int cfg);
 int mfma_k_tile(int cfg);
 
+// exhaustive search over hub sets (enumerate.hip)
+hipError_t launch_enum_init(const DevPtrs &P, hipStream_t st);
+hipError_t launch_enum_unrank(const DevPtrs &P, const Dims &d, int64_t first, int count, hipStream_t st);
+hipError_t launch_enum_select(const DevPtrs &P, const Dims &d, int64_t first, int count, hipStream_t st);
+hipError_t prepare_enum_kernels(int max_lds);
+
 // GA (ga_ops.hip, select.hip)
 hipError_t launch_ga_ops(const DevPtrs &P, const Dims &d, hipStream_t st);
 int ga_ops_blocks(const Dims &d);

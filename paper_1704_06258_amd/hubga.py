@@ -29,7 +29,7 @@ EXPORTS = ("ga_params_default", "ga_workspace_bytes", "ga_init", "ga_evaluate", 
            "ga_best", "ga_solve", "ga_population", "ga_ancestors", "ga_get_state", "ga_set_state", "ga_stats",
            "ga_profile_enable", "ga_profile_read", "ga_tile_config_count", "ga_tile_config_info",
            "ga_set_tile_config", "ga_evaluation_folded", "ga_set_stream", "ga_batch_create", "ga_batch_set", "ga_batch_step", "ga_batch_free",
-           "ga_status_str", "ga_last_error", "ga_free", "ga_init_static")
+           "ga_status_str", "ga_last_error", "ga_free", "ga_init_static", "ga_enumerate")
 
 
 class ga_params(ct.Structure):
@@ -70,6 +70,9 @@ def lib():
         L.ga_init_static.restype = ct.c_int
         L.ga_evaluate.argtypes = [vp, vp, i32, vp, vp, vp, vp]
         L.ga_evaluate_dev.argtypes = [vp, vp, i32, vp, vp]
+        L.ga_enumerate.argtypes = [vp, i64, i64, vp, ct.POINTER(ct.c_double), vp, ct.POINTER(i64), vp, vp,
+                                   ct.POINTER(i64)]
+        L.ga_enumerate.restype = ct.c_int
         L.ga_step.argtypes = [vp, i32]
         L.ga_best.argtypes = [vp, vp, vp, vp, vp, vp]
         L.ga_solve.argtypes = [vp, i32, vp, vp, vp]
@@ -247,6 +250,27 @@ class Solver:
             if t is not None:
                 t.record_stream(self.stream)
         return d_cost
+
+    def enumerate(self, first=0, count=-1, want_all=False):
+        """Exact best hub set of lexicographic ranks [first, first + count)
+        (ga_enumerate); with ``want_all`` also every set's cost and bound."""
+        import math
+        total = math.comb(self.n, self.p)
+        k = (total - first) if count < 0 else count
+        hubs = np.zeros(self.p, np.int32)
+        cost = ct.c_double()
+        parts = np.zeros(3)
+        rank = ct.c_int64()
+        rechecks = ct.c_int64()
+        costs = np.zeros(max(k, 1)) if want_all else None
+        eps = np.zeros(max(k, 1)) if want_all else None
+        _check(lib().ga_enumerate(self.ctx, int(first), int(count), hubs.ctypes.data, ct.byref(cost),
+                                  parts.ctypes.data, ct.byref(rank), costs.ctypes.data if want_all else None,
+                                  eps.ctypes.data if want_all else None, ct.byref(rechecks)), self.ctx)
+        out = dict(hubs=hubs, cost=cost.value, parts=parts, rank=rank.value, rechecks=rechecks.value)
+        if want_all:
+            out["costs"], out["eps"] = costs[:k], eps[:k]
+        return out
 
     # -- GA ---------------------------------------------------------------
     def step(self, generations=1):
