@@ -100,6 +100,16 @@ def _load():
         return lib
 
 
+def set_threads(k: int) -> int:
+    """Threads of the oracle's OpenMP loops from now on (the OpenMP runtime the
+    library links); returns the number its parallel regions will use."""
+    _load()
+    gomp = ct.CDLL("libgomp.so.1")
+    gomp.omp_set_num_threads(int(k))
+    gomp.omp_get_max_threads.restype = ct.c_int
+    return int(gomp.omp_get_max_threads())
+
+
 def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 

@@ -58,27 +58,40 @@ __global__ __launch_bounds__(256) void k_eval_fp32(const int32_t *__restrict__ h
     for (int e = tid; e < p * p; e += nt) Ch[e] = (float)Ct[(size_t)h[e % p] * n + h[e / p]];
     __syncthreads();
     double tsum = 0.0;
+    constexpr int RU = 8;   // rows whose W loads are in flight together, as in the binary64 kernel
     for (int j0 = tid; j0 < n; j0 += 4 * nt) {
-        int js[4], kj[4];
+        int js[4], kj[4], jc[4];
         float acc[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             js[q] = j0 + q * nt;
             kj[q] = js[q] < n ? kid[js[q]] : 0;
+            jc[q] = js[q] < n ? js[q] : 0;   // absent columns read column 0 and are discarded
             acc[q] = 0.0f;
         }
-        const bool full = js[3] < n;
-        for (int i = 0; i < n; ++i) {
+        int i = 0;
+        for (; i + RU <= n; i += RU) {
+            float w[RU][4];
+            int ki[RU];
+#pragma unroll
+            for (int u = 0; u < RU; ++u) {
+                const float *wr = W + (size_t)(i + u) * n;
+                ki[u] = kid[i + u];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) w[u][q] = wr[jc[q]];
+            }
+#pragma unroll
+            for (int u = 0; u < RU; ++u) {
+                const float *chr = Ch + (size_t)ki[u] * p;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[q] = __builtin_fmaf(w[u][q], chr[kj[q]], acc[q]);
+            }
+        }
+        for (; i < n; ++i) {
             const float *wr = W + (size_t)i * n;
             const float *chr = Ch + (size_t)kid[i] * p;
-            if (full) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) acc[q] = __builtin_fmaf(wr[js[q]], chr[kj[q]], acc[q]);
-            } else {
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    if (js[q] < n) acc[q] = __builtin_fmaf(wr[js[q]], chr[kj[q]], acc[q]);
-            }
+            for (int q = 0; q < 4; ++q) acc[q] = __builtin_fmaf(wr[jc[q]], chr[kj[q]], acc[q]);
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q)
