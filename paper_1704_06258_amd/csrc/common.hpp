@@ -13,6 +13,8 @@ constexpr int kMfmaMinRows = 64;        // smallest row tile of the batched kern
 constexpr int kPad = 128;               // n is padded to a multiple of this for the bf16 copies
 
 enum Precision { kFP64 = 0, kFP32 = 1, kSplitBF16 = 2 };
+// Layouts of the bf16 hi/lo split of W (one pair of buffers per context).
+enum WLayout { kWRowMajor = 0, kWFrag = 1, kWFragFolded = 2 };
 
 // Running state of an exhaustive search (enumerate.hip).
 struct EnumState {
@@ -31,12 +33,16 @@ struct DevPtrs {
     float *Ct32;        // Ct rounded to FP32 (== Ct for an FP32 instance)
     void *W;            // n*n, instance dtype
     float *W32;         // n*n FP32 copy (FP32 mode with a binary64 instance), else null
-    uint16_t *Whi;      // n_pad*n_pad bf16 bits (split mode), else null
+    // The bf16 hi/lo split of W: n_pad*n_pad bf16 bits each (split mode), else
+    // null.  One pair of buffers holds the layout the current tile
+    // configuration reads (WLayout), rewritten when the configuration needs
+    // another; the names below alias it by layout:
+    uint16_t *Whi;      //   row-major
     uint16_t *Wlo;
-    uint16_t *Whsw;     // W hi/lo in fragment order: 16-byte chunk (row r, k 8c..8c+7) at
+    uint16_t *Whsw;     //   fragment order: 16-byte chunk (row r, k 8c..8c+7) at
     uint16_t *Wlsw;     //   ((r/64 * n_pad/16 + k/16)*2 + (k/8)%2)*64 + r%64
-    uint16_t *Wfhsw;    // the same layout of the folded W (C symmetric): W_rk + W_kr above the
-    uint16_t *Wflsw;    //   diagonal, W_rr on it, zero below; else null
+    uint16_t *Wfhsw;    //   fragment order of the folded W (C symmetric): W_rk + W_kr above
+    uint16_t *Wflsw;    //   the diagonal, W_rr on it, zero below
     double *O, *D, *dsum;
     int32_t *hubs;      // S*p current batch / children (sorted)
     uint16_t *kidx;     // S*n_pad hub positions (kNoHub in the padding)

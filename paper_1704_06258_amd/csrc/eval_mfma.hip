@@ -944,6 +944,17 @@ bool mfma_folds(const Dims &d, int cfg)
     return d.sym && c.nst > 0 && c.kt == 64 && kidx_transfers(c.colb, d.p) <= 2;
 }
 
+// The layout of the W split that configuration cfg reads for this context:
+// the register-staged kernels (and the few-hub fallback of the pipelined
+// ones) read it row-major, the pipelined ones in fragment order, of the
+// folded W when they fold.
+int mfma_w_layout(const Dims &d, int cfg)
+{
+    const MfmaCfg &c = kMfmaCfgs[cfg];
+    if (c.nst == 0 || kidx_transfers(c.colb, d.p) > 2) return kWRowMajor;
+    return mfma_folds(d, cfg) ? kWFragFolded : kWFrag;
+}
+
 // Row tiles the partials of configuration cfg use for p hubs.
 int mfma_partial_tiles(const Dims &d, int cfg)
 {

@@ -90,7 +90,7 @@ Dims make_dims(const ga_params *q, ga_dtype cdt, ga_dtype wdt)
 
 // Offsets of every device buffer; the same walk sizes and carves.
 struct Carve {
-    size_t C, Ct, Ct32, W, W32, Whi, Wlo, Whsw, Wlsw, Wfhsw, Wflsw, O, D, dsum, hubs, kidx, cost, parts, eps, cmax, Ch32, partial, anc, anc_cost,
+    size_t C, Ct, Ct32, W, W32, Whi, Wlo, O, D, dsum, hubs, kidx, cost, parts, eps, cmax, Ch32, partial, anc, anc_cost,
         anc_parts, best, best_cost, gen, stats, cand, cand_cnt, cand_cost, cand_parts, kidx_one, scratch, tbuf, slot_r, slot_c, slot_s, slot_done, handled, choice, total_slots, extra_r, extra_c, nextra, sync,
         enum_state, enum_best, binom;
     size_t total;
@@ -110,12 +110,9 @@ Carve carve(const Dims &d, int c_symmetric)
     c.Ct32 = d.c_f32 ? c.Ct : L.take((n2 + d.n) * 4);
     c.W = L.take(n2 * ws);
     c.W32 = (d.prec == kFP32 && !d.w_f32) ? L.take(n2 * 4) : (size_t)-1;
+    // one pair of split buffers, in the layout the current tile configuration reads
     c.Whi = split ? L.take(np2 * 2) : (size_t)-1;
     c.Wlo = split ? L.take(np2 * 2) : (size_t)-1;
-    c.Whsw = split ? L.take(np2 * 2) : (size_t)-1;
-    c.Wlsw = split ? L.take(np2 * 2) : (size_t)-1;
-    c.Wfhsw = split && d.sym ? L.take(np2 * 2) : (size_t)-1;
-    c.Wflsw = split && d.sym ? L.take(np2 * 2) : (size_t)-1;
     c.O = L.take((size_t)d.n * 8);
     c.D = L.take((size_t)d.n * 8);
     c.dsum = L.take((size_t)d.n * 8);
@@ -188,6 +185,7 @@ struct ga_ctx {
     // exhaustive search: the binomial table is copied to the device on first use
     bool binom_ready = false;
     uint64_t nsets = 0;    // C(n, p), saturated at 2^63
+    int wlayout = -1;      // WLayout held in the split buffers (-1: none yet)
 };
 
 // ------------------------------------------------- allocation-free init --
@@ -216,6 +214,7 @@ struct ga_batch {
     hipStream_t st = nullptr;
     int cfg = 7;
     std::vector<ga_ctx *> ctxs;
+    std::vector<ga_ctx *> grouped;   // stepped by the grouped launches
     std::vector<ga_ctx *> solo;      // stepped by their own generation on side streams
     std::vector<hipStream_t> side;
     std::vector<hipEvent_t> ev;      // [0] fork, [1 + k] join of side stream k
@@ -268,6 +267,19 @@ void prof_events(ga_ctx *ctx, hipEvent_t *a, hipEvent_t *b)
     *a = ctx->ev[ctx->ev_used];
     *b = ctx->ev[ctx->ev_used + 1];
     ctx->ev_used += 2;
+}
+
+// The split buffers into the layout tile configuration cfg reads (split
+// mode), enqueued on the context's stream when it differs from the layout
+// they hold.  Never called during graph capture.
+ga_status ensure_w_layout(ga_ctx *ctx, int cfg)
+{
+    if (ctx->d.prec != kSplitBF16) return GA_OK;
+    const int want = mfma_w_layout(ctx->d, cfg);
+    if (want == ctx->wlayout) return GA_OK;
+    HIPCHK(launch_w_layout(ctx->P, ctx->d, want, ctx->st));
+    ctx->wlayout = want;
+    return GA_OK;
 }
 
 // Evaluate `count` sorted hub sets at `hubs` (device) into P.cost / P.parts /
@@ -523,10 +535,8 @@ static ga_status init_ctx(const ga_params *q, const void *C, ga_dtype cdt, const
         P.W32 = at<float>(b, c.W32);
         P.Whi = at<uint16_t>(b, c.Whi);
         P.Wlo = at<uint16_t>(b, c.Wlo);
-        P.Whsw = at<uint16_t>(b, c.Whsw);
-        P.Wlsw = at<uint16_t>(b, c.Wlsw);
-        P.Wfhsw = at<uint16_t>(b, c.Wfhsw);
-        P.Wflsw = at<uint16_t>(b, c.Wflsw);
+        P.Whsw = P.Wfhsw = P.Whi;
+        P.Wlsw = P.Wflsw = P.Wlo;
         P.O = at<double>(b, c.O);
         P.D = at<double>(b, c.D);
         P.dsum = at<double>(b, c.dsum);
@@ -579,6 +589,11 @@ static ga_status init_ctx(const ga_params *q, const void *C, ga_dtype cdt, const
         if ((he = hipMemcpyAsync(P.W, W, n2 * (d.w_f32 ? 4 : 8), hipMemcpyHostToDevice, ctx->st)) != hipSuccess)
             return dev_fail(he, "copy W");
         if ((he = launch_prep(P, d, ctx->st)) != hipSuccess) return dev_fail(he, "prep");
+        if (d.prec == kSplitBF16) {
+            if ((he = launch_w_layout(P, d, mfma_w_layout(d, d.mfma_cfg), ctx->st)) != hipSuccess)
+                return dev_fail(he, "split of W");
+            ctx->wlayout = mfma_w_layout(d, d.mfma_cfg);
+        }
         // ancestor P0: middle nodes, nearest-hub allocation, exact cost (Sec. 4.1)
         if ((he = launch_middle_nodes(P, d, P.best, P.scratch, ctx->st)) != hipSuccess)
             return dev_fail(he, "middle nodes");
@@ -655,6 +670,8 @@ ga_status ga_evaluate(ga_ctx *ctx, const int32_t *hubs, int32_t count, double *c
             std::string e = sort_check_hubs(hubs + (size_t)s * d.p, d.p, d.n, &sorted[(size_t)s * d.p]);
             if (!e.empty()) return fail(ctx, GA_ERR_INVALID, "hub set " + std::to_string(s) + ": " + e);
         }
+        ga_status ls = ensure_w_layout(ctx, d.mfma_cfg);
+        if (ls != GA_OK) return ls;
         std::vector<double> c((size_t)d.S), pr((size_t)3 * d.S), ep((size_t)d.S);
         std::vector<uint16_t> kx;
         if (alloc_out) kx.resize((size_t)d.S * d.n_pad);
@@ -695,8 +712,10 @@ ga_status ga_evaluate_dev(ga_ctx *ctx, const int32_t *d_hubs, int32_t count, uin
     const Dims &d = ctx->d;
     if (!d_hubs || !d_cost || count < 1 || count > d.S)
         return fail(ctx, GA_ERR_INVALID, "need 1 <= count <= population and device hubs/cost");
+    ga_status s = ensure_w_layout(ctx, d.mfma_cfg);
+    if (s != GA_OK) return s;
     HIPCHK(launch_copy_clamp(d_hubs, ctx->P.hubs, count * d.p, d.n, ctx->st));
-    ga_status s = run_eval(ctx, ctx->P.hubs, count, ctx->P.kidx);
+    s = run_eval(ctx, ctx->P.hubs, count, ctx->P.kidx);
     if (s != GA_OK) return s;
     HIPCHK(hipMemcpyAsync(d_cost, ctx->P.cost, 8 * (size_t)count, hipMemcpyDeviceToDevice, ctx->st));
     if (d_kidx)
@@ -734,6 +753,8 @@ ga_status ga_enumerate(ga_ctx *ctx, int64_t first, int64_t count, int32_t *hubs_
         if (count < 0) count = (int64_t)(total - (uint64_t)first);
         if (count == 0 || (uint64_t)count > total - (uint64_t)first)
             return fail(ctx, GA_ERR_INVALID, "count must be in [1, C(n, p) - first], or -1");
+        ga_status ls = ensure_w_layout(ctx, d.mfma_cfg);
+        if (ls != GA_OK) return ls;
         HIPCHK(launch_enum_init(P, ctx->st));
         for (int64_t off = 0; off < count; off += d.S) {
             const int cnt = (int)std::min<int64_t>(d.S, count - off);
@@ -767,6 +788,8 @@ ga_status ga_step(ga_ctx *ctx, int32_t generations)
     CTXCHK(ctx);
     if (generations < 0) return fail(ctx, GA_ERR_INVALID, "generations must be >= 0");
     if (generations == 0) return GA_OK;
+    ga_status ls = ensure_w_layout(ctx, ctx->d.mfma_cfg);
+    if (ls != GA_OK) return ls;
     if (!ctx->prof_on && (ctx->gexec || capture_generation(ctx))) {
         for (int g = 0; g < generations; ++g) HIPCHK(hipGraphLaunch(ctx->gexec, ctx->st));
         return GA_OK;
@@ -969,7 +992,7 @@ ga_status ga_set_tile_config(ga_ctx *ctx, int32_t cfg)
     if (cfg < 0 || cfg >= mfma_num_configs()) return fail(ctx, GA_ERR_INVALID, "no such tile configuration");
     if (ctx->d.mfma_cfg != cfg) drop_graph(ctx);
     ctx->d.mfma_cfg = cfg;
-    return GA_OK;
+    return ensure_w_layout(ctx, cfg);
 }
 
 ga_status ga_evaluation_folded(ga_ctx *ctx, int32_t *folded)
@@ -1027,8 +1050,12 @@ ga_status ga_batch_set(ga_batch *b, ga_ctx *const *ctxs, int32_t count)
         else
             solo.push_back(c);
     }
-    for (ga_ctx *c : solo)
+    for (ga_ctx *c : grouped)
+        if (ensure_w_layout(c, b->cfg) != GA_OK) return fail(nullptr, GA_ERR_DEVICE, "split of W: " + c->err);
+    for (ga_ctx *c : solo) {
+        if (ensure_w_layout(c, c->d.mfma_cfg) != GA_OK) return fail(nullptr, GA_ERR_DEVICE, "split of W: " + c->err);
         if (!c->gexec && !c->prof_on) (void)capture_generation(c);
+    }
     const int njobs = (int)grouped.size();
     std::vector<const DevPtrs *> P;
     std::vector<const Dims *> D;
@@ -1115,6 +1142,7 @@ ga_status ga_batch_set(ga_batch *b, ga_ctx *const *ctxs, int32_t count)
         b->ev.push_back(ev);
     }
     b->ctxs.assign(ctxs, ctxs + count);
+    b->grouped = grouped;
     b->solo = solo;
     return GA_OK;
 }
@@ -1133,6 +1161,12 @@ ga_status ga_batch_step(ga_batch *b, int32_t generations)
     const TickJob *tjobs = (const TickJob *)((char *)b->d_tab + b->tick_off);
     const int nj = b->njobs;
     hipError_t e;
+    // a member evaluated on its own since (another tile configuration) gets
+    // the batch's layout of the W split back first
+    for (ga_ctx *c : b->grouped)
+        if (ensure_w_layout(c, b->cfg) != GA_OK) return dev_fail(hipErrorUnknown, "split of W");
+    for (ga_ctx *c : b->solo)
+        if (ensure_w_layout(c, c->d.mfma_cfg) != GA_OK) return dev_fail(hipErrorUnknown, "split of W");
     for (int g = 0; g < generations; ++g) {
         if (nsolo) {   // fork: every alone-stepped context starts after the previous generation
             if ((e = hipEventRecord(b->ev[0], b->st)) != hipSuccess) return dev_fail(e, "fork");

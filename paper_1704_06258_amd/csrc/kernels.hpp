@@ -7,6 +7,7 @@ namespace hubga {
 
 // instance preparation (prep.hip)
 hipError_t launch_prep(const DevPtrs &P, const Dims &d, hipStream_t st);
+hipError_t launch_w_layout(const DevPtrs &P, const Dims &d, int layout, hipStream_t st);
 hipError_t launch_middle_nodes(const DevPtrs &P, const Dims &d, int32_t *hubs_out, uint8_t *scratch, hipStream_t st);
 
 // nearest-hub allocation (alloc.hip)
@@ -39,6 +40,7 @@ hipError_t launch_mfma(const DevPtrs &P, const Dims &d, const uint16_t *kidx, in
 hipError_t launch_finalize(const DevPtrs &P, const Dims &d, int count, int cfg, hipStream_t st);
 int mfma_partial_tiles(const Dims &d, int cfg);
 bool mfma_folds(const Dims &d, int cfg);
+int mfma_w_layout(const Dims &d, int cfg);
 int finalize_blocks(int count);
 hipError_t launch_finalize_group(const TickJob *jobs, int njobs, int blocks, hipStream_t st);
 bool mfma_groupable(const Dims &d, int cfg);

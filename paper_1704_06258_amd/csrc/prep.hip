@@ -237,26 +237,35 @@ hipError_t launch_prep(const DevPtrs &P, const Dims &d, hipStream_t st)
         k_to_f32<<<(unsigned)((cnt + tb - 1) / tb), tb, 0, st>>>((const double *)P.Ct, P.Ct32, cnt);
     }
     k_inf_row<<<nb, tb, 0, st>>>(P.Ct32 + (size_t)n * n, n);
-    if (P.Whi) {
-        size_t cnt = (size_t)d.n_pad * d.n_pad;
-        unsigned g = (unsigned)((cnt + tb - 1) / tb);
+    return hipGetLastError();
+}
+
+// The bf16 hi/lo split of W into the context's one pair of split buffers, in
+// the layout the selected tile configuration reads: row-major, fragment
+// order, or fragment order of the folded W.
+hipError_t launch_w_layout(const DevPtrs &P, const Dims &d, int layout, hipStream_t st)
+{
+    if (!P.Whi) return hipSuccess;
+    const int n = d.n, tb = 256;
+    const size_t cnt = (size_t)d.n_pad * d.n_pad;
+    if (layout == kWRowMajor) {
+        const unsigned g = (unsigned)((cnt + tb - 1) / tb);
         if (d.w_f32)
             k_split_bf16<float><<<g, tb, 0, st>>>((const float *)P.W, n, d.n_pad, P.Whi, P.Wlo);
         else
             k_split_bf16<double><<<g, tb, 0, st>>>((const double *)P.W, n, d.n_pad, P.Whi, P.Wlo);
-        unsigned gs = (unsigned)((cnt / 8 + tb - 1) / tb);
-        if (d.w_f32)
-            k_split_bf16_swz<float><<<gs, tb, 0, st>>>((const float *)P.W, n, d.n_pad, P.Whsw, P.Wlsw);
-        else
-            k_split_bf16_swz<double><<<gs, tb, 0, st>>>((const double *)P.W, n, d.n_pad, P.Whsw, P.Wlsw);
-        if (P.Wfhsw) {
-            if (d.w_f32)
-                k_split_bf16_swz<float, true><<<gs, tb, 0, st>>>((const float *)P.W, n, d.n_pad, P.Wfhsw, P.Wflsw);
-            else
-                k_split_bf16_swz<double, true><<<gs, tb, 0, st>>>((const double *)P.W, n, d.n_pad, P.Wfhsw,
-                                                                  P.Wflsw);
-        }
+        return hipGetLastError();
     }
+    const unsigned gs = (unsigned)((cnt / 8 + tb - 1) / tb);
+    const bool fold = layout == kWFragFolded;
+    if (d.w_f32 && fold)
+        k_split_bf16_swz<float, true><<<gs, tb, 0, st>>>((const float *)P.W, n, d.n_pad, P.Whi, P.Wlo);
+    else if (d.w_f32)
+        k_split_bf16_swz<float><<<gs, tb, 0, st>>>((const float *)P.W, n, d.n_pad, P.Whi, P.Wlo);
+    else if (fold)
+        k_split_bf16_swz<double, true><<<gs, tb, 0, st>>>((const double *)P.W, n, d.n_pad, P.Whi, P.Wlo);
+    else
+        k_split_bf16_swz<double><<<gs, tb, 0, st>>>((const double *)P.W, n, d.n_pad, P.Whi, P.Wlo);
     return hipGetLastError();
 }
 

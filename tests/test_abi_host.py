@@ -54,13 +54,27 @@ def test_workspace_bytes(L):
     assert b > 2 * 8 * 1000 * 1000 + 2 * 2 * 1024 * 1024
     assert b < 80 * 2**20
     q.c_symmetric = 0
-    # an asymmetric C keeps its transpose (binary64, one row more); a symmetric
-    # one the folded W's hi/lo copies
+    # an asymmetric C keeps its transpose (binary64, one row more)
     ct_bytes = 8 * (1000 * 1000 + 1000)
-    fold_bytes = 2 * 2 * 1024 * 1024
     diff = hubga.ga_workspace_bytes(q) - b
-    assert abs(diff - (ct_bytes - fold_bytes)) < 64 * 1024, diff
+    assert abs(diff - ct_bytes) < 64 * 1024, diff
     assert hubga.ga_workspace_bytes(q, hubga.GA_DT_F32, hubga.GA_DT_F32) < hubga.ga_workspace_bytes(q)
+
+
+def test_workspace_breakdown_large_fp32_instance():
+    """n=6000, p=50, population 2048, FP32 C and W, C symmetric: C and W in
+    their dtype (C's FP32 copy is C itself), one bf16 hi/lo pair of the padded
+    W, the epilogue partials, the hub positions, the per-individual hub
+    distance tables and the re-evaluation column sums make up the workspace;
+    the rest is below 8 MB."""
+    n, p, S, n_pad = 6000, 50, 2048, 6016
+    q = hubga.make_params(n, p, chi=3, alpha=0.75, delta=2, population=S, precision="split_bf16", c_symmetric=True)
+    b = hubga.ga_workspace_bytes(q, hubga.GA_DT_F32, hubga.GA_DT_F32)
+    major = {"C": 4 * (n * n + n), "W": 4 * n * n, "W hi/lo": 2 * 2 * n_pad * n_pad,
+             "partials": 8 * (n_pad // 64) * S * p, "hub positions": 2 * S * n_pad, "column sums": 8 * 512 * n,
+             "hub distance tables": 4 * S * p * p}
+    assert 0 <= b - sum(major.values()) < 8e6, (b, sum(major.values()))
+    assert b < 600e6
 
 
 @pytest.mark.parametrize("field,value", [("n", 0), ("p", 0), ("p", 26), ("island_size", 3), ("population", 96),

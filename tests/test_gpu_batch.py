@@ -165,3 +165,26 @@ def test_many_contexts_share_the_reevaluation_pool():
         s.close()
     batch.close()
     torch.cuda.synchronize()
+
+
+def test_member_evaluated_alone_between_batch_steps():
+    """A grouped member evaluated on its own tile configuration between
+    batched generations (its W split rewritten to that configuration's layout
+    and back) keeps the trajectory of stepping alone."""
+    inst = I.uniform(seed=7, n=300, p=8)
+    kw = dict(population=512, island_size=64, n1=3, seed=4, precision="split_bf16")
+    hubs = I.random_hub_sets(9, inst.n, inst.p, 32)
+    with make(inst, **kw) as a:
+        a.step(6)
+        ref = state_of(a)
+        ref_eval = a.evaluate(hubs)["cost"]
+    batch = hubga.Batch(tile_config=16)
+    with make(inst, stream=batch.stream, **kw) as s:
+        batch.set([s])
+        batch.step(3)
+        got_eval = s.evaluate(hubs)["cost"]          # tile configuration 0: row-major split
+        batch.step(3)                                # the batch's folded split again
+        batch.synchronize()
+        assert same(state_of(s), ref)
+    batch.close()
+    assert np.array_equal(got_eval, ref_eval)
