@@ -16,6 +16,8 @@ Each wrapper names the passage of the paper it follows:
 * ``ga_children`` / ``ga_run`` -- the island GA of Sec. 4.2 and Sec. 5;
 * ``enumerate_best`` -- exhaustive search of the nearest-hub solution space,
   the optimum of Sec. 6.2's comparisons over the GA's search space;
+* ``shortest_paths`` and the ``Ctr`` argument -- multi-hop routing of the
+  inter-hub flow (eq. (4) of Sec. 3, read as routes along shortest paths).
 * ``philox`` -- Philox4x64-10 (Salmon et al., SC'11), the counter-based
   generator that both sides implement from its published definition.
 """
@@ -96,6 +98,19 @@ def _load():
         lib.oracle_ga_run.argtypes = [i32, i32, _dp, _dp, i32, i32, i32, i32, f64, f64, f64, f64, u64, i32,
                                       _ip, _dp, _dp, _ip, _dp, _dp, _lp, ct.c_void_p]
         lib.oracle_ga_run.restype = i32
+        lib.oracle_shortest_paths.argtypes = [i32, _dp, _dp]
+        lib.oracle_shortest_paths.restype = None
+        lib.oracle_cost_alloc_routed.argtypes = [i32, _dp, ct.c_void_p, _dp, _ip, f64, f64, f64, f64, _dp]
+        lib.oracle_cost_alloc_routed.restype = f64
+        lib.oracle_evaluate_routed.argtypes = [i32, i32, _dp, ct.c_void_p, _dp, i32, _ip, f64, f64, f64, f64, _dp,
+                                               ct.c_void_p, ct.c_void_p]
+        lib.oracle_evaluate_routed.restype = i32
+        lib.oracle_ga_init_routed.argtypes = [i32, i32, _dp, ct.c_void_p, _dp, i32, i32, f64, f64, f64, f64,
+                                              _ip, _dp, _dp, _ip, _dp, _dp, _lp]
+        lib.oracle_ga_init_routed.restype = i32
+        lib.oracle_ga_run_routed.argtypes = [i32, i32, _dp, ct.c_void_p, _dp, i32, i32, i32, i32, f64, f64, f64,
+                                             f64, u64, i32, _ip, _dp, _dp, _ip, _dp, _dp, _lp, ct.c_void_p]
+        lib.oracle_ga_run_routed.restype = i32
         _lib = lib
         return lib
 
@@ -151,11 +166,32 @@ def flows(W):
     return O, D
 
 
-def cost_alloc(C, W, alloc, chi, alpha, delta, scale=1.0):
-    """Cost of an arbitrary allocation (node ids); returns (cost, (Cc, T, Dd))."""
+def _tr(Ctr):
+    """(pointer, keep-alive array) of an optional transfer matrix."""
+    if Ctr is None:
+        return None, None
+    Ctr = _f64(Ctr)
+    return Ctr.ctypes.data, Ctr
+
+
+def shortest_paths(C):
+    """All-pairs shortest-path distances of C (Floyd-Warshall in binary64):
+    the transfer costs of multi-hop routing, eq. (4) of Sec. 3."""
+    C = _f64(C)
+    out = np.empty_like(C)
+    _load().oracle_shortest_paths(C.shape[0], C, out)
+    return out
+
+
+def cost_alloc(C, W, alloc, chi, alpha, delta, scale=1.0, Ctr=None):
+    """Cost of an arbitrary allocation (node ids); returns (cost, (Cc, T, Dd)).
+    Ctr: transfer matrix of the inter-hub legs (default C: direct routing;
+    ``shortest_paths(C)``: multi-hop routing)."""
     C, W = _f64(C), _f64(W)
     parts = np.zeros(3)
-    f = _load().oracle_cost_alloc(C.shape[0], C, W, _i32(alloc), chi, alpha, delta, scale, parts)
+    tp, keep = _tr(Ctr)
+    f = _load().oracle_cost_alloc_routed(C.shape[0], C, tp, W, _i32(alloc), chi, alpha, delta, scale, parts)
+    del keep
     return f, parts
 
 
@@ -186,8 +222,9 @@ def middle_nodes(C, p):
     return h
 
 
-def evaluate(C, W, hubs, chi, alpha, delta, scale=1.0, want_alloc=False):
-    """Costs of a batch of hub sets (count x p); returns (cost, parts[, alloc])."""
+def evaluate(C, W, hubs, chi, alpha, delta, scale=1.0, want_alloc=False, Ctr=None):
+    """Costs of a batch of hub sets (count x p); returns (cost, parts[, alloc]).
+    Ctr as in ``cost_alloc``."""
     C, W = _f64(C), _f64(W)
     hubs = _i32(np.atleast_2d(hubs))
     n = C.shape[0]
@@ -195,14 +232,16 @@ def evaluate(C, W, hubs, chi, alpha, delta, scale=1.0, want_alloc=False):
     cost = np.zeros(count)
     parts = np.zeros((count, 3))
     alloc = np.zeros((count, n), np.int32) if want_alloc else None
-    rc = _load().oracle_evaluate(n, p, C, W, count, hubs, chi, alpha, delta, scale, cost,
-                                 parts.ctypes.data, alloc.ctypes.data if want_alloc else None)
+    tp, keep = _tr(Ctr)
+    rc = _load().oracle_evaluate_routed(n, p, C, tp, W, count, hubs, chi, alpha, delta, scale, cost,
+                                        parts.ctypes.data, alloc.ctypes.data if want_alloc else None)
+    del keep
     if rc:
         raise ValueError("invalid hub set (out of range or repeated)")
     return (cost, parts, alloc) if want_alloc else (cost, parts)
 
 
-def enumerate_best(C, W, p, chi, alpha, delta, scale=1.0, first=0, count=None):
+def enumerate_best(C, W, p, chi, alpha, delta, scale=1.0, first=0, count=None, Ctr=None):
     """Exhaustive search of the nearest-hub solution space (the optimum the
     GA is compared with in Sec. 6.2; allocation rule of Sec. 4.1 and 5): the
     p-subsets of range(n) of lexicographic ranks [first, first + count), each
@@ -214,7 +253,7 @@ def enumerate_best(C, W, p, chi, alpha, delta, scale=1.0, first=0, count=None):
     total = math.comb(n, p)
     count = total - first if count is None else count
     sets = np.array(list(itertools.islice(itertools.combinations(range(n), p), first, first + count)), np.int32)
-    costs, _ = evaluate(C, W, sets, chi, alpha, delta, scale)
+    costs, _ = evaluate(C, W, sets, chi, alpha, delta, scale, Ctr=Ctr)
     j = int(np.argmin(costs))          # first occurrence: the lowest rank among equal costs
     return float(costs[j]), sets[j].copy(), first + j, costs
 
@@ -277,25 +316,30 @@ class GAState:
         return s
 
 
-def ga_init(C, W, p, S, m, chi, alpha, delta, scale=1.0) -> GAState:
+def ga_init(C, W, p, S, m, chi, alpha, delta, scale=1.0, Ctr=None) -> GAState:
     """Every island ancestor set to the middle-node solution P0 (Sec. 4.1, Sec. 5)."""
     C, W = _f64(C), _f64(W)
     st = GAState(S // m, p)
-    rc = _load().oracle_ga_init(C.shape[0], p, C, W, S, m, chi, alpha, delta, scale, st.anc, st.anc_cost,
-                                st.anc_parts, st.best, st.best_cost, st.best_parts, st.gen)
+    tp, keep = _tr(Ctr)
+    rc = _load().oracle_ga_init_routed(C.shape[0], p, C, tp, W, S, m, chi, alpha, delta, scale, st.anc,
+                                       st.anc_cost, st.anc_parts, st.best, st.best_cost, st.best_parts, st.gen)
+    del keep
     if rc:
         raise ValueError("invalid GA configuration")
     return st
 
 
-def ga_run(C, W, st: GAState, generations, *, S, m, n1, seed, chi, alpha, delta, scale=1.0, elitist=1):
-    """Advance the GA state by ``generations``; returns the best-cost trace."""
+def ga_run(C, W, st: GAState, generations, *, S, m, n1, seed, chi, alpha, delta, scale=1.0, elitist=1, Ctr=None):
+    """Advance the GA state by ``generations``; returns the best-cost trace.
+    Ctr as in ``cost_alloc``."""
     C, W = _f64(C), _f64(W)
     n, p = C.shape[0], st.anc.shape[1]
     trace = np.zeros(max(generations, 1))
-    rc = _load().oracle_ga_run(n, p, C, W, S, m, n1, elitist, chi, alpha, delta, scale, seed, generations,
-                               st.anc, st.anc_cost, st.anc_parts, st.best, st.best_cost, st.best_parts,
-                               st.gen, trace.ctypes.data)
+    tp, keep = _tr(Ctr)
+    rc = _load().oracle_ga_run_routed(n, p, C, tp, W, S, m, n1, elitist, chi, alpha, delta, scale, seed,
+                                      generations, st.anc, st.anc_cost, st.anc_parts, st.best, st.best_cost,
+                                      st.best_parts, st.gen, trace.ctypes.data)
+    del keep
     if rc:
         raise ValueError("invalid GA configuration")
     return trace[:generations]

@@ -24,6 +24,18 @@
  * scale is 1 (raw cost), 1/sum(W) (CAB-style fitness) or 1e-3 (AP/Urand-style
  * fitness), Sec. 4.3.
  *
+ * Multi-hop routing (the "_routed" entry points): in the MIP of Sec. 3 the
+ * variables Y_kl^i exist for every arc (k, l) and eq. (4) only conserves flow,
+ * so for fixed hubs and allocation the cheapest routing of the flow from hub
+ * a_i to hub a_j follows a shortest path of the network with arc costs C
+ * (Sec. 3: with the hubs fixed the problem is solved by a shortest-path
+ * algorithm).  The transfer term then reads C* = the all-pairs shortest-path
+ * distances of C instead of C:  t_j = sum_i W_ij*C*[a_i][a_j].  Collection
+ * and distribution keep the direct arcs C_ik of eq. (1).  C* is computed by
+ * Floyd-Warshall in binary64 (intermediate node k ascending, then i, then j
+ * ascending; a path through k replaces the entry only when strictly shorter).
+ * With a metric C, C* = C up to rounding.
+ *
  * The GA (Sec. 4 and 5) is a heuristic, so this file follows its steps in the
  * paper's order: perturbation of the island ancestor (Sec. 4.1 and 5),
  * single-point crossover of thread pairs, hub<->spoke swap mutation,
@@ -107,8 +119,8 @@ void oracle_flows(int n, const double *W, double *O, double *D)
 
 /* Cost of an arbitrary allocation a (node ids), canonical order above.
  * parts (may be NULL) receives {Cc, T, Dd}.  Returns cost = f*scale. */
-static double cost_with_flows(int n, const double *C, const double *W, const double *O, const double *D,
-                              const int *a, double chi, double alpha, double delta, double scale,
+static double cost_with_flows(int n, const double *C, const double *Ctr, const double *W, const double *O,
+                              const double *D, const int *a, double chi, double alpha, double delta, double scale,
                               double *parts)
 {
     double Cc = 0.0, Dd = 0.0, T = 0.0;
@@ -122,7 +134,7 @@ static double cost_with_flows(int n, const double *C, const double *W, const dou
     }
     for (int j = 0; j < n; ++j) {
         double tj = 0.0;
-        for (int i = 0; i < n; ++i) tj = tj + W[(size_t)i * n + j] * C[(size_t)a[i] * n + a[j]];
+        for (int i = 0; i < n; ++i) tj = tj + W[(size_t)i * n + j] * Ctr[(size_t)a[i] * n + a[j]];
         T = T + tj;
     }
     double f = ((chi * Cc) + (alpha * T)) + (delta * Dd);
@@ -134,16 +146,39 @@ static double cost_with_flows(int n, const double *C, const double *W, const dou
     return f * scale;
 }
 
-double oracle_cost_alloc(int n, const double *C, const double *W, const int *a, double chi, double alpha,
-                         double delta, double scale, double *parts)
+/* Transfer matrix Ctr (NULL: C itself, direct hub-to-hub routing). */
+double oracle_cost_alloc_routed(int n, const double *C, const double *Ctr, const double *W, const int *a, double chi,
+                                double alpha, double delta, double scale, double *parts)
 {
     double *O = (double *)malloc(sizeof(double) * (size_t)n);
     double *D = (double *)malloc(sizeof(double) * (size_t)n);
     oracle_flows(n, W, O, D);
-    double f = cost_with_flows(n, C, W, O, D, a, chi, alpha, delta, scale, parts);
+    double f = cost_with_flows(n, C, Ctr ? Ctr : C, W, O, D, a, chi, alpha, delta, scale, parts);
     free(O);
     free(D);
     return f;
+}
+
+double oracle_cost_alloc(int n, const double *C, const double *W, const int *a, double chi, double alpha,
+                         double delta, double scale, double *parts)
+{
+    return oracle_cost_alloc_routed(n, C, NULL, W, a, chi, alpha, delta, scale, parts);
+}
+
+/* All-pairs shortest-path distances of C (Floyd-Warshall, binary64): out
+ * starts as C; for k ascending, every (i, j) in ascending order takes
+ * out[i][k] + out[k][j] when that is strictly smaller. */
+void oracle_shortest_paths(int n, const double *C, double *out)
+{
+    memcpy(out, C, sizeof(double) * (size_t)n * n);
+    for (int k = 0; k < n; ++k)
+        for (int i = 0; i < n; ++i) {
+            const double dik = out[(size_t)i * n + k];
+            for (int j = 0; j < n; ++j) {
+                const double via = dik + out[(size_t)k * n + j];
+                if (via < out[(size_t)i * n + j]) out[(size_t)i * n + j] = via;
+            }
+        }
 }
 
 /* Hub-to-hub flow matrix F[k][l] = sum_i sum_j [k(i)=k][k(j)=l] W_ij, with
@@ -371,9 +406,11 @@ static void sort_ints(int *x, int c)
 /* Batch evaluation of hub sets (any order; sorted here).  cost[s] is the
  * scaled cost; parts (3 per set) and alloc (n per set) may be NULL.  Returns
  * 0, or 1 when a hub set is invalid (out of range or repeated). */
-int oracle_evaluate(int n, int p, const double *C, const double *W, int count, const int *hubs, double chi,
-                    double alpha, double delta, double scale, double *cost, double *parts, int *alloc)
+int oracle_evaluate_routed(int n, int p, const double *C, const double *Ctr, const double *W, int count,
+                           const int *hubs, double chi, double alpha, double delta, double scale, double *cost,
+                           double *parts, int *alloc)
 {
+    if (!Ctr) Ctr = C;
     double *O = (double *)malloc(sizeof(double) * (size_t)n);
     double *D = (double *)malloc(sizeof(double) * (size_t)n);
     oracle_flows(n, W, O, D);
@@ -395,7 +432,8 @@ int oracle_evaluate(int n, int p, const double *C, const double *W, int count, c
                 continue;
             }
             oracle_allocate(n, p, C, h, a, NULL);
-            cost[s] = cost_with_flows(n, C, W, O, D, a, chi, alpha, delta, scale, parts ? parts + (size_t)3 * s : NULL);
+            cost[s] = cost_with_flows(n, C, Ctr, W, O, D, a, chi, alpha, delta, scale,
+                                      parts ? parts + (size_t)3 * s : NULL);
             if (alloc) memcpy(alloc + (size_t)s * n, a, sizeof(int) * (size_t)n);
         }
         free(h);
@@ -406,13 +444,19 @@ int oracle_evaluate(int n, int p, const double *C, const double *W, int count, c
     return bad;
 }
 
+int oracle_evaluate(int n, int p, const double *C, const double *W, int count, const int *hubs, double chi,
+                    double alpha, double delta, double scale, double *cost, double *parts, int *alloc)
+{
+    return oracle_evaluate_routed(n, p, C, NULL, W, count, hubs, chi, alpha, delta, scale, cost, parts, alloc);
+}
+
 /* GA state, caller-owned arrays:
  *   anc[R*p] ancestors (sorted), anc_cost[R], anc_parts[3R],
  *   best[p], best_cost[1], best_parts[3], gen[1] (generation counter g).
  * oracle_ga_init sets every ancestor to the middle-node solution P0. */
-int oracle_ga_init(int n, int p, const double *C, const double *W, int S, int m, double chi, double alpha,
-                   double delta, double scale, int *anc, double *anc_cost, double *anc_parts, int *best,
-                   double *best_cost, double *best_parts, int64_t *gen)
+int oracle_ga_init_routed(int n, int p, const double *C, const double *Ctr, const double *W, int S, int m, double chi,
+                          double alpha, double delta, double scale, int *anc, double *anc_cost, double *anc_parts,
+                          int *best, double *best_cost, double *best_parts, int64_t *gen)
 {
     if (n < 1 || p < 1 || p > n || m < 2 || m % 2 || S < m || S % m) return 1;
     int R = S / m;
@@ -421,7 +465,7 @@ int oracle_ga_init(int n, int p, const double *C, const double *W, int S, int m,
     double parts[3];
     oracle_middle_nodes(n, p, C, h);
     oracle_allocate(n, p, C, h, a, NULL);
-    double f = oracle_cost_alloc(n, C, W, a, chi, alpha, delta, scale, parts);
+    double f = oracle_cost_alloc_routed(n, C, Ctr, W, a, chi, alpha, delta, scale, parts);
     for (int r = 0; r < R; ++r) {
         memcpy(anc + (size_t)r * p, h, sizeof(int) * (size_t)p);
         anc_cost[r] = f;
@@ -438,10 +482,10 @@ int oracle_ga_init(int n, int p, const double *C, const double *W, int S, int m,
 
 /* Run `generations` generations from the given state.  trace (may be NULL)
  * receives best_cost after each generation. */
-int oracle_ga_run(int n, int p, const double *C, const double *W, int S, int m, int n1, int elitist, double chi,
-                  double alpha, double delta, double scale, uint64_t seed, int generations, int *anc,
-                  double *anc_cost, double *anc_parts, int *best, double *best_cost, double *best_parts,
-                  int64_t *gen, double *trace)
+int oracle_ga_run_routed(int n, int p, const double *C, const double *Ctr, const double *W, int S, int m, int n1,
+                         int elitist, double chi, double alpha, double delta, double scale, uint64_t seed,
+                         int generations, int *anc, double *anc_cost, double *anc_parts, int *best,
+                         double *best_cost, double *best_parts, int64_t *gen, double *trace)
 {
     ga_cfg cf = {n, p, S, m, n1, elitist, chi, alpha, delta, scale, seed};
     if (!cfg_ok(&cf)) return 1;
@@ -452,7 +496,7 @@ int oracle_ga_run(int n, int p, const double *C, const double *W, int S, int m, 
     for (int it = 0; it < generations; ++it) {
         uint64_t g = (uint64_t)*gen;
         oracle_ga_children(n, p, S, m, seed, g, anc, children);
-        oracle_evaluate(n, p, C, W, S, children, chi, alpha, delta, scale, cost, parts, NULL);
+        oracle_evaluate_routed(n, p, C, Ctr, W, S, children, chi, alpha, delta, scale, cost, parts, NULL);
         /* island selection: argmin over the island's m children */
         for (int r = 0; r < R; ++r) {
             int js = r * m;
@@ -492,4 +536,21 @@ int oracle_ga_run(int n, int p, const double *C, const double *W, int S, int m, 
     free(cost);
     free(parts);
     return 0;
+}
+
+int oracle_ga_init(int n, int p, const double *C, const double *W, int S, int m, double chi, double alpha,
+                   double delta, double scale, int *anc, double *anc_cost, double *anc_parts, int *best,
+                   double *best_cost, double *best_parts, int64_t *gen)
+{
+    return oracle_ga_init_routed(n, p, C, NULL, W, S, m, chi, alpha, delta, scale, anc, anc_cost, anc_parts, best,
+                                 best_cost, best_parts, gen);
+}
+
+int oracle_ga_run(int n, int p, const double *C, const double *W, int S, int m, int n1, int elitist, double chi,
+                  double alpha, double delta, double scale, uint64_t seed, int generations, int *anc,
+                  double *anc_cost, double *anc_parts, int *best, double *best_cost, double *best_parts,
+                  int64_t *gen, double *trace)
+{
+    return oracle_ga_run_routed(n, p, C, NULL, W, S, m, n1, elitist, chi, alpha, delta, scale, seed, generations,
+                                anc, anc_cost, anc_parts, best, best_cost, best_parts, gen, trace);
 }

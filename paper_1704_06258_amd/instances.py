@@ -18,6 +18,10 @@ synthetic stand-ins with the same shapes, sizes and factor values:
   (a seeded choice) scaled by 100 in FP32.
 * ``serving``  n in {50,100,200,500,1000,2000}, p in {3,5,10,20},
   population in {256,512,1024,2048}, uniform coordinates, lognormal flows.
+* ``nonmetric`` (PlanetLab-like, Sec. 6.1: delays that break the triangle
+  inequality, chi = alpha = delta = 1): Euclidean distances of uniform
+  coordinates, each pair scaled by a symmetric lognormal factor exp(0.6 Z),
+  zero diagonal; lognormal flows.
 
 Every generator uses ``numpy.random.Generator(Philox(seed))``; the distance
 matrix is exactly symmetric with a zero diagonal.
@@ -113,6 +117,19 @@ def uniform(seed: int, n: int, p: int, chi=3.0, alpha=0.75, delta=2.0) -> Instan
     rng = _rng(seed)
     xy = rng.uniform(0.0, 10000.0, size=(n, 2))
     return Instance("uniform", euclidean(xy), lognormal_flows(rng, n), p, chi, alpha, delta)
+
+
+def nonmetric(seed: int = 6, n: int = 300, p: int = 10, spread: float = 0.6) -> Instance:
+    """Symmetric distances that violate the triangle inequality (Sec. 6.1,
+    PlanetLab-like), chi = alpha = delta = 1."""
+    rng = _rng(seed)
+    xy = rng.uniform(0.0, 10000.0, size=(n, 2))
+    z = rng.standard_normal((n, n))
+    z = np.triu(z, 1)
+    z = z + z.T
+    C = euclidean(xy) * np.exp(spread * z)
+    np.fill_diagonal(C, 0.0)
+    return Instance("nonmetric", C, lognormal_flows(rng, n), p, 1.0, 1.0, 1.0)
 
 
 def random_asymmetric(seed: int, n: int, p: int, chi=2.0, alpha=0.6, delta=1.5, integer=False) -> Instance:
