@@ -91,11 +91,18 @@ typedef struct {
     int32_t precision;    /* ga_precision */
     int32_t kernel;       /* ga_kernel: PLAIN with FP64/FP32, BATCHED with SPLIT_BF16 */
     int32_t c_symmetric;  /* 1: C == C^T (checked by ga_init); 0: a transposed copy is kept */
+    int32_t multihop;     /* 0: inter-hub flow goes directly hub -> hub (C[h_k][h_l]);
+                           * 1: along shortest paths of the network (eq. (4) of Sec. 3 lets
+                           *    flow use every arc): the transfer term reads the all-pairs
+                           *    shortest-path distances C* of C (Floyd-Warshall in binary64
+                           *    at ga_init, O(n^3)), collection and distribution keep C.
+                           *    Differs from 0 only when C breaks the triangle inequality
+                           *    (the PlanetLab setting of Sec. 6.1). */
 } ga_params;
 
 /* Fill p with defaults for n nodes and p hubs: chi=3, alpha=0.75, delta=2,
  * scale=1, seed=1, population 64, island 64, n1=10, elitist, FP64 plain,
- * c_symmetric=0. */
+ * c_symmetric=0, multihop=0. */
 void ga_params_default(ga_params *p, int32_t n, int32_t hubs);
 
 /* Device workspace bytes ga_init needs for these parameters and dtypes; 0 if

@@ -8,7 +8,8 @@
 // up to n_pad), the largest cluster size, and (when asked) the collection and
 // distribution sums Cc = sum_i O_i c_i, Dd = sum_i D_i c_i with c_i =
 // C[i][a_i] in binary64 (a fixed summation order), and the FP32 hub-to-hub table
-// Ch32[s][k][l] = C[h_k][h_l] used by the batched kernel's epilogue.
+// Ch32[s][k][l] = C[h_k][h_l] used by the batched kernel's epilogue (the
+// shortest-path distance Ctr[h_k][h_l] instead under multi-hop routing).
 #include "kernels.hpp"
 
 namespace hubga {
@@ -29,7 +30,7 @@ __device__ __forceinline__ void alloc_body(const int32_t *__restrict__ hubs, int
                                            const double *__restrict__ O, const double *__restrict__ D,
                                            uint16_t *__restrict__ kidx, double *__restrict__ parts,
                                            int32_t *__restrict__ cmax, float *__restrict__ Ch32, int want_sums,
-                                           int blk)
+                                           const double *__restrict__ Ctr, int blk)
 {
 #pragma clang fp contract(off)
     constexpr int T = kScanNodes, H = kScanHubs;
@@ -64,7 +65,9 @@ __device__ __forceinline__ void alloc_body(const int32_t *__restrict__ hubs, int
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const int e = tid + q * 256;
-            chv[q] = e < p * p ? (float)Ct[(size_t)sh_h[e % p] * n + sh_h[e / p]] : 0.0f;
+            chv[q] = e >= p * p ? 0.0f
+                     : Ctr ? (float)Ctr[(size_t)sh_h[e / p] * n + sh_h[e % p]]
+                           : (float)Ct[(size_t)sh_h[e % p] * n + sh_h[e / p]];
         }
     }
     double pc = 0.0, pd = 0.0;
@@ -180,7 +183,8 @@ __device__ __forceinline__ void alloc_body(const int32_t *__restrict__ hubs, int
             if (e < p * p) Ch32[(size_t)s * p * p + e] = chv[q];
         }
         for (int e = tid + 512; e < p * p; e += 256)
-            Ch32[(size_t)s * p * p + e] = (float)Ct[(size_t)sh_h[e % p] * n + sh_h[e / p]];
+            Ch32[(size_t)s * p * p + e] = Ctr ? (float)Ctr[(size_t)sh_h[e / p] * n + sh_h[e % p]]
+                                              : (float)Ct[(size_t)sh_h[e % p] * n + sh_h[e / p]];
     }
     // Cc and Dd: each wave's lanes merged by halving distance, then the four
     // waves in order (a fixed order)
@@ -230,9 +234,10 @@ __global__ __launch_bounds__(256, 8) void k_alloc(const int32_t *__restrict__ hu
                                                const CT *__restrict__ Ct, const float *__restrict__ Ct32,
                                                const double *__restrict__ O, const double *__restrict__ D,
                                                uint16_t *__restrict__ kidx, double *__restrict__ parts,
-                                               int32_t *__restrict__ cmax, float *__restrict__ Ch32, int want_sums)
+                                               int32_t *__restrict__ cmax, float *__restrict__ Ch32, int want_sums,
+                                               const double *__restrict__ Ctr)
 {
-    alloc_body<CT>(hubs, count, n, n_pad, p, Ct, Ct32, O, D, kidx, parts, cmax, Ch32, want_sums, blockIdx.x);
+    alloc_body<CT>(hubs, count, n, n_pad, p, Ct, Ct32, O, D, kidx, parts, cmax, Ch32, want_sums, Ctr, blockIdx.x);
 }
 
 // Grouped: the children of every context, with their sums and hub tables
@@ -245,10 +250,10 @@ __global__ __launch_bounds__(256, 8) void k_alloc_group(const TickJob *__restric
     const Dims &d = J.d;
     if (d.c_f32)
         alloc_body<float>(P.hubs, d.S, d.n, d.n_pad, d.p, (const float *)P.Ct, P.Ct32, P.O, P.D, P.kidx, P.parts,
-                          P.cmax, P.Ch32, 1, blk);
+                          P.cmax, P.Ch32, 1, P.Ctr, blk);
     else
         alloc_body<double>(P.hubs, d.S, d.n, d.n_pad, d.p, (const double *)P.Ct, P.Ct32, P.O, P.D, P.kidx,
-                           P.parts, P.cmax, P.Ch32, 1, blk);
+                           P.parts, P.cmax, P.Ch32, 1, P.Ctr, blk);
 }
 
 int alloc_blocks(int count) { return ((count + 7) / 8) * 8; }
@@ -261,10 +266,10 @@ hipError_t launch_alloc(const DevPtrs &P, const Dims &d, const int32_t *hubs, in
     const unsigned grid = (unsigned)alloc_blocks(count);
     if (d.c_f32)
         k_alloc<float><<<grid, 256, 0, st>>>(hubs, count, d.n, d.n_pad, d.p, (const float *)P.Ct, P.Ct32, P.O, P.D,
-                                             kidx, P.parts, P.cmax, ch, want_sums);
+                                             kidx, P.parts, P.cmax, ch, want_sums, P.Ctr);
     else
         k_alloc<double><<<grid, 256, 0, st>>>(hubs, count, d.n, d.n_pad, d.p, (const double *)P.Ct, P.Ct32, P.O,
-                                              P.D, kidx, P.parts, P.cmax, ch, want_sums);
+                                              P.D, kidx, P.parts, P.cmax, ch, want_sums, P.Ctr);
     return hipGetLastError();
 }
 

@@ -32,6 +32,8 @@ struct DevPtrs {
     void *Ct;           // n*n transposed (== C when C is symmetric): hub rows for allocation
     float *Ct32;        // Ct rounded to FP32 (== Ct for an FP32 instance)
     void *W;            // n*n, instance dtype
+    double *Ctr;        // n*n all-pairs shortest-path distances of C (multi-hop routing), else null:
+                        //   the transfer term's C[h_k][h_l] is read from here when set
     float *W32;         // n*n FP32 copy (FP32 mode with a binary64 instance), else null
     // The bf16 hi/lo split of W: n_pad*n_pad bf16 bits each (split mode), else
     // null.  One pair of buffers holds the layout the current tile
@@ -89,6 +91,7 @@ struct Dims {
     int mfma_cfg;       // tile configuration of the batched kernel
     int c_f32, w_f32;   // instance dtypes (1 = FP32)
     int sym;            // C == C^T: the batched K-64 configurations use the folded W
+    int multihop;       // transfer term through the shortest-path distances Ctr
     double chi, alpha, delta, scale;
     uint64_t seed;
 };

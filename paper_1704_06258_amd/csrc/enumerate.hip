@@ -131,7 +131,8 @@ template <typename CT, typename WT>
 __global__ __launch_bounds__(256) void k_enum_exact(const int32_t *__restrict__ hubs, const uint16_t *__restrict__ kidx,
                                                     const int32_t *__restrict__ cand, const EnumState *st, int n,
                                                     int n_pad, int p, const CT *__restrict__ C,
-                                                    const WT *__restrict__ W, const double *__restrict__ O,
+                                                    const double *__restrict__ Ctr, const WT *__restrict__ W,
+                                                    const double *__restrict__ O,
                                                     const double *__restrict__ D, double chi, double alpha,
                                                     double delta, double scale, double *__restrict__ cand_cost,
                                                     double *__restrict__ cand_parts)
@@ -140,8 +141,8 @@ __global__ __launch_bounds__(256) void k_enum_exact(const int32_t *__restrict__ 
     const int cnt = st->cand_count;
     for (int c = blockIdx.x; c < cnt; c += gridDim.x) {
         const int s = cand[c];
-        eval_exact_body<CT, WT>(hubs + (size_t)s * p, kidx + (size_t)s * n_pad, n, p, C, W, O, D, chi, alpha, delta,
-                                scale, cand_cost + c, cand_parts + 3 * (size_t)c, smem);
+        eval_exact_body<CT, WT>(hubs + (size_t)s * p, kidx + (size_t)s * n_pad, n, p, C, Ctr, W, O, D, chi, alpha,
+                                delta, scale, cand_cost + c, cand_parts + 3 * (size_t)c, smem);
         __syncthreads();   // the LDS is reused by the next entry
     }
 }
@@ -167,7 +168,8 @@ template <typename CT, typename WT>
 static hipError_t enum_exact_launch(const DevPtrs &P, const Dims &d, hipStream_t st)
 {
     k_enum_exact<CT, WT><<<kEnumExactBlocks, 256, exact_smem_bytes(d.n, d.p), st>>>(
-        P.hubs, P.kidx, P.cand, P.enum_state, d.n, d.n_pad, d.p, (const CT *)P.C, (const WT *)P.W, P.O, P.D, d.chi,
+        P.hubs, P.kidx, P.cand, P.enum_state, d.n, d.n_pad, d.p, (const CT *)P.C, P.Ctr, (const WT *)P.W, P.O, P.D,
+        d.chi,
         d.alpha, d.delta, d.scale, P.cand_cost, P.cand_parts);
     return hipGetLastError();
 }

@@ -18,7 +18,8 @@ namespace hubga {
 template <typename CT, typename WT>
 __global__ __launch_bounds__(256) void k_eval_exact(const int32_t *__restrict__ hubs,
                                                     const uint16_t *__restrict__ kidx, int count, int n, int n_pad,
-                                                    int p, const CT *__restrict__ C, const WT *__restrict__ W,
+                                                    int p, const CT *__restrict__ C, const double *__restrict__ Ctr,
+                                                    const WT *__restrict__ W,
                                                     const double *__restrict__ O, const double *__restrict__ D,
                                                     double chi, double alpha, double delta, double scale,
                                                     double *__restrict__ cost, double *__restrict__ parts,
@@ -27,8 +28,8 @@ __global__ __launch_bounds__(256) void k_eval_exact(const int32_t *__restrict__ 
     extern __shared__ __align__(16) char smem[];
     const int s = blockIdx.x;
     if (s >= count) return;
-    eval_exact_body<CT, WT>(hubs + (size_t)s * p, kidx + (size_t)s * n_pad, n, p, C, W, O, D, chi, alpha, delta,
-                            scale, cost + s, parts + 3 * (size_t)s, smem);
+    eval_exact_body<CT, WT>(hubs + (size_t)s * p, kidx + (size_t)s * n_pad, n, p, C, Ctr, W, O, D, chi, alpha,
+                            delta, scale, cost + s, parts + 3 * (size_t)s, smem);
     if (threadIdx.x == 0 && eps) eps[s] = 0.0;
 }
 
@@ -37,7 +38,8 @@ __global__ __launch_bounds__(256) void k_eval_exact(const int32_t *__restrict__ 
 template <typename CT>
 __global__ __launch_bounds__(256) void k_eval_fp32(const int32_t *__restrict__ hubs, const uint16_t *__restrict__ kidx,
                                                    int count, int n, int n_pad, int p, const CT *__restrict__ Ct,
-                                                   const float *__restrict__ W, double chi, double alpha,
+                                                   const double *__restrict__ Ctr, const float *__restrict__ W,
+                                                   double chi, double alpha,
                                                    double delta, double scale, double eps_bound,
                                                    double *__restrict__ cost, double *__restrict__ parts,
                                                    double *__restrict__ eps)
@@ -55,7 +57,8 @@ __global__ __launch_bounds__(256) void k_eval_fp32(const int32_t *__restrict__ h
     if (tid < p) h[tid] = hubs[(size_t)s * p + tid];
     for (int i = tid; i < n; i += nt) kid[i] = krow[i];
     __syncthreads();
-    for (int e = tid; e < p * p; e += nt) Ch[e] = (float)Ct[(size_t)h[e % p] * n + h[e / p]];
+    for (int e = tid; e < p * p; e += nt)
+        Ch[e] = Ctr ? (float)Ctr[(size_t)h[e / p] * n + h[e % p]] : (float)Ct[(size_t)h[e % p] * n + h[e / p]];
     __syncthreads();
     double tsum = 0.0;
     constexpr int RU = 8;   // rows whose W loads are in flight together, as in the binary64 kernel
@@ -122,7 +125,7 @@ static hipError_t exact_launch(const DevPtrs &P, const Dims &d, const int32_t *h
 {
     size_t sm = exact_smem_bytes(d.n, d.p);
     k_eval_exact<CT, WT><<<count, eval_block(d.n), sm, st>>>(hubs, kidx, count, d.n, d.n_pad, d.p, (const CT *)P.C,
-                                                             (const WT *)P.W, P.O, P.D, d.chi, d.alpha, d.delta,
+                                                             P.Ctr, (const WT *)P.W, P.O, P.D, d.chi, d.alpha, d.delta,
                                                              d.scale, cost, parts, eps);
     return hipGetLastError();
 }
@@ -151,11 +154,11 @@ hipError_t launch_eval_fp32(const DevPtrs &P, const Dims &d, const int32_t *hubs
     double eb = fp32_eps_bound(d.n);
     if (d.c_f32) {
         k_eval_fp32<float><<<count, eval_block(d.n), sm, st>>>(hubs, kidx, count, d.n, d.n_pad, d.p,
-                                                                (const float *)P.Ct, W, d.chi, d.alpha, d.delta,
+                                                                (const float *)P.Ct, P.Ctr, W, d.chi, d.alpha, d.delta,
                                                                 d.scale, eb, P.cost, P.parts, P.eps);
     } else {
         k_eval_fp32<double><<<count, eval_block(d.n), sm, st>>>(hubs, kidx, count, d.n, d.n_pad, d.p,
-                                                                 (const double *)P.Ct, W, d.chi, d.alpha, d.delta,
+                                                                 (const double *)P.Ct, P.Ctr, W, d.chi, d.alpha, d.delta,
                                                                  d.scale, eb, P.cost, P.parts, P.eps);
     }
     return hipGetLastError();

@@ -33,11 +33,13 @@ __device__ inline double seq_sum(const double *buf, int n)
 }
 
 // RU: rows whose W loads are in flight together (registers: 8*RU per lane).
+// Ctr (may be null): the transfer term's distances (multi-hop routing); C
+// itself when null.
 template <typename CT, typename WT, int RU = 8>
 __device__ void eval_exact_body(const int32_t *__restrict__ hg, const uint16_t *__restrict__ krow, int n, int p,
-                                const CT *__restrict__ C, const WT *__restrict__ W, const double *__restrict__ O,
-                                const double *__restrict__ D, double chi, double alpha, double delta, double scale,
-                                double *cost_out, double *parts_out, char *smem)
+                                const CT *__restrict__ C, const double *__restrict__ Ctr, const WT *__restrict__ W,
+                                const double *__restrict__ O, const double *__restrict__ D, double chi, double alpha,
+                                double delta, double scale, double *cost_out, double *parts_out, char *smem)
 {
 #pragma clang fp contract(off)
     double *Ch = (double *)smem;
@@ -48,7 +50,8 @@ __device__ void eval_exact_body(const int32_t *__restrict__ hg, const uint16_t *
     if (tid < p) h[tid] = hg[tid];
     for (int i = tid; i < n; i += nt) kid[i] = krow[i];
     __syncthreads();
-    for (int e = tid; e < p * p; e += nt) Ch[e] = (double)C[(size_t)h[e / p] * n + h[e % p]];
+    for (int e = tid; e < p * p; e += nt)
+        Ch[e] = Ctr ? Ctr[(size_t)h[e / p] * n + h[e % p]] : (double)C[(size_t)h[e / p] * n + h[e % p]];
     __syncthreads();
     // t_j = sum over ascending i of W_ij * C[a_i][a_j], four columns per lane at a time
     for (int j0 = tid; j0 < n; j0 += 4 * nt) {

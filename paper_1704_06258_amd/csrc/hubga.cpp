@@ -55,6 +55,7 @@ std::string check_params(const ga_params *q)
     if (q->n1 < 1) return "n1 must be >= 1";
     if (q->elitist != 0 && q->elitist != 1) return "elitist must be 0 or 1";
     if (q->c_symmetric != 0 && q->c_symmetric != 1) return "c_symmetric must be 0 or 1";
+    if (q->multihop != 0 && q->multihop != 1) return "multihop must be 0 or 1";
     if (!is_valid_combo(q->precision, q->kernel))
         return "precision/kernel must be FP64+PLAIN, FP32+PLAIN or SPLIT_BF16+BATCHED";
     return "";
@@ -79,6 +80,7 @@ Dims make_dims(const ga_params *q, ga_dtype cdt, ga_dtype wdt)
     d.prec = q->precision;
     d.c_f32 = cdt == GA_DT_F32;
     d.sym = q->c_symmetric;
+    d.multihop = q->multihop;
     d.w_f32 = wdt == GA_DT_F32;
     d.chi = q->chi;
     d.alpha = q->alpha;
@@ -90,7 +92,7 @@ Dims make_dims(const ga_params *q, ga_dtype cdt, ga_dtype wdt)
 
 // Offsets of every device buffer; the same walk sizes and carves.
 struct Carve {
-    size_t C, Ct, Ct32, W, W32, Whi, Wlo, O, D, dsum, hubs, kidx, cost, parts, eps, cmax, Ch32, partial, anc, anc_cost,
+    size_t C, Ct, Ct32, W, W32, Ctr, Whi, Wlo, O, D, dsum, hubs, kidx, cost, parts, eps, cmax, Ch32, partial, anc, anc_cost,
         anc_parts, best, best_cost, gen, stats, cand, cand_cnt, cand_cost, cand_parts, kidx_one, scratch, tbuf, slot_r, slot_c, slot_s, slot_done, handled, choice, total_slots, extra_r, extra_c, nextra, sync,
         enum_state, enum_best, binom;
     size_t total;
@@ -110,6 +112,7 @@ Carve carve(const Dims &d, int c_symmetric)
     c.Ct32 = d.c_f32 ? c.Ct : L.take((n2 + d.n) * 4);
     c.W = L.take(n2 * ws);
     c.W32 = (d.prec == kFP32 && !d.w_f32) ? L.take(n2 * 4) : (size_t)-1;
+    c.Ctr = d.multihop ? L.take(n2 * 8) : (size_t)-1;
     // one pair of split buffers, in the layout the current tile configuration reads
     c.Whi = split ? L.take(np2 * 2) : (size_t)-1;
     c.Wlo = split ? L.take(np2 * 2) : (size_t)-1;
@@ -423,6 +426,7 @@ void ga_params_default(ga_params *q, int32_t n, int32_t hubs)
     q->precision = GA_PREC_FP64;
     q->kernel = GA_KERN_PLAIN;
     q->c_symmetric = 0;
+    q->multihop = 0;
 }
 
 size_t ga_workspace_bytes(const ga_params *q, ga_dtype cdt, ga_dtype wdt)
@@ -533,6 +537,7 @@ static ga_status init_ctx(const ga_params *q, const void *C, ga_dtype cdt, const
         P.Ct32 = at<float>(b, c.Ct32);
         P.W = at<void>(b, c.W);
         P.W32 = at<float>(b, c.W32);
+        P.Ctr = at<double>(b, c.Ctr);
         P.Whi = at<uint16_t>(b, c.Whi);
         P.Wlo = at<uint16_t>(b, c.Wlo);
         P.Whsw = P.Wfhsw = P.Whi;
@@ -589,6 +594,7 @@ static ga_status init_ctx(const ga_params *q, const void *C, ga_dtype cdt, const
         if ((he = hipMemcpyAsync(P.W, W, n2 * (d.w_f32 ? 4 : 8), hipMemcpyHostToDevice, ctx->st)) != hipSuccess)
             return dev_fail(he, "copy W");
         if ((he = launch_prep(P, d, ctx->st)) != hipSuccess) return dev_fail(he, "prep");
+        if ((he = launch_shortest_paths(P, d, ctx->st)) != hipSuccess) return dev_fail(he, "shortest paths");
         if (d.prec == kSplitBF16) {
             if ((he = launch_w_layout(P, d, mfma_w_layout(d, d.mfma_cfg), ctx->st)) != hipSuccess)
                 return dev_fail(he, "split of W");

@@ -8,6 +8,7 @@ namespace hubga {
 // instance preparation (prep.hip)
 hipError_t launch_prep(const DevPtrs &P, const Dims &d, hipStream_t st);
 hipError_t launch_w_layout(const DevPtrs &P, const Dims &d, int layout, hipStream_t st);
+hipError_t launch_shortest_paths(const DevPtrs &P, const Dims &d, hipStream_t st);
 hipError_t launch_middle_nodes(const DevPtrs &P, const Dims &d, int32_t *hubs_out, uint8_t *scratch, hipStream_t st);
 
 // nearest-hub allocation (alloc.hip)

@@ -202,6 +202,45 @@ __global__ void k_inf_row(float *__restrict__ row, int n)
     if (t < n) row[t] = __builtin_huge_valf();
 }
 
+// Multi-hop routing (eq. (4) of Sec. 3 lets inter-hub flow use every arc):
+// the transfer term reads the all-pairs shortest-path distances of C,
+// Floyd-Warshall in binary64.  One launch per intermediate node k updates
+// every entry: out[i][j] takes out[i][k] + out[k][j] when strictly smaller.
+// Row k and column k cannot change during step k (out[k][k] >= 0 and adding a
+// non-negative number never decreases a binary64 sum), so the entries read in
+// step k are those of the sequential algorithm and the result is its result
+// bit for bit.
+template <typename T>
+__global__ void k_to_f64(const T *__restrict__ src, double *__restrict__ dst, size_t count)
+{
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < count) dst[idx] = (double)src[idx];
+}
+
+__global__ void k_fw_step(double *__restrict__ D, int n, int k)
+{
+#pragma clang fp contract(off)
+    const int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
+    if (j >= n) return;
+    const double via = D[(size_t)i * n + k] + D[(size_t)k * n + j];
+    if (via < D[(size_t)i * n + j]) D[(size_t)i * n + j] = via;
+}
+
+hipError_t launch_shortest_paths(const DevPtrs &P, const Dims &d, hipStream_t st)
+{
+    if (!P.Ctr) return hipSuccess;
+    const int n = d.n, tb = 256;
+    const size_t cnt = (size_t)n * n;
+    const unsigned g = (unsigned)((cnt + tb - 1) / tb);
+    if (d.c_f32)
+        k_to_f64<float><<<g, tb, 0, st>>>((const float *)P.C, P.Ctr, cnt);
+    else
+        k_to_f64<double><<<g, tb, 0, st>>>((const double *)P.C, P.Ctr, cnt);
+    const dim3 grid((n + tb - 1) / tb, n);
+    for (int k = 0; k < n; ++k) k_fw_step<<<grid, tb, 0, st>>>(P.Ctr, n, k);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------ launchers --
 
 hipError_t launch_prep(const DevPtrs &P, const Dims &d, hipStream_t st)

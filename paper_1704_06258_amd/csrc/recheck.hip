@@ -213,7 +213,8 @@ __device__ __forceinline__ void rc_column_item(const DevPtrs &P, const Dims &d, 
     rc_stage_candidate(d, V, P.slot_s[slot], L, sh_h);
     for (int e = tid; e < (p + 1) * kRcCols; e += kRcThreads) {   // chT[k][c] = C[h_k][a_j], j = j0 + c; row p zero
         const int k = e / kRcCols, jj = j0 + e % kRcCols < n ? j0 + e % kRcCols : n - 1;
-        L.chT[e] = k < p ? (double)((const CT *)P.C)[(size_t)sh_h[k] * n + sh_h[L.kid[jj]]] : 0.0;
+        const size_t at = (size_t)sh_h[k < p ? k : 0] * n + sh_h[L.kid[jj]];
+        L.chT[e] = k < p ? (P.Ctr ? P.Ctr[at] : (double)((const CT *)P.C)[at]) : 0.0;
     }
     lds_wait();
     wg_barrier();
@@ -402,7 +403,7 @@ __device__ __forceinline__ void rc_extra(const DevPtrs &P, const Dims &d, const 
     const size_t o = (size_t)r * V.m + c;
     __syncthreads();   // LDS of the previous item free
     eval_exact_body<CT, WT, 2>(V.children + (size_t)s * d.p, V.kidx + (size_t)s * d.n_pad, d.n, d.p, (const CT *)P.C,
-                            (const WT *)P.W, P.O, P.D, d.chi, d.alpha, d.delta, d.scale, V.cost_out + o,
+                            P.Ctr, (const WT *)P.W, P.O, P.D, d.chi, d.alpha, d.delta, d.scale, V.cost_out + o,
                             V.parts_out + 3 * o, smem);
 }
 

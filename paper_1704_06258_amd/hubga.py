@@ -37,7 +37,7 @@ class ga_params(ct.Structure):
                 ("delta", ct.c_double), ("scale", ct.c_double), ("seed", ct.c_uint64),
                 ("population", ct.c_int32), ("island_size", ct.c_int32), ("n1", ct.c_int32),
                 ("elitist", ct.c_int32), ("precision", ct.c_int32), ("kernel", ct.c_int32),
-                ("c_symmetric", ct.c_int32)]
+                ("c_symmetric", ct.c_int32), ("multihop", ct.c_int32)]
 
 
 class HubGAError(RuntimeError):
@@ -152,7 +152,7 @@ def ga_workspace_bytes(params: ga_params, c_dtype=GA_DT_F64, w_dtype=GA_DT_F64) 
 
 
 def make_params(n, p, *, chi, alpha, delta, scale=1.0, seed=1, population=64, island_size=None, n1=10,
-                elitist=True, precision="fp64", kernel=None, c_symmetric=False) -> ga_params:
+                elitist=True, precision="fp64", kernel=None, c_symmetric=False, multihop=False) -> ga_params:
     q = ga_params_default(n, p)
     q.chi, q.alpha, q.delta, q.scale, q.seed = chi, alpha, delta, scale, seed
     q.population = population
@@ -161,6 +161,7 @@ def make_params(n, p, *, chi, alpha, delta, scale=1.0, seed=1, population=64, is
     q.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     q.kernel = DEFAULT_KERNEL[q.precision] if kernel is None else int(kernel)
     q.c_symmetric = int(bool(c_symmetric))
+    q.multihop = int(bool(multihop))
     return q
 
 
@@ -177,7 +178,7 @@ class Solver:
 
     def __init__(self, C, W, p, *, chi, alpha, delta, scale=1.0, seed=1, population=64, island_size=None, n1=10,
                  elitist=True, precision="fp64", kernel=None, stream=None, device=0, c_symmetric=None,
-                 static_workspace=False):
+                 static_workspace=False, multihop=False):
         """``static_workspace``: build the context with ga_init_static on the
         library's per-device static workspace (no device allocation) instead
         of ga_init on a torch-allocated one."""
@@ -191,7 +192,7 @@ class Solver:
         sym = bool(np.array_equal(C, C.T)) if c_symmetric is None else bool(c_symmetric)
         self.params = make_params(n, p, chi=chi, alpha=alpha, delta=delta, scale=scale, seed=seed,
                                   population=population, island_size=island_size, n1=n1, elitist=elitist,
-                                  precision=precision, kernel=kernel, c_symmetric=sym)
+                                  precision=precision, kernel=kernel, c_symmetric=sym, multihop=multihop)
         self.S = self.params.population
         self.R = self.S // self.params.island_size
         cdt, wdt = _dtype_code(C), _dtype_code(W)

@@ -39,8 +39,8 @@ def test_library_exports_every_declared_symbol(L):
 
 
 def test_params_struct_layout_matches_header():
-    # int32 n, p; 4 doubles; uint64 seed; 7 int32 -> 80 bytes with natural alignment
-    assert ct.sizeof(hubga.ga_params) == 4 * 2 + 8 * 4 + 8 + 4 * 7 + 4
+    # int32 n, p; 4 doubles; uint64 seed; 8 int32 -> 80 bytes with natural alignment
+    assert ct.sizeof(hubga.ga_params) == 4 * 2 + 8 * 4 + 8 + 4 * 8
     q = hubga.ga_params_default(25, 3)
     assert (q.n, q.p, q.population, q.island_size, q.n1, q.elitist) == (25, 3, 64, 64, 10, 1)
     assert (q.chi, q.alpha, q.delta, q.scale, q.seed) == (3.0, 0.75, 2.0, 1.0, 1)
@@ -79,7 +79,7 @@ def test_workspace_breakdown_large_fp32_instance():
 
 @pytest.mark.parametrize("field,value", [("n", 0), ("p", 0), ("p", 26), ("island_size", 3), ("population", 96),
                                          ("n1", 0), ("elitist", 2), ("chi", -1.0), ("scale", 0.0),
-                                         ("alpha", float("nan")), ("precision", 7)])
+                                         ("alpha", float("nan")), ("precision", 7), ("multihop", 2)])
 def test_invalid_params_rejected_on_host(L, field, value):
     q = hubga.make_params(25, 3, chi=1, alpha=0.75, delta=1, population=64)
     setattr(q, field, value)
