@@ -337,17 +337,20 @@ def main():
         # the same generations as the batched leg's timed window
         plain = {}
         steps = args.steps if N <= 2000 else min(args.steps, 3)
-        for prec in ("fp64", "fp32"):
-            s2 = hubga.Solver(inst.C, inst.W, inst.p, precision=prec, **kw)
+        # plain per-individual kernels (FP64, FP32) and the batched FP32 vector kernel
+        for name, prec, kern in (("fp64", "fp64", "plain"), ("fp32", "fp32", "plain"),
+                                 ("fp32_vector_batched", "fp32", "batched")):
+            s2 = hubga.Solver(inst.C, inst.W, inst.p, precision=prec, kernel=kern, **kw)
             dt2, kms2, l2 = time_steps(s2, steps, pre + args.warmup, kernel_steps=3)
             s2.close()
-            plain[prec] = {"evals_per_s": S * steps / dt2, "ms_per_step": 1e3 * dt2 / steps,
+            plain[name] = {"evals_per_s": S * steps / dt2, "ms_per_step": 1e3 * dt2 / steps,
                            "kernel_avg_ms": kms2 / max(l2, 1),
                            "timed_generations": [pre + args.warmup, pre + args.warmup + steps - 1]}
-            log(f"plain {prec}: {1e3 * dt2 / steps:.3f} ms per generation")
+            log(f"{name}: {1e3 * dt2 / steps:.3f} ms per generation, kernel {kms2 / max(l2, 1):.3f} ms")
         out["plain"] = plain
         out["speedup_vs_plain_fp64"] = value / plain["fp64"]["evals_per_s"]
         out["speedup_vs_plain_fp32"] = value / plain["fp32"]["evals_per_s"]
+        out["speedup_vs_fp32_vector_batched"] = value / plain["fp32_vector_batched"]["evals_per_s"]
 
     if not args.no_enumerate and args.workload == "clustered":
         out["enumeration"] = enumeration_leg()

@@ -73,7 +73,11 @@ typedef enum { GA_DT_F64 = 0, GA_DT_F32 = 1 } ga_dtype;
 typedef enum { GA_PREC_FP64 = 0, GA_PREC_FP32 = 1, GA_PREC_SPLIT_BF16 = 2 } ga_precision;
 
 /* GA_KERN_PLAIN: one workgroup per individual (FP64 or FP32).
- * GA_KERN_BATCHED: the whole population as one matrix-core GEMM (SPLIT_BF16). */
+ * GA_KERN_BATCHED: the whole population in one launch -- with SPLIT_BF16 the
+ * one-hot matrix-core product; with FP32 a vector kernel in which a workgroup
+ * applies each W element it loads to a group of individuals, gathering their
+ * hub-to-hub distances from LDS (n^2 multiply-adds per individual whatever p
+ * is; the same error bound as FP32 + PLAIN). */
 typedef enum { GA_KERN_PLAIN = 0, GA_KERN_BATCHED = 1 } ga_kernel;
 
 typedef struct {
@@ -89,7 +93,7 @@ typedef struct {
     int32_t n1;           /* generations per outer step (global argmin every n1), >= 1 */
     int32_t elitist;      /* 1: an island ancestor is replaced only by a strictly better child */
     int32_t precision;    /* ga_precision */
-    int32_t kernel;       /* ga_kernel: PLAIN with FP64/FP32, BATCHED with SPLIT_BF16 */
+    int32_t kernel;       /* ga_kernel: PLAIN with FP64/FP32, BATCHED with FP32/SPLIT_BF16 */
     int32_t c_symmetric;  /* 1: C == C^T (checked by ga_init); 0: a transposed copy is kept */
     int32_t multihop;     /* 0: inter-hub flow goes directly hub -> hub (C[h_k][h_l]);
                            * 1: along shortest paths of the network (eq. (4) of Sec. 3 lets

@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhubga.so")
 SOURCES = ["prep.hip", "alloc.hip", "eval_plain.hip", "recheck.hip", "eval_mfma.hip", "ga_ops.hip", "select.hip",
-           "enumerate.hip", "hubga.cpp"]
+           "enumerate.hip", "eval_vec.hip", "hubga.cpp"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 

@@ -87,6 +87,7 @@ struct DevPtrs {
 
 struct Dims {
     int n, p, S, m, R, n_pad, n_mtiles, n1, elitist, prec;
+    int kern;           // ga_kernel: 0 plain (one workgroup per individual), 1 batched
     int tot;            // candidate slots of the column-parallel exact re-evaluation
     int mfma_cfg;       // tile configuration of the batched kernel
     int c_f32, w_f32;   // instance dtypes (1 = FP32)

@@ -34,7 +34,8 @@ struct Layout {
 
 bool is_valid_combo(int prec, int kern)
 {
-    return (prec == GA_PREC_FP64 && kern == GA_KERN_PLAIN) || (prec == GA_PREC_FP32 && kern == GA_KERN_PLAIN) ||
+    return (prec == GA_PREC_FP64 && kern == GA_KERN_PLAIN) ||
+           (prec == GA_PREC_FP32 && (kern == GA_KERN_PLAIN || kern == GA_KERN_BATCHED)) ||
            (prec == GA_PREC_SPLIT_BF16 && kern == GA_KERN_BATCHED);
 }
 
@@ -57,7 +58,7 @@ std::string check_params(const ga_params *q)
     if (q->c_symmetric != 0 && q->c_symmetric != 1) return "c_symmetric must be 0 or 1";
     if (q->multihop != 0 && q->multihop != 1) return "multihop must be 0 or 1";
     if (!is_valid_combo(q->precision, q->kernel))
-        return "precision/kernel must be FP64+PLAIN, FP32+PLAIN or SPLIT_BF16+BATCHED";
+        return "precision/kernel must be FP64+PLAIN, FP32+PLAIN, FP32+BATCHED or SPLIT_BF16+BATCHED";
     return "";
 }
 
@@ -78,6 +79,7 @@ Dims make_dims(const ga_params *q, ga_dtype cdt, ga_dtype wdt)
     d.n1 = q->n1;
     d.elitist = q->elitist;
     d.prec = q->precision;
+    d.kern = q->kernel;
     d.c_f32 = cdt == GA_DT_F32;
     d.sym = q->c_symmetric;
     d.multihop = q->multihop;
@@ -125,8 +127,9 @@ Carve carve(const Dims &d, int c_symmetric)
     c.parts = L.take((size_t)d.S * 24);
     c.eps = L.take((size_t)d.S * 8);
     c.cmax = L.take((size_t)d.S * 4);
-    c.Ch32 = split ? L.take((size_t)d.S * d.p * d.p * 4) : (size_t)-1;
-    c.partial = split ? L.take((size_t)d.n_mtiles * d.S * d.p * 8) : (size_t)-1;
+    const bool vec = d.prec == kFP32 && d.kern == GA_KERN_BATCHED;
+    c.Ch32 = split || vec ? L.take((size_t)d.S * d.p * d.p * 4) : (size_t)-1;
+    c.partial = split ? L.take((size_t)d.n_mtiles * d.S * d.p * 8) : vec ? L.take(vec_partial_bytes(d)) : (size_t)-1;
     c.anc = L.take((size_t)d.R * d.p * 4);
     c.anc_cost = L.take((size_t)d.R * 8);
     c.anc_parts = L.take((size_t)d.R * 24);
@@ -298,6 +301,9 @@ ga_status run_eval(ga_ctx *ctx, const int32_t *hubs, int count, uint16_t *kidx, 
         if (a) HIPCHK(hipEventRecord(a, s));
         HIPCHK(launch_eval_exact(P, d, hubs, kidx, count, P.cost, P.parts, P.eps, s));
         if (b) HIPCHK(hipEventRecord(b, s));
+    } else if (d.prec == kFP32 && d.kern == GA_KERN_BATCHED) {
+        HIPCHK(launch_alloc(P, d, hubs, count, kidx, 1, 1, s));
+        HIPCHK(launch_eval_vec(P, d, kidx, count, s, a, b));
     } else if (d.prec == kFP32) {
         HIPCHK(launch_alloc(P, d, hubs, count, kidx, 1, 0, s));
         if (a) HIPCHK(hipEventRecord(a, s));

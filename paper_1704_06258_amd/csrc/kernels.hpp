@@ -24,6 +24,12 @@ hipError_t launch_eval_exact(const DevPtrs &P, const Dims &d, const int32_t *hub
 hipError_t launch_eval_fp32(const DevPtrs &P, const Dims &d, const int32_t *hubs, const uint16_t *kidx, int count,
                             hipStream_t st);
 double fp32_eps_bound(int n);
+
+// batched FP32 evaluation on the vector units (eval_vec.hip)
+hipError_t launch_eval_vec(const DevPtrs &P, const Dims &d, const uint16_t *kidx, int count, hipStream_t st,
+                           hipEvent_t ev0, hipEvent_t ev1);
+size_t vec_partial_bytes(const Dims &d);
+int vec_group(int p);
 hipError_t prepare_plain_kernels(int max_lds);
 
 // exact re-evaluation of candidates, island decisions, P0 (recheck.hip)

@@ -23,6 +23,7 @@ GA_KERN_PLAIN, GA_KERN_BATCHED = 0, 1
 
 PRECISIONS = {"fp64": GA_PREC_FP64, "fp32": GA_PREC_FP32, "split_bf16": GA_PREC_SPLIT_BF16}
 DEFAULT_KERNEL = {GA_PREC_FP64: GA_KERN_PLAIN, GA_PREC_FP32: GA_KERN_PLAIN, GA_PREC_SPLIT_BF16: GA_KERN_BATCHED}
+KERNELS = {"plain": GA_KERN_PLAIN, "batched": GA_KERN_BATCHED}
 
 # Every symbol declared in include/hubga.h.
 EXPORTS = ("ga_params_default", "ga_workspace_bytes", "ga_init", "ga_evaluate", "ga_evaluate_dev", "ga_step",
@@ -159,7 +160,8 @@ def make_params(n, p, *, chi, alpha, delta, scale=1.0, seed=1, population=64, is
     q.island_size = island_size if island_size is not None else min(64, population)
     q.n1, q.elitist = n1, int(bool(elitist))
     q.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-    q.kernel = DEFAULT_KERNEL[q.precision] if kernel is None else int(kernel)
+    q.kernel = DEFAULT_KERNEL[q.precision] if kernel is None else (
+        KERNELS[kernel] if isinstance(kernel, str) else int(kernel))
     q.c_symmetric = int(bool(c_symmetric))
     q.multihop = int(bool(multihop))
     return q

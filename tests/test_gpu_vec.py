@@ -1,0 +1,73 @@
+"""GPU: the batched FP32 vector kernel (precision FP32 with the batched
+kernel), the comparator of the matrix-core path.  Bars: every cost within its
+returned FP32 bound of the oracle's; GA trajectories bit-identical to the
+oracle's (certified selection); the same bound as the plain FP32 kernel, over
+hub counts that change the group size (p = 3, 20, 50, 64), ragged n and
+counts, asymmetric C, FP32 instances and multi-hop routing."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1704_06258_amd import hubga
+from paper_1704_06258_amd import instances as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    hubga.lib()
+    yield
+
+
+def make(inst, **kw):
+    return hubga.Solver(inst.C, inst.W, inst.p, chi=inst.chi, alpha=inst.alpha, delta=inst.delta,
+                        scale=inst.scale, precision="fp32", kernel="batched", **kw)
+
+
+CASES = [("uniform_n333_p3", lambda: I.uniform(seed=60, n=333, p=3), 77),
+         ("clustered_n1000_p20", lambda: I.clustered(), 256),
+         ("float32_n700_p50", lambda: I.large(seed=4, n=700, p=50), 64),
+         ("uniform_n300_p64", lambda: I.uniform(seed=61, n=300, p=64), 30),
+         ("asym_n131_p6", lambda: I.random_asymmetric(seed=62, n=131, p=6), 40),
+         ("n1_p1", lambda: I.uniform(seed=63, n=1, p=1), 2),
+         ("n2_p1", lambda: I.uniform(seed=64, n=2, p=1), 2)]
+
+
+@pytest.mark.parametrize("name,mk,count", CASES, ids=[c[0] for c in CASES])
+def test_vec_within_bound(name, mk, count):
+    inst = mk()
+    hubs = I.random_hub_sets(65, inst.n, inst.p, count)
+    ref, ref_parts = oracle.evaluate(inst.C64(), inst.W64(), hubs, inst.chi, inst.alpha, inst.delta, inst.scale)
+    pop = count + (count % 2)
+    with make(inst, population=pop, island_size=2) as s:
+        out = s.evaluate(hubs)
+    err = np.abs(out["cost"] - ref) / np.maximum(ref, 1e-300)
+    assert np.all(out["eps"] > 0) and np.all(err <= out["eps"]), (err.max(), out["eps"].min())
+    assert np.allclose(out["parts"][:, [0, 2]], ref_parts[:, [0, 2]], rtol=1e-12, atol=0)
+
+
+def test_vec_trajectory_equals_oracle():
+    inst = I.medium()
+    st = oracle.ga_init(inst.C64(), inst.W64(), inst.p, 1024, 64, inst.chi, inst.alpha, inst.delta)
+    oracle.ga_run(inst.C64(), inst.W64(), st, 25, S=1024, m=64, n1=10, seed=1, chi=inst.chi, alpha=inst.alpha,
+                  delta=inst.delta)
+    with make(inst, population=1024, island_size=64, n1=10, seed=1) as s:
+        s.step(25)
+        anc, anc_cost = s.ancestors()
+        best = s.best()
+    assert np.array_equal(anc, st.anc) and np.array_equal(anc_cost, st.anc_cost)
+    assert np.array_equal(best["hubs"], st.best) and best["cost"] == st.best_cost[0]
+
+
+def test_vec_routed_within_bound():
+    inst = I.nonmetric(seed=66, n=250, p=9)
+    C, W = inst.C64(), inst.W64()
+    hubs = I.random_hub_sets(67, inst.n, inst.p, 48)
+    ref, _ = oracle.evaluate(C, W, hubs, inst.chi, inst.alpha, inst.delta, Ctr=oracle.shortest_paths(C))
+    with make(inst, population=48, island_size=2, multihop=True) as s:
+        out = s.evaluate(hubs)
+    err = np.abs(out["cost"] - ref) / ref
+    assert np.all(err <= out["eps"]), err.max()
