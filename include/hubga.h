@@ -268,7 +268,11 @@ ga_status ga_evaluation_folded(ga_ctx *ctx, int32_t *folded);
  * are grouped: each step of their generation (operators, allocation, the
  * matrix-core product, cost assembly, selection, exact re-evaluation, island
  * decisions) is one launch over all of them, its grid the concatenation of
- * the contexts' own grids.  Other contexts replay their own generation graph
+ * the contexts' own grids.  The six launches are captured once as a HIP graph
+ * whose kernels read the composition from the batch's device table; it is
+ * replayed for every composition that fits its grids and captured anew, with
+ * room to grow, when one does not (at most 256 grouped contexts).  The grouped
+ * generation then costs one graph launch.  Other contexts replay their own generation graph
  * on side streams beside the grouped launches.  tile_config must be a
  * pipelined configuration (see ga_tile_config_info).  Every context must use
  * the batch's (non-null) stream (ga_set_stream moves one there) and must not

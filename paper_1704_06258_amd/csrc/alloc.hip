@@ -242,9 +242,11 @@ __global__ __launch_bounds__(256, 8) void k_alloc(const int32_t *__restrict__ hu
 
 // Grouped: the children of every context, with their sums and hub tables
 // (the split-bf16 generation).
-__global__ __launch_bounds__(256, 8) void k_alloc_group(const TickJob *__restrict__ jobs, int njobs)
+__global__ __launch_bounds__(256, 8) void k_alloc_group(const GroupHdr *__restrict__ hdr,
+                                                       const TickJob *__restrict__ jobs)
 {
-    const TickJob &J = jobs[tick_job(jobs, njobs, kTickAlloc, blockIdx.x)];
+    if ((int)blockIdx.x >= hdr->blocks[kTickAlloc]) return;
+    const TickJob &J = jobs[tick_job(jobs, hdr->njobs, kTickAlloc, blockIdx.x)];
     const int blk = blockIdx.x - J.start[kTickAlloc];
     const DevPtrs &P = J.P;
     const Dims &d = J.d;
@@ -273,10 +275,10 @@ hipError_t launch_alloc(const DevPtrs &P, const Dims &d, const int32_t *hubs, in
     return hipGetLastError();
 }
 
-hipError_t launch_alloc_group(const TickJob *jobs, int njobs, int blocks, hipStream_t st)
+hipError_t launch_alloc_group(const GroupHdr *hdr, const TickJob *jobs, int njobs, int blocks, hipStream_t st)
 {
     if (njobs <= 0 || blocks <= 0) return hipSuccess;
-    k_alloc_group<<<blocks, 256, 0, st>>>(jobs, njobs);
+    k_alloc_group<<<blocks, 256, 0, st>>>(hdr, jobs);
     return hipGetLastError();
 }
 

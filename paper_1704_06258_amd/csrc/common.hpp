@@ -113,6 +113,18 @@ struct TickJob {
     int blocks[kTickPhases];
 };
 
+// The composition of a grouped generation, in device memory ahead of the job
+// tables: the grouped kernels read their job count and sizes from here, so a
+// graph captured with grids of some capacity serves every composition that
+// fits it (workgroups past a phase's total return at once).
+struct GroupHdr {
+    int njobs;
+    int total_tiles;           // matrix-core work units
+    int round_robin;           // some context is folded: units go round robin over the XCDs
+    int pad;
+    int blocks[kTickPhases];   // workgroups of each phase
+};
+
 // The context owning workgroup b of a grouped launch (last job with start <= b).
 __device__ inline int tick_job(const TickJob *__restrict__ jobs, int njobs, int phase, int b)
 {

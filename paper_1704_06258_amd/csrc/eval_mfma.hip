@@ -767,12 +767,15 @@ __global__ __launch_bounds__(256, OCC) void k_eval_mfma_pipe(MfmaJob J)
 // One launch over the tiles of several contexts: the concatenated tile list
 // (each context row-tile major) is split into 8 contiguous ranges, one per
 // XCD (blockIdx % 8), so every XCD walks whole row panels; round robin when
-// a context is folded.
+// a context is folded.  The grid may exceed the composition's tiles (a
+// captured graph's capacity): the extra workgroups return.
 template <int ROWB, int COLB, int NST, int KINS, int OCC, int EARLY>
-__global__ __launch_bounds__(256, OCC) void k_eval_mfma_pipe_group(const MfmaJob *__restrict__ jobs, int njobs,
-                                                                   int total_tiles, int round_robin)
+__global__ __launch_bounds__(256, OCC) void k_eval_mfma_pipe_group(const GroupHdr *__restrict__ hdr,
+                                                                   const MfmaJob *__restrict__ jobs)
 {
     __shared__ __align__(16) u32x4 ring[pipe_ring_chunks<ROWB, COLB, NST, KINS, EARLY>()];
+    const int total_tiles = hdr->total_tiles, round_robin = hdr->round_robin, njobs = hdr->njobs;
+    if (!round_robin && (int)(blockIdx.x >> 3) >= (total_tiles + 7) / 8) return;
     const int t = pipe_tile_of_block(total_tiles, round_robin);
     if (t >= total_tiles) return;
     int lo = 0, hi = njobs - 1;   // last job with tile_start <= t
@@ -831,9 +834,11 @@ __global__ __launch_bounds__(256) void k_finalize_split(const double *__restrict
     finalize_body(partial, cmax, count, p, n_mt, n, c_f32, chi, alpha, delta, scale, cost, parts, eps, blockIdx.x);
 }
 
-__global__ __launch_bounds__(256) void k_finalize_group(const TickJob *__restrict__ jobs, int njobs)
+__global__ __launch_bounds__(256) void k_finalize_group(const GroupHdr *__restrict__ hdr,
+                                                        const TickJob *__restrict__ jobs)
 {
-    const TickJob &J = jobs[tick_job(jobs, njobs, kTickFinal, blockIdx.x)];
+    if ((int)blockIdx.x >= hdr->blocks[kTickFinal]) return;
+    const TickJob &J = jobs[tick_job(jobs, hdr->njobs, kTickFinal, blockIdx.x)];
     const DevPtrs &P = J.P;
     const Dims &d = J.d;
     finalize_body(P.partial, P.cmax, d.S, d.p, J.n_mt, d.n, d.c_f32, d.chi, d.alpha, d.delta, d.scale, P.cost,
@@ -974,10 +979,10 @@ hipError_t launch_finalize(const DevPtrs &P, const Dims &d, int count, int cfg, 
 
 int finalize_blocks(int count) { return (count + 3) / 4; }
 
-hipError_t launch_finalize_group(const TickJob *jobs, int njobs, int blocks, hipStream_t st)
+hipError_t launch_finalize_group(const GroupHdr *hdr, const TickJob *jobs, int njobs, int blocks, hipStream_t st)
 {
     if (njobs <= 0 || blocks <= 0) return hipSuccess;
-    k_finalize_group<<<blocks, 256, 0, st>>>(jobs, njobs);
+    k_finalize_group<<<blocks, 256, 0, st>>>(hdr, jobs);
     return hipGetLastError();
 }
 
@@ -1020,44 +1025,45 @@ int mfma_fill_jobs(const DevPtrs *const *P, const Dims *const *d, int njobs, int
 }
 
 template <int ROWB, int COLB, int NST, int KINS, int OCC, int EARLY>
-static hipError_t group_launch(const void *d_jobs, int njobs, int total, int rr, hipStream_t st)
+static hipError_t group_launch(const GroupHdr *hdr, const void *d_jobs, int grid, hipStream_t st)
 {
-    const int per = (total + 7) / 8;
-    k_eval_mfma_pipe_group<ROWB, COLB, NST, KINS, OCC, EARLY><<<per * 8, 256, 0, st>>>((const MfmaJob *)d_jobs,
-                                                                                      njobs, total, rr);
+    k_eval_mfma_pipe_group<ROWB, COLB, NST, KINS, OCC, EARLY><<<grid, 256, 0, st>>>(hdr, (const MfmaJob *)d_jobs);
     return hipGetLastError();
 }
 
 template <int ROWB, int COLB, int NST, int OCC, int EARLY = 0>
-static hipError_t group_dispatch(int kins, const void *d_jobs, int njobs, int total, int rr, hipStream_t st)
+static hipError_t group_dispatch(int kins, const GroupHdr *hdr, const void *d_jobs, int grid, hipStream_t st)
 {
-    if (kins <= 1) return group_launch<ROWB, COLB, NST, 1, OCC, EARLY>(d_jobs, njobs, total, rr, st);
-    return group_launch<ROWB, COLB, NST, 2, OCC, EARLY>(d_jobs, njobs, total, rr, st);
+    if (kins <= 1) return group_launch<ROWB, COLB, NST, 1, OCC, EARLY>(hdr, d_jobs, grid, st);
+    return group_launch<ROWB, COLB, NST, 2, OCC, EARLY>(hdr, d_jobs, grid, st);
 }
 
-hipError_t launch_mfma_group(const void *d_jobs, int njobs, int total, int cfg, int min_p, int rr,
-                             hipStream_t st)
+int mfma_group_kins(int cfg, int min_p) { return kidx_transfers(kMfmaCfgs[cfg].colb, min_p); }
+
+// grid: workgroups, a multiple of 8 and at least the composition's tiles
+// rounded up to one; kins: hub-position transfers the kernel stages (enough
+// for the smallest hub count of the composition).
+hipError_t launch_mfma_group(const GroupHdr *hdr, const void *d_jobs, int grid, int cfg, int kins, hipStream_t st)
 {
-    if (njobs <= 0 || total <= 0) return hipSuccess;
-    const int kins = kidx_transfers(kMfmaCfgs[cfg].colb, min_p);
-    if (kins > 2) return hipErrorInvalidValue;
+    if (grid <= 0) return hipSuccess;
+    if (kins > 2 || grid % 8) return hipErrorInvalidValue;
     switch (cfg) {
-    case 6: return group_dispatch<4, 2, 4, 1>(kins, d_jobs, njobs, total, rr, st);
-    case 7: return group_dispatch<4, 2, 3, 2>(kins, d_jobs, njobs, total, rr, st);
-    case 8: return group_dispatch<4, 4, 4, 1>(kins, d_jobs, njobs, total, rr, st);
-    case 9: return group_dispatch<4, 4, 3, 1>(kins, d_jobs, njobs, total, rr, st);
-    case 10: return group_dispatch<2, 4, 4, 2>(kins, d_jobs, njobs, total, rr, st);
-    case 11: return group_dispatch<4, 2, 3, 2, 1>(kins, d_jobs, njobs, total, rr, st);
-    case 12: return group_dispatch<4, 2, 4, 1, 1>(kins, d_jobs, njobs, total, rr, st);
-    case 13: return group_dispatch<2, 4, 4, 2, 1>(kins, d_jobs, njobs, total, rr, st);
-    case 14: return group_dispatch<4, 2, 4, 2>(kins, d_jobs, njobs, total, rr, st);
-    case 15: return group_dispatch<4, 2, 4, 2, 1>(kins, d_jobs, njobs, total, rr, st);
-    case 16: return group_dispatch<4, 2, 2, 2, 2>(kins, d_jobs, njobs, total, rr, st);
-    case 17: return group_dispatch<4, 2, 3, 1, 2>(kins, d_jobs, njobs, total, rr, st);
-    case 18: return group_dispatch<4, 4, 3, 1, 2>(kins, d_jobs, njobs, total, rr, st);
-    case 19: return group_dispatch<4, 4, 2, 1, 2>(kins, d_jobs, njobs, total, rr, st);
-    case 20: return group_dispatch<2, 4, 3, 2, 2>(kins, d_jobs, njobs, total, rr, st);
-    case 21: return group_dispatch<2, 4, 2, 2, 2>(kins, d_jobs, njobs, total, rr, st);
+    case 6: return group_dispatch<4, 2, 4, 1>(kins, hdr, d_jobs, grid, st);
+    case 7: return group_dispatch<4, 2, 3, 2>(kins, hdr, d_jobs, grid, st);
+    case 8: return group_dispatch<4, 4, 4, 1>(kins, hdr, d_jobs, grid, st);
+    case 9: return group_dispatch<4, 4, 3, 1>(kins, hdr, d_jobs, grid, st);
+    case 10: return group_dispatch<2, 4, 4, 2>(kins, hdr, d_jobs, grid, st);
+    case 11: return group_dispatch<4, 2, 3, 2, 1>(kins, hdr, d_jobs, grid, st);
+    case 12: return group_dispatch<4, 2, 4, 1, 1>(kins, hdr, d_jobs, grid, st);
+    case 13: return group_dispatch<2, 4, 4, 2, 1>(kins, hdr, d_jobs, grid, st);
+    case 14: return group_dispatch<4, 2, 4, 2>(kins, hdr, d_jobs, grid, st);
+    case 15: return group_dispatch<4, 2, 4, 2, 1>(kins, hdr, d_jobs, grid, st);
+    case 16: return group_dispatch<4, 2, 2, 2, 2>(kins, hdr, d_jobs, grid, st);
+    case 17: return group_dispatch<4, 2, 3, 1, 2>(kins, hdr, d_jobs, grid, st);
+    case 18: return group_dispatch<4, 4, 3, 1, 2>(kins, hdr, d_jobs, grid, st);
+    case 19: return group_dispatch<4, 4, 2, 1, 2>(kins, hdr, d_jobs, grid, st);
+    case 20: return group_dispatch<2, 4, 3, 2, 2>(kins, hdr, d_jobs, grid, st);
+    case 21: return group_dispatch<2, 4, 2, 2, 2>(kins, hdr, d_jobs, grid, st);
     default: return hipErrorInvalidValue;
     }
 }

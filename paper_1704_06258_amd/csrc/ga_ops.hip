@@ -144,9 +144,10 @@ __global__ __launch_bounds__(256) void k_ga_ops(const int32_t *__restrict__ anc,
     ga_ops_body(anc, children, gen, n, p, S, m, seed, blockIdx.x);
 }
 
-__global__ __launch_bounds__(256) void k_ga_ops_group(const TickJob *__restrict__ jobs, int njobs)
+__global__ __launch_bounds__(256) void k_ga_ops_group(const GroupHdr *__restrict__ hdr, const TickJob *__restrict__ jobs)
 {
-    const TickJob &J = jobs[tick_job(jobs, njobs, kTickOps, blockIdx.x)];
+    if ((int)blockIdx.x >= hdr->blocks[kTickOps]) return;
+    const TickJob &J = jobs[tick_job(jobs, hdr->njobs, kTickOps, blockIdx.x)];
     ga_ops_body(J.P.anc, J.P.hubs, J.P.gen, J.d.n, J.d.p, J.d.S, J.d.m, J.d.seed, blockIdx.x - J.start[kTickOps]);
 }
 
@@ -158,10 +159,10 @@ hipError_t launch_ga_ops(const DevPtrs &P, const Dims &d, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_ga_ops_group(const TickJob *jobs, int njobs, int blocks, hipStream_t st)
+hipError_t launch_ga_ops_group(const GroupHdr *hdr, const TickJob *jobs, int njobs, int blocks, hipStream_t st)
 {
     if (njobs <= 0 || blocks <= 0) return hipSuccess;
-    k_ga_ops_group<<<blocks, 256, 0, st>>>(jobs, njobs);
+    k_ga_ops_group<<<blocks, 256, 0, st>>>(hdr, jobs);
     return hipGetLastError();
 }
 

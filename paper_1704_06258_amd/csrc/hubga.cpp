@@ -228,7 +228,12 @@ struct ga_batch {
     // device table is rewritten in stream order; its host staging is a ring of
     // pinned buffers, so a recomposition waits only for a copy kStageRing
     // recompositions old.
+    // The device table: the composition header (GroupHdr), the matrix-core
+    // job table and the TickJob table at fixed offsets sized for kMaxPoolJobs
+    // contexts, so a captured generation's pointers stay valid for every
+    // composition.
     static constexpr int kStageRing = 8;
+    static constexpr size_t kHdrBytes = 256;
     void *d_tab = nullptr;
     void *h_tab[kStageRing] = {};
     hipEvent_t tab_copied[kStageRing] = {};
@@ -238,6 +243,15 @@ struct ga_batch {
     int round_robin = 0;   // some context is folded: tiles go round robin over the XCDs
     int blocks[kTickPhases] = {};
     size_t lds_recheck = 0;
+    // One grouped generation captured as a graph, its grids sized to a
+    // capacity; every composition that fits replays it (the kernels read the
+    // composition from the header), a larger one is captured anew.
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    bool graph_failed = false;
+    int cap_blocks[kTickPhases] = {};
+    int cap_grid = 0, cap_kins = 0, cap_sel = 0;
+    size_t cap_lds = 0;
 };
 
 namespace {
@@ -1019,6 +1033,92 @@ ga_status ga_evaluation_folded(ga_ctx *ctx, int32_t *folded)
 
 // ------------------------------------------------------------- batches --
 
+namespace {
+
+// Offset of the TickJob table in a batch's device table, and its size.
+size_t batch_tick_offset()
+{
+    return ga_batch::kHdrBytes + ((mfma_job_bytes() * kMaxPoolJobs + 255) & ~(size_t)255);
+}
+size_t batch_table_bytes() { return batch_tick_offset() + sizeof(TickJob) * kMaxPoolJobs; }
+
+// One grouped generation: the six grouped launches with the given grids
+// (workgroups per phase, matrix-core workgroups, hub-position transfers,
+// selection block size, re-evaluation LDS); the kernels take the composition
+// from the table's header.
+hipError_t launch_grouped(const ga_batch *b, const int *grid, int mfma_grid, int kins, int sel_threads,
+                          size_t lds_recheck)
+{
+    const GroupHdr *hdr = (const GroupHdr *)b->d_tab;
+    const void *mjobs = (const char *)b->d_tab + ga_batch::kHdrBytes;
+    const TickJob *tjobs = (const TickJob *)((const char *)b->d_tab + batch_tick_offset());
+    const int nj = b->njobs;
+    hipError_t e;
+    if ((e = launch_ga_ops_group(hdr, tjobs, nj, grid[kTickOps], b->st)) != hipSuccess) return e;
+    if ((e = launch_alloc_group(hdr, tjobs, nj, grid[kTickAlloc], b->st)) != hipSuccess) return e;
+    if ((e = launch_mfma_group(hdr, mjobs, mfma_grid, b->cfg, kins, b->st)) != hipSuccess) return e;
+    if ((e = launch_finalize_group(hdr, tjobs, nj, grid[kTickFinal], b->st)) != hipSuccess) return e;
+    if ((e = launch_select1_group(hdr, tjobs, nj, grid[kTickSel1], sel_threads, b->st)) != hipSuccess) return e;
+    return launch_recheck_group(hdr, tjobs, nj, lds_recheck, b->st);
+}
+
+void drop_batch_graph(ga_batch *b)
+{
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->gexec = nullptr;
+    b->graph = nullptr;
+}
+
+int grid_cap(int need)   // a power of two, at least 8
+{
+    int c = 8;
+    while (c < need) c *= 2;
+    return c;
+}
+
+// Keep the captured grouped generation when the current composition fits
+// its grids; otherwise capture one whose grids have room to grow.  A stream
+// that cannot be captured leaves direct launches.
+void capture_batch_generation(ga_batch *b)
+{
+    const int kins = mfma_group_kins(b->cfg, b->min_p);
+    bool fits = b->gexec && kins <= b->cap_kins && b->sel_threads <= b->cap_sel && b->lds_recheck <= b->cap_lds &&
+                b->total_tiles <= b->cap_grid;
+    for (int q = 0; q < kTickPhases && fits; ++q) fits = b->blocks[q] <= b->cap_blocks[q];
+    if (fits || b->graph_failed) return;
+    drop_batch_graph(b);
+    int caps[kTickPhases];
+    for (int q = 0; q < kTickPhases; ++q) caps[q] = grid_cap(b->blocks[q]);
+    const int cap_grid = grid_cap(b->total_tiles), cap_kins = std::max(kins, b->cap_kins);
+    const int cap_sel = std::max(b->sel_threads, b->cap_sel);
+    const size_t cap_lds = std::max(b->lds_recheck, b->cap_lds);
+    if (hipStreamBeginCapture(b->st, hipStreamCaptureModeRelaxed) != hipSuccess) {
+        (void)hipGetLastError();
+        b->graph_failed = true;
+        return;
+    }
+    const hipError_t le = launch_grouped(b, caps, cap_grid, cap_kins, cap_sel, cap_lds);
+    hipGraph_t g = nullptr;
+    const hipError_t ee = hipStreamEndCapture(b->st, &g);
+    hipGraphExec_t x = nullptr;
+    if (le != hipSuccess || ee != hipSuccess || !g || hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        b->graph_failed = true;
+        return;
+    }
+    b->graph = g;
+    b->gexec = x;
+    memcpy(b->cap_blocks, caps, sizeof(caps));
+    b->cap_grid = cap_grid;
+    b->cap_kins = cap_kins;
+    b->cap_sel = cap_sel;
+    b->cap_lds = cap_lds;
+}
+
+}  // namespace
+
 extern "C" {
 
 ga_status ga_batch_create(void *hip_stream, int32_t tile_config, ga_batch **out)
@@ -1036,6 +1136,17 @@ ga_status ga_batch_create(void *hip_stream, int32_t tile_config, ga_batch **out)
         if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
             ga_batch_free(b);
             return fail(nullptr, GA_ERR_DEVICE, "event");
+        }
+    // the device table and its pinned staging ring, at their full size
+    b->tab_cap = batch_table_bytes();
+    if (hipMalloc(&b->d_tab, b->tab_cap) != hipSuccess) {
+        ga_batch_free(b);
+        return fail(nullptr, GA_ERR_OOM, "job table");
+    }
+    for (auto &h : b->h_tab)
+        if (hipHostMalloc(&h, b->tab_cap, 0) != hipSuccess) {
+            ga_batch_free(b);
+            return fail(nullptr, GA_ERR_OOM, "job table staging");
         }
     *out = b;
     return GA_OK;
@@ -1100,39 +1211,33 @@ ga_status ga_batch_set(ga_batch *b, ga_ctx *const *ctxs, int32_t count)
     }
     if (njobs && lds_recheck > recheck_group_lds_cap())
         return fail(nullptr, GA_ERR_INVALID, "batch: re-evaluation LDS exceeds the device limit");
-    // tables, copied in stream order after earlier generations
-    const size_t mbytes = ((mfma_job_bytes() * std::max(1, njobs)) + 255) & ~(size_t)255;
-    const size_t bytes = mbytes + sizeof(TickJob) * std::max(1, njobs);
-    if (bytes > b->tab_cap) {
-        if ((e = hipStreamSynchronize(b->st)) != hipSuccess) return fail(nullptr, GA_ERR_DEVICE, hipGetErrorString(e));
-        if (b->d_tab) (void)hipFree(b->d_tab);
-        b->d_tab = nullptr;
-        for (auto &h : b->h_tab) {
-            if (h) (void)hipHostFree(h);
-            h = nullptr;
-        }
-        b->tab_cap = 0;
-        const size_t cap = std::max(bytes * 2, (size_t)64 * (mfma_job_bytes() + sizeof(TickJob)) + 256);
-        if (hipMalloc(&b->d_tab, cap) != hipSuccess) return fail(nullptr, GA_ERR_OOM, "job table");
-        for (auto &h : b->h_tab)
-            if (hipHostMalloc(&h, cap, 0) != hipSuccess) return fail(nullptr, GA_ERR_OOM, "job table staging");
-        b->tab_cap = cap;
-    }
+    // tables (header, matrix-core jobs, TickJobs), copied in stream order
+    // after earlier generations, into the fixed layout
+    const size_t tick_off = batch_tick_offset();
     if (njobs) {
         const int k = b->stage;
         b->stage = (k + 1) % ga_batch::kStageRing;
         if ((e = hipEventSynchronize(b->tab_copied[k])) != hipSuccess)   // this staging buffer's last copy
             return fail(nullptr, GA_ERR_DEVICE, hipGetErrorString(e));
-        b->total_tiles = mfma_fill_jobs(P.data(), D.data(), njobs, b->cfg, b->h_tab[k]);
-        memcpy((char *)b->h_tab[k] + mbytes, tj.data(), sizeof(TickJob) * njobs);
-        if ((e = hipMemcpyAsync(b->d_tab, b->h_tab[k], bytes, hipMemcpyHostToDevice, b->st)) != hipSuccess)
+        b->total_tiles = mfma_fill_jobs(P.data(), D.data(), njobs, b->cfg, (char *)b->h_tab[k] + ga_batch::kHdrBytes);
+        memcpy((char *)b->h_tab[k] + tick_off, tj.data(), sizeof(TickJob) * njobs);
+        GroupHdr hdr{};
+        hdr.njobs = njobs;
+        hdr.total_tiles = b->total_tiles;
+        hdr.round_robin = round_robin;
+        memcpy(hdr.blocks, blocks, sizeof(blocks));
+        memcpy(b->h_tab[k], &hdr, sizeof(hdr));
+        const size_t head = ga_batch::kHdrBytes + mfma_job_bytes() * njobs;
+        if ((e = hipMemcpyAsync(b->d_tab, b->h_tab[k], head, hipMemcpyHostToDevice, b->st)) != hipSuccess ||
+            (e = hipMemcpyAsync((char *)b->d_tab + tick_off, (char *)b->h_tab[k] + tick_off,
+                                sizeof(TickJob) * njobs, hipMemcpyHostToDevice, b->st)) != hipSuccess)
             return fail(nullptr, GA_ERR_DEVICE, hipGetErrorString(e));
         if ((e = hipEventRecord(b->tab_copied[k], b->st)) != hipSuccess)
             return fail(nullptr, GA_ERR_DEVICE, hipGetErrorString(e));
     } else {
         b->total_tiles = 0;
     }
-    b->tick_off = mbytes;
+    b->tick_off = tick_off;
     b->njobs = njobs;
     b->min_p = min_p;
     b->round_robin = round_robin;
@@ -1169,8 +1274,6 @@ ga_status ga_batch_step(ga_batch *b, int32_t generations)
         for (auto *c : b->ctxs) c->poisoned = true;
         return fail(nullptr, GA_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
     };
-    const void *mjobs = b->d_tab;
-    const TickJob *tjobs = (const TickJob *)((char *)b->d_tab + b->tick_off);
     const int nj = b->njobs;
     hipError_t e;
     // a member evaluated on its own since (another tile configuration) gets
@@ -1179,6 +1282,7 @@ ga_status ga_batch_step(ga_batch *b, int32_t generations)
         if (ensure_w_layout(c, b->cfg) != GA_OK) return dev_fail(hipErrorUnknown, "split of W");
     for (ga_ctx *c : b->solo)
         if (ensure_w_layout(c, c->d.mfma_cfg) != GA_OK) return dev_fail(hipErrorUnknown, "split of W");
+    if (nj) capture_batch_generation(b);   // a no-op while the composition fits the captured graph
     for (int g = 0; g < generations; ++g) {
         if (nsolo) {   // fork: every alone-stepped context starts after the previous generation
             if ((e = hipEventRecord(b->ev[0], b->st)) != hipSuccess) return dev_fail(e, "fork");
@@ -1195,18 +1299,12 @@ ga_status ga_batch_step(ga_batch *b, int32_t generations)
             }
         }
         if (nj) {
-            if ((e = launch_ga_ops_group(tjobs, nj, b->blocks[kTickOps], b->st)) != hipSuccess)
-                return dev_fail(e, "grouped operators");
-            if ((e = launch_alloc_group(tjobs, nj, b->blocks[kTickAlloc], b->st)) != hipSuccess)
-                return dev_fail(e, "grouped allocation");
-            if ((e = launch_mfma_group(mjobs, nj, b->total_tiles, b->cfg, b->min_p, b->round_robin, b->st)) != hipSuccess)
-                return dev_fail(e, "grouped matrix-core evaluation");
-            if ((e = launch_finalize_group(tjobs, nj, b->blocks[kTickFinal], b->st)) != hipSuccess)
-                return dev_fail(e, "grouped cost assembly");
-            if ((e = launch_select1_group(tjobs, nj, b->blocks[kTickSel1], b->sel_threads, b->st)) != hipSuccess)
-                return dev_fail(e, "grouped selection");
-            if ((e = launch_recheck_group(tjobs, nj, b->lds_recheck, b->st)) != hipSuccess)
-                return dev_fail(e, "grouped re-evaluation");
+            if (b->gexec)
+                e = hipGraphLaunch(b->gexec, b->st);
+            else
+                e = launch_grouped(b, b->blocks, ((b->total_tiles + 7) / 8) * 8,
+                                   mfma_group_kins(b->cfg, b->min_p), b->sel_threads, b->lds_recheck);
+            if (e != hipSuccess) return dev_fail(e, "grouped generation");
         }
         if (nsolo)   // join
             for (int k = 0; k < nside; ++k) {
@@ -1226,6 +1324,7 @@ void ga_batch_free(ga_batch *b)
     for (auto ev : b->ev) (void)hipEventDestroy(ev);
     for (auto ev : b->tab_copied)
         if (ev) (void)hipEventDestroy(ev);
+    drop_batch_graph(b);
     if (b->d_tab) (void)hipFree(b->d_tab);
     for (auto h : b->h_tab)
         if (h) (void)hipHostFree(h);

@@ -16,7 +16,7 @@ hipError_t launch_alloc(const DevPtrs &P, const Dims &d, const int32_t *hubs, in
                         int want_sums, int want_ch, hipStream_t st);
 hipError_t launch_copy_clamp(const int32_t *src, int32_t *dst, int total, int n, hipStream_t st);
 int alloc_blocks(int count);
-hipError_t launch_alloc_group(const TickJob *jobs, int njobs, int blocks, hipStream_t st);
+hipError_t launch_alloc_group(const GroupHdr *hdr, const TickJob *jobs, int njobs, int blocks, hipStream_t st);
 
 // per-individual evaluation (eval_plain.hip)
 hipError_t launch_eval_exact(const DevPtrs &P, const Dims &d, const int32_t *hubs, const uint16_t *kidx, int count,
@@ -37,7 +37,7 @@ hipError_t launch_recheck(const DevPtrs &P, const Dims &d, hipStream_t st);
 hipError_t launch_p0_exact(const DevPtrs &P, const Dims &d, hipStream_t st);
 size_t recheck_lds(int n, int p);
 size_t recheck_group_lds_cap();
-hipError_t launch_recheck_group(const TickJob *jobs, int njobs, size_t lds, hipStream_t st);
+hipError_t launch_recheck_group(const GroupHdr *hdr, const TickJob *jobs, int njobs, size_t lds, hipStream_t st);
 hipError_t prepare_recheck_kernels(int max_lds);
 
 // batched matrix-core evaluation (eval_mfma.hip)
@@ -49,12 +49,12 @@ int mfma_partial_tiles(const Dims &d, int cfg);
 bool mfma_folds(const Dims &d, int cfg);
 int mfma_w_layout(const Dims &d, int cfg);
 int finalize_blocks(int count);
-hipError_t launch_finalize_group(const TickJob *jobs, int njobs, int blocks, hipStream_t st);
+hipError_t launch_finalize_group(const GroupHdr *hdr, const TickJob *jobs, int njobs, int blocks, hipStream_t st);
 bool mfma_groupable(const Dims &d, int cfg);
 size_t mfma_job_bytes();
 int mfma_fill_jobs(const DevPtrs *const *P, const Dims *const *d, int njobs, int cfg, void *jobs_host);
-hipError_t launch_mfma_group(const void *d_jobs, int njobs, int total, int cfg, int min_p, int round_robin,
-                             hipStream_t st);
+hipError_t launch_mfma_group(const GroupHdr *hdr, const void *d_jobs, int grid, int cfg, int kins, hipStream_t st);
+int mfma_group_kins(int cfg, int min_p);
 int mfma_pipelined(int cfg);
 int mfma_num_configs();
 int mfma_rows_per_tile(int cfg);
@@ -70,9 +70,10 @@ hipError_t prepare_enum_kernels(int max_lds);
 // GA (ga_ops.hip, select.hip)
 hipError_t launch_ga_ops(const DevPtrs &P, const Dims &d, hipStream_t st);
 int ga_ops_blocks(const Dims &d);
-hipError_t launch_ga_ops_group(const TickJob *jobs, int njobs, int blocks, hipStream_t st);
+hipError_t launch_ga_ops_group(const GroupHdr *hdr, const TickJob *jobs, int njobs, int blocks, hipStream_t st);
 int select_threads(int m);
-hipError_t launch_select1_group(const TickJob *jobs, int njobs, int blocks, int threads, hipStream_t st);
+hipError_t launch_select1_group(const GroupHdr *hdr, const TickJob *jobs, int njobs, int blocks, int threads,
+                                hipStream_t st);
 hipError_t launch_select(const DevPtrs &P, const Dims &d, int exact, hipStream_t st);
 hipError_t launch_init_state(const DevPtrs &P, const Dims &d, hipStream_t st);
 

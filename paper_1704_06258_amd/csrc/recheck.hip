@@ -517,11 +517,13 @@ __device__ __forceinline__ void rc_group_item(const TickJob &J, int item, char *
     }
 }
 
-__global__ __launch_bounds__(kRcThreads) void k_recheck_group(const TickJob *__restrict__ jobs, int njobs)
+__global__ __launch_bounds__(kRcThreads) void k_recheck_group(const GroupHdr *__restrict__ hdr,
+                                                              const TickJob *__restrict__ jobs)
 {
     extern __shared__ __align__(16) char smem[];
     __shared__ int pre[kMaxPoolJobs + 1];
     __shared__ int sh_h[kMaxP];
+    const int njobs = hdr->njobs;
     const int items = pool_prefix(njobs, [&](int j) { return rc_items(jobs[j]); }, pre);
     for (int g = blockIdx.x; g < items; g += gridDim.x) {
         const int j = pool_job(pre, njobs, g);
@@ -587,11 +589,11 @@ hipError_t launch_p0_exact(const DevPtrs &P, const Dims &d, hipStream_t st)
     return rc_dispatch(P, d, V, st);
 }
 
-hipError_t launch_recheck_group(const TickJob *jobs, int njobs, size_t lds, hipStream_t st)
+hipError_t launch_recheck_group(const GroupHdr *hdr, const TickJob *jobs, int njobs, size_t lds, hipStream_t st)
 {
     if (njobs <= 0) return hipSuccess;
     if (njobs > kMaxPoolJobs) return hipErrorInvalidValue;
-    k_recheck_group<<<kRecheckBlocks, kRcThreads, lds, st>>>(jobs, njobs);
+    k_recheck_group<<<kRecheckBlocks, kRcThreads, lds, st>>>(hdr, jobs);
     return hipGetLastError();
 }
 

@@ -188,9 +188,11 @@ __global__ __launch_bounds__(1024) void k_select1(SelState S, const double *__re
                  nextra, sync, blockIdx.x, gridDim.x);
 }
 
-__global__ __launch_bounds__(1024) void k_select1_group(const TickJob *__restrict__ jobs, int njobs)
+__global__ __launch_bounds__(1024) void k_select1_group(const GroupHdr *__restrict__ hdr,
+                                                        const TickJob *__restrict__ jobs)
 {
-    const TickJob &J = jobs[tick_job(jobs, njobs, kTickSel1, blockIdx.x)];
+    if ((int)blockIdx.x >= hdr->blocks[kTickSel1]) return;
+    const TickJob &J = jobs[tick_job(jobs, hdr->njobs, kTickSel1, blockIdx.x)];
     const DevPtrs &P = J.P;
     const SelState S = make_sel_state(P, J.d);
     select1_body(S, P.cost, P.eps, P.parts, P.cand, P.cand_cnt, J.d.tot, P.slot_r, P.slot_c, P.slot_s, P.handled,
@@ -251,10 +253,11 @@ hipError_t launch_select(const DevPtrs &P, const Dims &d, int exact, hipStream_t
     return launch_recheck(P, d, st);
 }
 
-hipError_t launch_select1_group(const TickJob *jobs, int njobs, int blocks, int threads, hipStream_t st)
+hipError_t launch_select1_group(const GroupHdr *hdr, const TickJob *jobs, int njobs, int blocks, int threads,
+                                hipStream_t st)
 {
     if (njobs <= 0 || blocks <= 0) return hipSuccess;
-    k_select1_group<<<blocks, threads, 0, st>>>(jobs, njobs);
+    k_select1_group<<<blocks, threads, 0, st>>>(hdr, jobs);
     return hipGetLastError();
 }
 

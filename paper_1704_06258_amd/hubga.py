@@ -366,8 +366,9 @@ class Solver:
 
 
 class Batch:
-    """Several Solvers advanced together (ga_batch_*): each step of a
-    generation is one grouped launch over all grouped members' populations.
+    """Several Solvers advanced together (ga_batch_*): a generation of the
+    grouped members is one replay of a captured graph of six grouped launches
+    (kept across compositions that fit its grids, captured anew otherwise).
     Every member must be on ``batch.stream`` (``Solver.set_stream``)."""
 
     def __init__(self, device=0, tile_config=7, stream=None):

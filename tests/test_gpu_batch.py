@@ -188,3 +188,31 @@ def test_member_evaluated_alone_between_batch_steps():
         assert same(state_of(s), ref)
     batch.close()
     assert np.array_equal(got_eval, ref_eval)
+
+
+def test_recomposition_replays_or_recaptures_the_batch_graph():
+    """Compositions that shrink (the captured graph replays with idle
+    workgroups) and grow beyond its capacity (captured anew), with eager work
+    between replays: every member ends where stepping it alone ends."""
+    insts = [I.uniform(seed=21, n=200, p=6), I.uniform(seed=22, n=90, p=4), I.uniform(seed=23, n=600, p=12)]
+    kw = dict(island_size=64, n1=3, precision="split_bf16")
+    pops = [256, 128, 1024]
+    steps = [(0, 1), (0, 1), (0,), (0, 1, 2), (2,), (0, 1, 2)]   # members of each batch phase, 2 generations each
+    gens = [sum(2 for ph in steps if k in ph) for k in range(3)]
+    alone = []
+    for k, inst in enumerate(insts):
+        with make(inst, population=pops[k], seed=30 + k, **kw) as s:
+            s.step(gens[k])
+            alone.append(state_of(s))
+    batch = hubga.Batch(tile_config=16)
+    members = [make(inst, population=pops[k], seed=30 + k, stream=batch.stream, **kw) for k, inst in enumerate(insts)]
+    for ph in steps:
+        batch.set([members[k] for k in ph])
+        batch.step(1)
+        members[ph[0]].ancestors()          # eager work and a wait between replays
+        batch.step(1)
+    batch.synchronize()
+    for s, ref in zip(members, alone):
+        assert same(state_of(s), ref)
+        s.close()
+    batch.close()
