@@ -339,8 +339,13 @@ def main():
         steps = args.steps if N <= 2000 else min(args.steps, 3)
         # plain per-individual kernels (FP64, FP32) and the batched FP32 vector kernel
         for name, prec, kern in (("fp64", "fp64", "plain"), ("fp32", "fp32", "plain"),
-                                 ("fp32_vector_batched", "fp32", "batched")):
+                                 ("fp32_vector_batched", "fp32", "batched"),
+                                 ("split3_bf16_batched", "split3_bf16", "batched")):
             s2 = hubga.Solver(inst.C, inst.W, inst.p, precision=prec, kernel=kern, **kw)
+            if prec == "split3_bf16":
+                from paper_1704_06258_amd import autotune
+                s2.step(1)
+                autotune.autotune(s2, force=True)
             dt2, kms2, l2 = time_steps(s2, steps, pre + args.warmup, kernel_steps=3)
             s2.close()
             plain[name] = {"evals_per_s": S * steps / dt2, "ms_per_step": 1e3 * dt2 / steps,

@@ -66,11 +66,17 @@ typedef enum { GA_DT_F64 = 0, GA_DT_F32 = 1 } ga_dtype;
  *                      W * [A_1 ... A_S] (A_s the one-hot n x p allocation
  *                      matrix of individual s) on bf16 matrix cores with FP32
  *                      accumulation, FP64 epilogue and reduction.
+ *   GA_PREC_SPLIT3_BF16 the same with W split into three bf16 parts
+ *                      (hi, mid, lo: each the round-to-nearest-even of what
+ *                      the previous parts leave), |W - hi - mid - lo| <=
+ *                      2^-24 W against 2^-16 W for two parts, for 1.5x the
+ *                      matrix-core work; register-staged tile configurations
+ *                      (0, 2, 3 and 5) only.
  * In the approximate modes every returned cost carries a rigorous relative
  * error bound (ga_evaluate's eps_out) and GA selection is certified: any
  * individual whose interval could change a decision is re-evaluated exactly,
  * so GA trajectories are identical in all modes. */
-typedef enum { GA_PREC_FP64 = 0, GA_PREC_FP32 = 1, GA_PREC_SPLIT_BF16 = 2 } ga_precision;
+typedef enum { GA_PREC_FP64 = 0, GA_PREC_FP32 = 1, GA_PREC_SPLIT_BF16 = 2, GA_PREC_SPLIT3_BF16 = 3 } ga_precision;
 
 /* GA_KERN_PLAIN: one workgroup per individual (FP64 or FP32).
  * GA_KERN_BATCHED: the whole population in one launch -- with SPLIT_BF16 the
@@ -93,7 +99,7 @@ typedef struct {
     int32_t n1;           /* generations per outer step (global argmin every n1), >= 1 */
     int32_t elitist;      /* 1: an island ancestor is replaced only by a strictly better child */
     int32_t precision;    /* ga_precision */
-    int32_t kernel;       /* ga_kernel: PLAIN with FP64/FP32, BATCHED with FP32/SPLIT_BF16 */
+    int32_t kernel;       /* ga_kernel: PLAIN with FP64/FP32, BATCHED with FP32/SPLIT_BF16/SPLIT3_BF16 */
     int32_t c_symmetric;  /* 1: C == C^T (checked by ga_init); 0: a transposed copy is kept */
     int32_t multihop;     /* 0: inter-hub flow goes directly hub -> hub (C[h_k][h_l]);
                            * 1: along shortest paths of the network (eq. (4) of Sec. 3 lets

@@ -50,9 +50,13 @@ def autotune(solver, cache_path=DEFAULT_CACHE, force=False, reps=5):
     Returns {"config": c, "ms": {c: ms}, "cached": bool}."""
     import numpy as np
     import torch
-    if solver.params.precision != hubga.GA_PREC_SPLIT_BF16:
+    if solver.params.precision not in (hubga.GA_PREC_SPLIT_BF16, hubga.GA_PREC_SPLIT3_BF16):
         return {"config": None, "ms": {}, "cached": False}
-    key = cache_key(solver.n, solver.p, solver.S)
+    # the three-part split runs in the register-staged configurations 0, 2, 3, 5
+    candidates = ([0, 2, 3, 5] if solver.params.precision == hubga.GA_PREC_SPLIT3_BF16
+                  else list(range(len(hubga.tile_configs()))))
+    key = cache_key(solver.n, solver.p, solver.S) + ("|split3" if solver.params.precision == hubga.GA_PREC_SPLIT3_BF16
+                                                     else "")
     cache = _load(cache_path)
     if not force and key in cache:
         solver.set_tile_config(int(cache[key]["config"]))
@@ -63,7 +67,7 @@ def autotune(solver, cache_path=DEFAULT_CACHE, force=False, reps=5):
         hubs = np.repeat(anc, solver.S // anc.shape[0], axis=0)
     d_hubs = torch.from_numpy(np.ascontiguousarray(hubs)).to(solver.device)
     times = {}
-    for cfg in range(len(hubga.tile_configs())):
+    for cfg in candidates:
         times[cfg] = time_config(solver, cfg, d_hubs, reps)
     best = min(times, key=times.get)
     solver.set_tile_config(best)

@@ -12,7 +12,9 @@ constexpr uint16_t kNoHub = 0xFFFF;
 constexpr int kMfmaMinRows = 64;        // smallest row tile of the batched kernel (sizes its partials)
 constexpr int kPad = 128;               // n is padded to a multiple of this for the bf16 copies
 
-enum Precision { kFP64 = 0, kFP32 = 1, kSplitBF16 = 2 };
+enum Precision { kFP64 = 0, kFP32 = 1, kSplitBF16 = 2, kSplit3BF16 = 3 };
+// Modes whose fitness is the bf16 matrix-core product (two or three parts of W).
+__host__ __device__ inline bool split_mode(int prec) { return prec == kSplitBF16 || prec == kSplit3BF16; }
 // Layouts of the bf16 hi/lo split of W (one pair of buffers per context).
 enum WLayout { kWRowMajor = 0, kWFrag = 1, kWFragFolded = 2 };
 
@@ -41,6 +43,7 @@ struct DevPtrs {
     // another; the names below alias it by layout:
     uint16_t *Whi;      //   row-major
     uint16_t *Wlo;
+    uint16_t *Wmd;      //   the middle part of the three-part split (row-major), else null
     uint16_t *Whsw;     //   fragment order: 16-byte chunk (row r, k 8c..8c+7) at
     uint16_t *Wlsw;     //   ((r/64 * n_pad/16 + k/16)*2 + (k/8)%2)*64 + r%64
     uint16_t *Wfhsw;    //   fragment order of the folded W (C symmetric): W_rk + W_kr above
@@ -176,6 +179,7 @@ constexpr double kU64 = 1.1102230246251565e-16;   // 2^-53
 constexpr double kU32 = 5.9604644775390625e-08;   // 2^-24
 constexpr double kU32Faithful = 1.1920928955078125e-07;  // 2^-23 (any faithful FP32 rounding)
 constexpr double kSplitResidual = 1.52587890625e-05;     // 2^-16: |W - hi - lo| <= 2^-16 W
+constexpr double kSplit3Residual = 5.9604644775390625e-08;  // 2^-24: |W - hi - mid - lo| <= 2^-24 W
 // The FP32 accumulators add hi and lo parts, whose magnitudes sum to at most
 // (1 + 2^-8) W + (1 + 2^-8) 2^-8 W <= (1 + 2^-6) W (bf16 unit roundoff 2^-8),
 // so the accumulation bound is taken relative to that mass, not to W.

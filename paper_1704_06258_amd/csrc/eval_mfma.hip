@@ -62,9 +62,12 @@ __device__ __forceinline__ uint32_t onehot2_packed(uint32_t kk, uint32_t lq2, co
     return __builtin_bit_cast(uint32_t, m * c.mul + c.add);
 }
 
-template <int ROWB, int COLB, int KT, int OCC>
+// NP: parts of the split of W (2: hi, lo; 3: hi, lo, mid), all accumulated
+// into the same FP32 registers.
+template <int ROWB, int COLB, int KT, int OCC, int NP = 2>
 __global__ __launch_bounds__(256, OCC) void k_eval_mfma(const uint16_t *__restrict__ Whi,
                                                       const uint16_t *__restrict__ Wlo,
+                                                      const uint16_t *__restrict__ Wmd,
                                                       const uint16_t *__restrict__ kidx,
                                                       const float *__restrict__ Ch32, int n, int n_pad, int p,
                                                       int NS, int n_mt, int n_nt, double *__restrict__ partial)
@@ -74,7 +77,8 @@ __global__ __launch_bounds__(256, OCC) void k_eval_mfma(const uint16_t *__restri
     constexpr int LDS_ROW = KT + 8;          // bf16 per LDS row (16-byte pad against bank conflicts)
     constexpr int A_ELEMS = MT * LDS_ROW;    // one matrix, one stage
     constexpr int KSTEPS = KT / 16;
-    __shared__ __align__(16) uint16_t sA[2][2][A_ELEMS];   // [stage][hi/lo]
+    __shared__ __align__(16) uint16_t sA[2][NP][A_ELEMS];   // [stage][hi/lo(/mid)]
+    const uint16_t *const Wpart[3] = {Whi, Wlo, Wmd};
 
     // XCD-aware tile order: XCD x (= blockIdx % 8) gets the contiguous tile
     // range [x*per, (x+1)*per), row-tile major.
@@ -115,7 +119,7 @@ __global__ __launch_bounds__(256, OCC) void k_eval_mfma(const uint16_t *__restri
     constexpr int CHUNKS = MT * (KT / 8);
     constexpr int PER_THREAD = CHUNKS / 256;   // per matrix
     static_assert(CHUNKS % 256 == 0, "tile must split evenly over 256 threads");
-    u32x4 stage_hi[PER_THREAD], stage_lo[PER_THREAD];
+    u32x4 stage[NP][PER_THREAD];
     u32x4 knext[KSTEPS][COLB], kcur[KSTEPS][COLB];
 
     auto gload = [&](int k0) {
@@ -124,8 +128,8 @@ __global__ __launch_bounds__(256, OCC) void k_eval_mfma(const uint16_t *__restri
             int c = tid + q * 256;
             int row = c / (KT / 8), kq = (c % (KT / 8)) * 8;
             size_t off = (size_t)(M0 + row) * n_pad + k0 + kq;
-            stage_hi[q] = *(const u32x4 *)(Whi + off);
-            stage_lo[q] = *(const u32x4 *)(Wlo + off);
+#pragma unroll
+            for (int part = 0; part < NP; ++part) stage[part][q] = *(const u32x4 *)(Wpart[part] + off);
         }
 #pragma unroll
         for (int kk = 0; kk < KSTEPS; ++kk)
@@ -137,8 +141,8 @@ __global__ __launch_bounds__(256, OCC) void k_eval_mfma(const uint16_t *__restri
         for (int q = 0; q < PER_THREAD; ++q) {
             int c = tid + q * 256;
             int row = c / (KT / 8), kq = (c % (KT / 8)) * 8;
-            *(u32x4 *)(&sA[st][0][row * LDS_ROW + kq]) = stage_hi[q];
-            *(u32x4 *)(&sA[st][1][row * LDS_ROW + kq]) = stage_lo[q];
+#pragma unroll
+            for (int part = 0; part < NP; ++part) *(u32x4 *)(&sA[st][part][row * LDS_ROW + kq]) = stage[part][q];
         }
 #pragma unroll
         for (int kk = 0; kk < KSTEPS; ++kk)
@@ -167,10 +171,10 @@ __global__ __launch_bounds__(256, OCC) void k_eval_mfma(const uint16_t *__restri
                 bb.w = onehot2(kv.w, l2);
                 bfrag[b] = __builtin_bit_cast(bf16x8, bb);
             }
-            // hi pass over every accumulator, then lo pass: consecutive MFMAs
-            // never feed each other
+            // hi pass over every accumulator, then lo (then mid): consecutive
+            // MFMAs never feed each other
 #pragma unroll
-            for (int part = 0; part < 2; ++part) {
+            for (int part = 0; part < NP; ++part) {
 #pragma unroll
                 for (int a = 0; a < ROWB; ++a) {
                     const int lrow = (a * 32 + l32) * LDS_ROW + kk * 16 + half * 8;
@@ -797,10 +801,13 @@ __global__ __launch_bounds__(256, OCC) void k_eval_mfma_pipe_group(const GroupHd
 // t, the individual's p columns contiguous in each), one wave per individual
 // with a fixed reduction order; cost assembly
 // f = ((chi*Cc) + (alpha*T)) + (delta*Dd) and its relative error bound.
+// resid: the split's residual bound; terms: non-zero addends per output and
+// cluster member (2 or 3 parts).
 __device__ __forceinline__ void finalize_body(const double *__restrict__ partial, const int32_t *__restrict__ cmax,
                                               int count, int p, int n_mt, int n, int c_f32, double chi, double alpha,
-                                              double delta, double scale, double *__restrict__ cost,
-                                              double *__restrict__ parts, double *__restrict__ eps, int blk)
+                                              double delta, double scale, double resid, double terms,
+                                              double *__restrict__ cost, double *__restrict__ parts,
+                                              double *__restrict__ eps, int blk)
 {
     const int s = blk * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -817,10 +824,10 @@ __device__ __forceinline__ void finalize_body(const double *__restrict__ partial
         const double Cc = parts[3 * (size_t)s], Dd = parts[3 * (size_t)s + 2];
         parts[3 * (size_t)s + 1] = T;
         cost[s] = (((chi * Cc) + (alpha * T)) + (delta * Dd)) * scale;
-        // split residual + FP32 accumulation of at most 2*cmax non-zero addends
-        // per output (any faithful rounding, relative to the hi + lo mass) +
-        // FP32 hub distances + binary64 sums
-        eps[s] = kSplitResidual + gamma_k(2.0 * cmax[s], kU32Faithful) * kHiLoMass + (c_f32 ? 0.0 : kU32) +
+        // split residual + FP32 accumulation of at most terms*cmax non-zero
+        // addends per output (any faithful rounding, relative to the mass of
+        // the parts) + FP32 hub distances + binary64 sums
+        eps[s] = resid + gamma_k(terms * cmax[s], kU32Faithful) * kHiLoMass + (c_f32 ? 0.0 : kU32) +
                  gamma_k((double)n + (double)len + 8.0, kU64) + gamma_k(n + 2.0, kU64) + gamma_k(8.0, kU64) + 1e-9;
     }
 }
@@ -828,10 +835,12 @@ __device__ __forceinline__ void finalize_body(const double *__restrict__ partial
 __global__ __launch_bounds__(256) void k_finalize_split(const double *__restrict__ partial,
                                                         const int32_t *__restrict__ cmax, int count, int p, int n_mt,
                                                         int n, int c_f32, double chi, double alpha, double delta,
-                                                        double scale, double *__restrict__ cost,
-                                                        double *__restrict__ parts, double *__restrict__ eps)
+                                                        double scale, double resid, double terms,
+                                                        double *__restrict__ cost, double *__restrict__ parts,
+                                                        double *__restrict__ eps)
 {
-    finalize_body(partial, cmax, count, p, n_mt, n, c_f32, chi, alpha, delta, scale, cost, parts, eps, blockIdx.x);
+    finalize_body(partial, cmax, count, p, n_mt, n, c_f32, chi, alpha, delta, scale, resid, terms, cost, parts, eps,
+                  blockIdx.x);
 }
 
 __global__ __launch_bounds__(256) void k_finalize_group(const GroupHdr *__restrict__ hdr,
@@ -841,11 +850,11 @@ __global__ __launch_bounds__(256) void k_finalize_group(const GroupHdr *__restri
     const TickJob &J = jobs[tick_job(jobs, hdr->njobs, kTickFinal, blockIdx.x)];
     const DevPtrs &P = J.P;
     const Dims &d = J.d;
-    finalize_body(P.partial, P.cmax, d.S, d.p, J.n_mt, d.n, d.c_f32, d.chi, d.alpha, d.delta, d.scale, P.cost,
-                  P.parts, P.eps, blockIdx.x - J.start[kTickFinal]);
+    finalize_body(P.partial, P.cmax, d.S, d.p, J.n_mt, d.n, d.c_f32, d.chi, d.alpha, d.delta, d.scale, kSplitResidual,
+                  2.0, P.cost, P.parts, P.eps, blockIdx.x - J.start[kTickFinal]);
 }
 
-template <int ROWB, int COLB, int KT, int OCC>
+template <int ROWB, int COLB, int KT, int OCC, int NP = 2>
 static hipError_t mfma_launch(const DevPtrs &P, const Dims &d, const uint16_t *kidx, int count, hipStream_t st)
 {
     const int MT = 32 * ROWB, NT = 128 * COLB;
@@ -854,10 +863,14 @@ static hipError_t mfma_launch(const DevPtrs &P, const Dims &d, const uint16_t *k
     const int n_nt = (NS + NT - 1) / NT;
     const int tiles = n_mt * n_nt;
     const int per = (tiles + 7) / 8;
-    k_eval_mfma<ROWB, COLB, KT, OCC><<<per * 8, 256, 0, st>>>(P.Whi, P.Wlo, kidx, P.Ch32, d.n, d.n_pad, d.p, NS,
-                                                             n_mt, n_nt, P.partial);
+    k_eval_mfma<ROWB, COLB, KT, OCC, NP><<<per * 8, 256, 0, st>>>(P.Whi, P.Wlo, P.Wmd, kidx, P.Ch32, d.n, d.n_pad,
+                                                                 d.p, NS, n_mt, n_nt, P.partial);
     return hipGetLastError();
 }
+
+// Tile configurations the three-part split runs in (register-staged, and
+// their three LDS stages within the static limit).
+bool mfma_split3_config(int cfg) { return cfg == 0 || cfg == 2 || cfg == 3 || cfg == 5; }
 
 template <int ROWB, int COLB, int NST, int KINS, int OCC, int EARLY>
 static hipError_t pipe_launch(const DevPtrs &P, const Dims &d, const uint16_t *kidx, int count, hipStream_t st)
@@ -915,6 +928,15 @@ int mfma_k_tile(int cfg) { return kMfmaCfgs[cfg].kt; }
 hipError_t launch_mfma(const DevPtrs &P, const Dims &d, const uint16_t *kidx, int count, hipStream_t st)
 {
     if (count <= 0) return hipSuccess;
+    if (d.prec == kSplit3BF16) {
+        switch (d.mfma_cfg) {
+        case 0: return mfma_launch<4, 2, 32, 2, 3>(P, d, kidx, count, st);
+        case 2: return mfma_launch<4, 4, 32, 1, 3>(P, d, kidx, count, st);
+        case 3: return mfma_launch<2, 4, 32, 2, 3>(P, d, kidx, count, st);
+        case 5: return mfma_launch<2, 2, 64, 2, 3>(P, d, kidx, count, st);
+        default: return hipErrorInvalidValue;
+        }
+    }
     switch (d.mfma_cfg) {
     case 0: return mfma_launch<4, 2, 32, 2>(P, d, kidx, count, st);
     case 1: return mfma_launch<4, 2, 64, 1>(P, d, kidx, count, st);
@@ -972,8 +994,10 @@ hipError_t launch_finalize(const DevPtrs &P, const Dims &d, int count, int cfg, 
 {
     if (count <= 0) return hipSuccess;
     const int n_mt = mfma_partial_tiles(d, cfg);
+    const bool three = d.prec == kSplit3BF16;
     k_finalize_split<<<(count + 3) / 4, 256, 0, st>>>(P.partial, P.cmax, count, d.p, n_mt, d.n, d.c_f32, d.chi,
-                                                      d.alpha, d.delta, d.scale, P.cost, P.parts, P.eps);
+                                                      d.alpha, d.delta, d.scale, three ? kSplit3Residual : kSplitResidual,
+                                                      three ? 3.0 : 2.0, P.cost, P.parts, P.eps);
     return hipGetLastError();
 }
 

@@ -36,7 +36,7 @@ bool is_valid_combo(int prec, int kern)
 {
     return (prec == GA_PREC_FP64 && kern == GA_KERN_PLAIN) ||
            (prec == GA_PREC_FP32 && (kern == GA_KERN_PLAIN || kern == GA_KERN_BATCHED)) ||
-           (prec == GA_PREC_SPLIT_BF16 && kern == GA_KERN_BATCHED);
+           ((prec == GA_PREC_SPLIT_BF16 || prec == GA_PREC_SPLIT3_BF16) && kern == GA_KERN_BATCHED);
 }
 
 bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0; }
@@ -58,7 +58,8 @@ std::string check_params(const ga_params *q)
     if (q->c_symmetric != 0 && q->c_symmetric != 1) return "c_symmetric must be 0 or 1";
     if (q->multihop != 0 && q->multihop != 1) return "multihop must be 0 or 1";
     if (!is_valid_combo(q->precision, q->kernel))
-        return "precision/kernel must be FP64+PLAIN, FP32+PLAIN, FP32+BATCHED or SPLIT_BF16+BATCHED";
+        return "precision/kernel must be FP64+PLAIN, FP32+PLAIN, FP32+BATCHED, SPLIT_BF16+BATCHED or "
+               "SPLIT3_BF16+BATCHED";
     return "";
 }
 
@@ -94,7 +95,7 @@ Dims make_dims(const ga_params *q, ga_dtype cdt, ga_dtype wdt)
 
 // Offsets of every device buffer; the same walk sizes and carves.
 struct Carve {
-    size_t C, Ct, Ct32, W, W32, Ctr, Whi, Wlo, O, D, dsum, hubs, kidx, cost, parts, eps, cmax, Ch32, partial, anc, anc_cost,
+    size_t C, Ct, Ct32, W, W32, Ctr, Whi, Wlo, Wmd, O, D, dsum, hubs, kidx, cost, parts, eps, cmax, Ch32, partial, anc, anc_cost,
         anc_parts, best, best_cost, gen, stats, cand, cand_cnt, cand_cost, cand_parts, kidx_one, scratch, tbuf, slot_r, slot_c, slot_s, slot_done, handled, choice, total_slots, extra_r, extra_c, nextra, sync,
         enum_state, enum_best, binom;
     size_t total;
@@ -106,7 +107,7 @@ Carve carve(const Dims &d, int c_symmetric)
     Carve c{};
     const size_t n2 = (size_t)d.n * d.n, np2 = (size_t)d.n_pad * d.n_pad;
     const size_t cs = d.c_f32 ? 4 : 8, ws = d.w_f32 ? 4 : 8;
-    const bool split = d.prec == kSplitBF16;
+    const bool split = split_mode(d.prec);
     // C, its transpose and the FP32 copy carry one row more: the FP32 copy's
     // extra row is +inf, the allocation scan's padding hub.
     c.C = L.take((n2 + d.n) * cs);
@@ -118,6 +119,7 @@ Carve carve(const Dims &d, int c_symmetric)
     // one pair of split buffers, in the layout the current tile configuration reads
     c.Whi = split ? L.take(np2 * 2) : (size_t)-1;
     c.Wlo = split ? L.take(np2 * 2) : (size_t)-1;
+    c.Wmd = d.prec == kSplit3BF16 ? L.take(np2 * 2) : (size_t)-1;
     c.O = L.take((size_t)d.n * 8);
     c.D = L.take((size_t)d.n * 8);
     c.dsum = L.take((size_t)d.n * 8);
@@ -294,7 +296,7 @@ void prof_events(ga_ctx *ctx, hipEvent_t *a, hipEvent_t *b)
 // they hold.  Never called during graph capture.
 ga_status ensure_w_layout(ga_ctx *ctx, int cfg)
 {
-    if (ctx->d.prec != kSplitBF16) return GA_OK;
+    if (!split_mode(ctx->d.prec)) return GA_OK;
     const int want = mfma_w_layout(ctx->d, cfg);
     if (want == ctx->wlayout) return GA_OK;
     HIPCHK(launch_w_layout(ctx->P, ctx->d, want, ctx->st));
@@ -488,7 +490,7 @@ static ga_status init_ctx(const ga_params *q, const void *C, ga_dtype cdt, const
         if ((cdt != GA_DT_F64 && cdt != GA_DT_F32) || (wdt != GA_DT_F64 && wdt != GA_DT_F32))
             return fail(nullptr, GA_ERR_INVALID, "unknown dtype");
         if (!C || !W) return fail(nullptr, GA_ERR_INVALID, "C and W must be host arrays");
-        const bool split = q->precision == GA_PREC_SPLIT_BF16;
+        const bool split = q->precision == GA_PREC_SPLIT_BF16 || q->precision == GA_PREC_SPLIT3_BF16;
         e = cdt == GA_DT_F32 ? check_matrix<float>(C, q->n, false) : check_matrix<double>(C, q->n, false);
         if (!e.empty()) return fail(nullptr, GA_ERR_INVALID, "C: " + e);
         e = wdt == GA_DT_F32 ? check_matrix<float>(W, q->n, split) : check_matrix<double>(W, q->n, split);
@@ -560,6 +562,7 @@ static ga_status init_ctx(const ga_params *q, const void *C, ga_dtype cdt, const
         P.Ctr = at<double>(b, c.Ctr);
         P.Whi = at<uint16_t>(b, c.Whi);
         P.Wlo = at<uint16_t>(b, c.Wlo);
+        P.Wmd = at<uint16_t>(b, c.Wmd);
         P.Whsw = P.Wfhsw = P.Whi;
         P.Wlsw = P.Wflsw = P.Wlo;
         P.O = at<double>(b, c.O);
@@ -615,7 +618,7 @@ static ga_status init_ctx(const ga_params *q, const void *C, ga_dtype cdt, const
             return dev_fail(he, "copy W");
         if ((he = launch_prep(P, d, ctx->st)) != hipSuccess) return dev_fail(he, "prep");
         if ((he = launch_shortest_paths(P, d, ctx->st)) != hipSuccess) return dev_fail(he, "shortest paths");
-        if (d.prec == kSplitBF16) {
+        if (split_mode(d.prec)) {
             if ((he = launch_w_layout(P, d, mfma_w_layout(d, d.mfma_cfg), ctx->st)) != hipSuccess)
                 return dev_fail(he, "split of W");
             ctx->wlayout = mfma_w_layout(d, d.mfma_cfg);
@@ -1016,6 +1019,8 @@ ga_status ga_set_tile_config(ga_ctx *ctx, int32_t cfg)
 {
     CTXCHK(ctx);
     if (cfg < 0 || cfg >= mfma_num_configs()) return fail(ctx, GA_ERR_INVALID, "no such tile configuration");
+    if (ctx->d.prec == kSplit3BF16 && !mfma_split3_config(cfg))
+        return fail(ctx, GA_ERR_INVALID, "the three-part split runs in tile configurations 0, 2, 3 and 5 only");
     if (ctx->d.mfma_cfg != cfg) drop_graph(ctx);
     ctx->d.mfma_cfg = cfg;
     return ensure_w_layout(ctx, cfg);

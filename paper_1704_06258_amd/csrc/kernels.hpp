@@ -48,6 +48,7 @@ hipError_t launch_finalize(const DevPtrs &P, const Dims &d, int count, int cfg, 
 int mfma_partial_tiles(const Dims &d, int cfg);
 bool mfma_folds(const Dims &d, int cfg);
 int mfma_w_layout(const Dims &d, int cfg);
+bool mfma_split3_config(int cfg);
 int finalize_blocks(int count);
 hipError_t launch_finalize_group(const GroupHdr *hdr, const TickJob *jobs, int njobs, int blocks, hipStream_t st);
 bool mfma_groupable(const Dims &d, int cfg);

@@ -82,24 +82,31 @@ __device__ inline uint16_t bf16_rne_bits(double x)
 
 __device__ inline double bf16_to_double(uint16_t b) { return (double)__uint_as_float(((uint32_t)b) << 16); }
 
+// mid non-null: the three-part split hi, mid, lo, each the bf16 rounding of
+// what the parts before it leave (the remainders are exact in binary64).
 template <typename T>
 __global__ void k_split_bf16(const T *__restrict__ W, int n, int n_pad, uint16_t *__restrict__ hi,
-                             uint16_t *__restrict__ lo)
+                             uint16_t *__restrict__ lo, uint16_t *__restrict__ mid)
 {
 #pragma clang fp contract(off)
     size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     size_t total = (size_t)n_pad * n_pad;
     if (idx >= total) return;
     int i = (int)(idx / n_pad), j = (int)(idx % n_pad);
-    uint16_t h = 0, l = 0;
+    uint16_t h = 0, m = 0, l = 0;
     if (i < n && j < n) {
         double x = (double)W[(size_t)i * n + j];
         h = bf16_rne_bits(x);
         double rem = x - bf16_to_double(h);   // exact (Sterbenz)
+        if (mid) {
+            m = bf16_rne_bits(rem);
+            rem = rem - bf16_to_double(m);    // exact
+        }
         l = bf16_rne_bits(rem);
     }
     hi[idx] = h;
     lo[idx] = l;
+    if (mid) mid[idx] = m;
 }
 
 // The same split written in fragment order: one thread per 16-byte chunk of
@@ -290,9 +297,9 @@ hipError_t launch_w_layout(const DevPtrs &P, const Dims &d, int layout, hipStrea
     if (layout == kWRowMajor) {
         const unsigned g = (unsigned)((cnt + tb - 1) / tb);
         if (d.w_f32)
-            k_split_bf16<float><<<g, tb, 0, st>>>((const float *)P.W, n, d.n_pad, P.Whi, P.Wlo);
+            k_split_bf16<float><<<g, tb, 0, st>>>((const float *)P.W, n, d.n_pad, P.Whi, P.Wlo, P.Wmd);
         else
-            k_split_bf16<double><<<g, tb, 0, st>>>((const double *)P.W, n, d.n_pad, P.Whi, P.Wlo);
+            k_split_bf16<double><<<g, tb, 0, st>>>((const double *)P.W, n, d.n_pad, P.Whi, P.Wlo, P.Wmd);
         return hipGetLastError();
     }
     const unsigned gs = (unsigned)((cnt / 8 + tb - 1) / tb);

@@ -18,11 +18,13 @@ LIB_PATH = os.path.join(HERE, "libhubga.so")
 
 GA_OK, GA_ERR_INVALID, GA_ERR_OOM, GA_ERR_DEVICE, GA_ERR_STATE = range(5)
 GA_DT_F64, GA_DT_F32 = 0, 1
-GA_PREC_FP64, GA_PREC_FP32, GA_PREC_SPLIT_BF16 = 0, 1, 2
+GA_PREC_FP64, GA_PREC_FP32, GA_PREC_SPLIT_BF16, GA_PREC_SPLIT3_BF16 = 0, 1, 2, 3
 GA_KERN_PLAIN, GA_KERN_BATCHED = 0, 1
 
-PRECISIONS = {"fp64": GA_PREC_FP64, "fp32": GA_PREC_FP32, "split_bf16": GA_PREC_SPLIT_BF16}
-DEFAULT_KERNEL = {GA_PREC_FP64: GA_KERN_PLAIN, GA_PREC_FP32: GA_KERN_PLAIN, GA_PREC_SPLIT_BF16: GA_KERN_BATCHED}
+PRECISIONS = {"fp64": GA_PREC_FP64, "fp32": GA_PREC_FP32, "split_bf16": GA_PREC_SPLIT_BF16,
+              "split3_bf16": GA_PREC_SPLIT3_BF16}
+DEFAULT_KERNEL = {GA_PREC_FP64: GA_KERN_PLAIN, GA_PREC_FP32: GA_KERN_PLAIN, GA_PREC_SPLIT_BF16: GA_KERN_BATCHED,
+                  GA_PREC_SPLIT3_BF16: GA_KERN_BATCHED}
 KERNELS = {"plain": GA_KERN_PLAIN, "batched": GA_KERN_BATCHED}
 
 # Every symbol declared in include/hubga.h.
