@@ -5,9 +5,12 @@
 // distance matrix are read coalesced (lane = node).
 //
 // Outputs per individual s: kidx[s][i] = hub position (kNoHub in the padding
-// up to n_pad), the largest cluster size, and (when asked) the collection and
-// distribution sums Cc = sum_i O_i c_i, Dd = sum_i D_i c_i with c_i =
-// C[i][a_i] in binary64 (a fixed summation order), and the FP32 hub-to-hub table
+// up to n_pad), the largest cluster size, and (when asked, in the approximate
+// modes) the collection and distribution sums Cc = sum_i O_i c_i, Dd = sum_i
+// D_i c_i in binary64 (a fixed summation order) with c_i = C[i][a_i] rounded
+// to FP32 -- the scan's own minimum, no second gather; its rounding, 2^-24
+// relative, is the one the error bounds already allow for every FP32
+// distance -- and the FP32 hub-to-hub table
 // Ch32[s][k][l] = C[h_k][h_l] used by the batched kernel's epilogue (the
 // shortest-path distance Ctr[h_k][h_l] instead under multi-hop routing).
 #include "kernels.hpp"
@@ -124,14 +127,18 @@ __device__ __forceinline__ void alloc_body(const int32_t *__restrict__ hubs, int
         }
         // hubs keep themselves; FP32 ties are rescanned in the instance dtype
         // (strict <, ties to the smaller hub id; +inf padding ties only when
-        // every distance is +inf: rescanned too)
+        // every distance is +inf: rescanned too).  c32: the FP32 distance to
+        // the chosen hub (a tie's winner has the tied FP32 value).
+        float c32[T];
 #pragma unroll
         for (int t = 0; t < T; ++t) {
             const int i = ii[t];
+            c32[t] = bd[t];
             if (i >= n) continue;
             const int self = sh_pos[i];
             if (self != 0xFF) {
                 best[t] = self;
+                c32[t] = Ct32[(size_t)i * n + i];
             } else if (at_min[t] > 1) {
                 int b = 0;
                 CT be = Ct[(size_t)hrow[0] * n + i];
@@ -154,7 +161,7 @@ __device__ __forceinline__ void alloc_body(const int32_t *__restrict__ hubs, int
 #pragma unroll
                 for (int u = 0; u < 2; ++u) {
                     const int t = t0 + u;
-                    cv[u] = (double)Ct[(size_t)sh_h[best[t]] * n + ic[t]];
+                    cv[u] = (double)c32[t];
                     ov[u] = O[ic[t]];
                     dv[u] = D[ic[t]];
                 }

@@ -133,8 +133,9 @@ def test_evaluate_split_bf16_within_bound(name, mk, count):
     err = np.abs(out["cost"] - ref_c) / ref_c
     assert np.all(err <= out["eps"]), (err.max(), out["eps"].min())
     assert np.all(out["eps"] < 1e-3)
-    # collection and distribution sums are binary64 tree sums
-    assert np.allclose(out["parts"][:, [0, 2]], ref_p[:, [0, 2]], rtol=1e-12, atol=0)
+    # collection and distribution sums: binary64 tree sums of FP32 distances
+    # (one rounding, 2^-24 relative, each)
+    assert np.allclose(out["parts"][:, [0, 2]], ref_p[:, [0, 2]], rtol=2.0 ** -23, atol=0)
     if name.startswith("clustered"):
         assert err.max() <= 1e-6, err.max()
 

@@ -46,7 +46,7 @@ def test_vec_within_bound(name, mk, count):
         out = s.evaluate(hubs)
     err = np.abs(out["cost"] - ref) / np.maximum(ref, 1e-300)
     assert np.all(out["eps"] > 0) and np.all(err <= out["eps"]), (err.max(), out["eps"].min())
-    assert np.allclose(out["parts"][:, [0, 2]], ref_parts[:, [0, 2]], rtol=1e-12, atol=0)
+    assert np.allclose(out["parts"][:, [0, 2]], ref_parts[:, [0, 2]], rtol=2.0 ** -23, atol=0)
 
 
 def test_vec_trajectory_equals_oracle():
