@@ -244,7 +244,7 @@ struct ga_batch {
     int njobs = 0, total_tiles = 0, min_p = 0, sel_threads = 64;
     int round_robin = 0;   // some context is folded: tiles go round robin over the XCDs
     int blocks[kTickPhases] = {};
-    size_t lds_recheck = 0;
+    size_t lds_recheck = 0, lds_recheck_wide = 0;
     // One grouped generation captured as a graph, its grids sized to a
     // capacity; every composition that fits replays it (the kernels read the
     // composition from the header), a larger one is captured anew.
@@ -253,7 +253,7 @@ struct ga_batch {
     bool graph_failed = false;
     int cap_blocks[kTickPhases] = {};
     int cap_grid = 0, cap_kins = 0, cap_sel = 0;
-    size_t cap_lds = 0;
+    size_t cap_lds = 0, cap_lds_wide = 0;
 };
 
 namespace {
@@ -527,7 +527,7 @@ static ga_status init_ctx(const ga_params *q, const void *C, ga_dtype cdt, const
                     max_lds = optin;
             }
             (void)hipGetLastError();
-            const size_t need = recheck_lds(d.n, d.p) + 4096;   // + the kernels' static LDS
+            const size_t need = std::max(recheck_lds(d.n, d.p), recheck_wide_lds(d.n, d.p)) + 4096;   // + static LDS
             if (need > (size_t)max_lds)
                 return fail(nullptr, GA_ERR_INVALID, "n too large for this device's LDS (exact kernels)");
         }
@@ -1052,7 +1052,7 @@ size_t batch_table_bytes() { return batch_tick_offset() + sizeof(TickJob) * kMax
 // selection block size, re-evaluation LDS); the kernels take the composition
 // from the table's header.
 hipError_t launch_grouped(const ga_batch *b, const int *grid, int mfma_grid, int kins, int sel_threads,
-                          size_t lds_recheck)
+                          size_t lds_recheck, size_t lds_recheck_wide)
 {
     const GroupHdr *hdr = (const GroupHdr *)b->d_tab;
     const void *mjobs = (const char *)b->d_tab + ga_batch::kHdrBytes;
@@ -1064,7 +1064,7 @@ hipError_t launch_grouped(const ga_batch *b, const int *grid, int mfma_grid, int
     if ((e = launch_mfma_group(hdr, mjobs, mfma_grid, b->cfg, kins, b->st)) != hipSuccess) return e;
     if ((e = launch_finalize_group(hdr, tjobs, nj, grid[kTickFinal], b->st)) != hipSuccess) return e;
     if ((e = launch_select1_group(hdr, tjobs, nj, grid[kTickSel1], sel_threads, b->st)) != hipSuccess) return e;
-    return launch_recheck_group(hdr, tjobs, nj, lds_recheck, b->st);
+    return launch_recheck_group(hdr, tjobs, nj, lds_recheck, lds_recheck_wide, b->st);
 }
 
 void drop_batch_graph(ga_batch *b)
@@ -1089,7 +1089,7 @@ void capture_batch_generation(ga_batch *b)
 {
     const int kins = mfma_group_kins(b->cfg, b->min_p);
     bool fits = b->gexec && kins <= b->cap_kins && b->sel_threads <= b->cap_sel && b->lds_recheck <= b->cap_lds &&
-                b->total_tiles <= b->cap_grid;
+                b->lds_recheck_wide <= b->cap_lds_wide && b->total_tiles <= b->cap_grid;
     for (int q = 0; q < kTickPhases && fits; ++q) fits = b->blocks[q] <= b->cap_blocks[q];
     if (fits || b->graph_failed) return;
     drop_batch_graph(b);
@@ -1098,12 +1098,13 @@ void capture_batch_generation(ga_batch *b)
     const int cap_grid = grid_cap(b->total_tiles), cap_kins = std::max(kins, b->cap_kins);
     const int cap_sel = std::max(b->sel_threads, b->cap_sel);
     const size_t cap_lds = std::max(b->lds_recheck, b->cap_lds);
+    const size_t cap_lds_wide = std::max(b->lds_recheck_wide, b->cap_lds_wide);
     if (hipStreamBeginCapture(b->st, hipStreamCaptureModeRelaxed) != hipSuccess) {
         (void)hipGetLastError();
         b->graph_failed = true;
         return;
     }
-    const hipError_t le = launch_grouped(b, caps, cap_grid, cap_kins, cap_sel, cap_lds);
+    const hipError_t le = launch_grouped(b, caps, cap_grid, cap_kins, cap_sel, cap_lds, cap_lds_wide);
     hipGraph_t g = nullptr;
     const hipError_t ee = hipStreamEndCapture(b->st, &g);
     hipGraphExec_t x = nullptr;
@@ -1120,6 +1121,7 @@ void capture_batch_generation(ga_batch *b)
     b->cap_kins = cap_kins;
     b->cap_sel = cap_sel;
     b->cap_lds = cap_lds;
+    b->cap_lds_wide = cap_lds_wide;
 }
 
 }  // namespace
@@ -1190,7 +1192,7 @@ ga_status ga_batch_set(ga_batch *b, ga_ctx *const *ctxs, int32_t count)
     std::vector<TickJob> tj(njobs);
     int min_p = 1 << 30, sel_threads = 64, round_robin = 0;
     int blocks[kTickPhases] = {};
-    size_t lds_recheck = 0;
+    size_t lds_recheck = 0, lds_recheck_wide = 0;
     for (int j = 0; j < njobs; ++j) {
         const ga_ctx *c = grouped[j];
         const Dims &d = c->d;
@@ -1200,6 +1202,7 @@ ga_status ga_batch_set(ga_batch *b, ga_ctx *const *ctxs, int32_t count)
         round_robin |= (int)mfma_folds(d, b->cfg);
         sel_threads = std::max(sel_threads, select_threads(d.m));
         lds_recheck = std::max(lds_recheck, recheck_lds(d.n, d.p));
+        lds_recheck_wide = std::max(lds_recheck_wide, recheck_wide_lds(d.n, d.p));
         TickJob &J = tj[j];
         memset(&J, 0, sizeof(J));
         J.P = c->P;
@@ -1214,7 +1217,7 @@ ga_status ga_batch_set(ga_batch *b, ga_ctx *const *ctxs, int32_t count)
             blocks[q] += J.blocks[q];
         }
     }
-    if (njobs && lds_recheck > recheck_group_lds_cap())
+    if (njobs && std::max(lds_recheck, lds_recheck_wide) > recheck_group_lds_cap())
         return fail(nullptr, GA_ERR_INVALID, "batch: re-evaluation LDS exceeds the device limit");
     // tables (header, matrix-core jobs, TickJobs), copied in stream order
     // after earlier generations, into the fixed layout
@@ -1248,6 +1251,7 @@ ga_status ga_batch_set(ga_batch *b, ga_ctx *const *ctxs, int32_t count)
     b->round_robin = round_robin;
     b->sel_threads = sel_threads;
     b->lds_recheck = lds_recheck;
+    b->lds_recheck_wide = lds_recheck_wide;
     memcpy(b->blocks, blocks, sizeof(blocks));
     // side streams (default priority) for the contexts stepped alone
     const int nside = std::min((int)solo.size(), 16);
@@ -1308,7 +1312,8 @@ ga_status ga_batch_step(ga_batch *b, int32_t generations)
                 e = hipGraphLaunch(b->gexec, b->st);
             else
                 e = launch_grouped(b, b->blocks, ((b->total_tiles + 7) / 8) * 8,
-                                   mfma_group_kins(b->cfg, b->min_p), b->sel_threads, b->lds_recheck);
+                                   mfma_group_kins(b->cfg, b->min_p), b->sel_threads, b->lds_recheck,
+                                   b->lds_recheck_wide);
             if (e != hipSuccess) return dev_fail(e, "grouped generation");
         }
         if (nsolo)   // join

@@ -36,8 +36,10 @@ hipError_t prepare_plain_kernels(int max_lds);
 hipError_t launch_recheck(const DevPtrs &P, const Dims &d, hipStream_t st);
 hipError_t launch_p0_exact(const DevPtrs &P, const Dims &d, hipStream_t st);
 size_t recheck_lds(int n, int p);
+size_t recheck_wide_lds(int n, int p);
 size_t recheck_group_lds_cap();
-hipError_t launch_recheck_group(const GroupHdr *hdr, const TickJob *jobs, int njobs, size_t lds, hipStream_t st);
+hipError_t launch_recheck_group(const GroupHdr *hdr, const TickJob *jobs, int njobs, size_t lds, size_t lds_wide,
+                                hipStream_t st);
 hipError_t prepare_recheck_kernels(int max_lds);
 
 // batched matrix-core evaluation (eval_mfma.hip)

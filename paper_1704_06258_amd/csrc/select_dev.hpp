@@ -15,18 +15,24 @@ __device__ inline bool better(double v, int i, double bv, int bi)
 // publishes its global writes (device-scope fence) before counting itself in;
 // the last one fences again before reading them and resets the counter for
 // the next launch.
+// Device-scope release and acquire fences.  A release writes the XCD's L2
+// back; only an acquire invalidates it (a full fence would do both, and the
+// invalidation drops what every other workgroup on that XCD has cached).
+__device__ __forceinline__ void release_agent() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+__device__ __forceinline__ void acquire_agent() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+
 __device__ inline bool last_block(int *counter, int nblocks)
 {
     __shared__ int is_last;
     __syncthreads();
     if (threadIdx.x == 0) {
-        __threadfence();
+        release_agent();
         const int prev = atomicAdd(counter, 1);
         is_last = prev == nblocks - 1;
         if (is_last) atomicExch(counter, 0);
     }
     __syncthreads();
-    if (is_last) __threadfence();
+    if (is_last) acquire_agent();
     return is_last != 0;
 }
 

@@ -279,7 +279,33 @@ def test_certified_selection_with_planted_ties(precision, elitist, n, p):
     if not elitist:
         assert stats["rechecks"] > 0
     if not elitist and n == 3:
-        assert stats["rechecks"] > 12 * 4 * 16   # beyond the 16 column-parallel slots per island
+        # beyond the 16 column-parallel slots per island: all 64 slots are in
+        # use, which is the range of the wide re-evaluation kernel
+        assert stats["rechecks"] > 12 * 4 * 16
+
+
+@pytest.mark.parametrize("n,p,w32,precision", [
+    (200, 7, False, "split_bf16"),   # rows 16-byte aligned: 16-byte stage loads, binary64 W
+    (203, 7, False, "split_bf16"),   # odd n: element loads
+    (200, 7, True, "fp32"),          # FP32 W, 16-byte loads
+    (203, 7, True, "split_bf16"),    # FP32 W, element loads
+    (90, 58, False, "split_bf16"),   # p past the wide kernel's LDS limit: the narrow kernel takes every burst
+])
+def test_reevaluation_bursts_every_load_path(n, p, w32, precision):
+    """64 islands whose first generations each carry a candidate: bursts of
+    24 or more slots go to the wide re-evaluation kernel (four candidates per
+    workgroup) unless p is past its limit; the trajectory equals the
+    oracle's, exact costs included."""
+    inst = I.uniform(seed=90 + n + p, n=n, p=p)
+    if w32:
+        inst = I.Instance(inst.name, inst.C, inst.W.astype(np.float32), inst.p, inst.chi, inst.alpha, inst.delta)
+    st = oracle_trajectory(inst, 4, S=2048, m=32, n1=3, seed=4)
+    with make(inst, population=2048, island_size=32, n1=3, seed=4, precision=precision) as s:
+        s.step(1)
+        burst = s.stats()["islands_rechecked"]
+        s.step(3)
+        assert_same_state(s, st)
+    assert burst >= 24, burst
 
 
 def test_every_tile_config_within_bound_and_same_trajectory():
