@@ -57,7 +57,7 @@ constexpr int kRwRows = 32;            // W rows of a ring stage
 constexpr int kRwDepth = 4;            // stages in flight in registers
 constexpr int kRwSum = 1024;           // tbuf values a wave stages at a time to sum a slot's T
 constexpr int kRcWideMin = 24;         // slots in use from which the wide kernel takes a launch
-constexpr int kRcWideBlocks = 1024;    // its persistent workgroups
+constexpr int kRcWideBlocks = 512;     // its persistent workgroups (two to a CU fit)
 // Wide item LDS: the W ring (two stages of binary64 or FP32 values), the
 // stages' hub positions ([2][slot][row]), then the four slots' p x p tables.
 constexpr size_t kRwRing = (size_t)2 * kRwRows * kRwCols * 8;

@@ -250,9 +250,17 @@ __device__ inline void decide_generation(const SelState &S, int32_t *__restrict_
         if (!take) sb = -1;
         const double fr = take ? v : fa;
         choice[r] = sb;
-        if (take) {
+        if (take) {   // the island's new hub list, its loads issued together
             S.anc_cost[r] = v;
             for (int q = 0; q < 3; ++q) S.anc_parts[3 * (size_t)r + q] = vp[q];
+            for (int k0 = 0; k0 < p; k0 += 8) {
+                int h[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) h[u] = k0 + u < p ? S.children[(size_t)sb * p + k0 + u] : 0;
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (k0 + u < p) S.anc[(size_t)r * p + k0 + u] = h[u];
+            }
         }
         cc += cnt;
         cr += cnt > 0;
@@ -306,16 +314,14 @@ __device__ inline void decide_generation(const SelState &S, int32_t *__restrict_
     const int rs = wi[0], sbs = wsb[0];
     const double vs = wv[0];
     auto hub_of_rs = [&](int k) { return sbs >= 0 ? S.children[(size_t)sbs * p + k] : S.anc[(size_t)rs * p + k]; };
-    // hub lists: the global step gives every other island rs's; else each island its choice
-    for (int e = tid; e < S.R * p; e += nt) {
-        const int r = e / p, k = e - r * p;
-        if (gstep && r != rs) {
-            S.anc[e] = hub_of_rs(k);
-        } else {
-            const int sb = choice[r];
-            if (sb >= 0) S.anc[e] = S.children[(size_t)sb * p + k];
+    // hub lists: each island took its choice above; the global step gives
+    // every other island rs's (island rs's own list is read from the child
+    // it took, or is its unchanged ancestor)
+    if (gstep)
+        for (int e = tid; e < S.R * p; e += nt) {
+            const int r = e / p, k = e - r * p;
+            if (r != rs) S.anc[e] = hub_of_rs(k);
         }
-    }
     if (gstep)
         for (int r = tid; r < S.R; r += nt)
             if (r != rs) {
