@@ -127,16 +127,18 @@ __host__ __device__ inline RcView rc_generation_view(const DevPtrs &P, const Dim
 }
 
 // acc + buf[0] + buf[1] + ... + buf[cnt-1], left to right (one lane; buf
-// 16-byte aligned, cnt <= kRcChain values of capacity).  Two register sets of
-// 16 values take turns: one is added while the other's reads are in flight;
-// the reads ahead stay inside the buffer (clamped), so no set is loaded on
-// one path only.
-template <int CAP = kRcChain>
+// 16-byte aligned, cnt <= CAP values of capacity).  SETS (2 or 3) register
+// sets of 16 values take turns: while one is added, the reads of the others
+// are in flight (three sets hide a longer LDS latency, for 32 more
+// registers).  The reads ahead stay inside the buffer (clamped), so no set is
+// loaded on one path only; a clamped set is never added.
+template <int CAP = kRcChain, int SETS = 2>
 __device__ inline double chain_sum(double acc, const double *buf, int cnt)
 {
 #pragma clang fp contract(off)
+    static_assert(SETS == 2 || SETS == 3, "two or three register sets");
     const double2 *b2 = (const double2 *)buf;
-    double2 A[8], B[8];
+    double2 A[8], B[8], C[8];
     auto load = [&](double2(&X)[8], int at) {
         at = at < CAP - 16 ? at : CAP - 16;
 #pragma unroll
@@ -152,15 +154,35 @@ __device__ inline double chain_sum(double acc, const double *buf, int cnt)
     };
     load(A, 0);
     int i = 0;
-    for (; i + 32 <= cnt; i += 32) {
-        load(B, i + 16);
-        add(A);
-        load(A, i + 32);
-        add(B);
-    }
-    if (i + 16 <= cnt) {   // A holds buf[i .. i+15]
-        add(A);
-        i += 16;
+    if constexpr (SETS == 3) {
+        load(B, 16);
+        for (; i + 48 <= cnt; i += 48) {
+            load(C, i + 32);
+            add(A);
+            load(A, i + 48);
+            add(B);
+            load(B, i + 64);
+            add(C);
+        }
+        if (i + 16 <= cnt) {   // A and B hold buf[i .. i+31]
+            add(A);
+            i += 16;
+            if (i + 16 <= cnt) {
+                add(B);
+                i += 16;
+            }
+        }
+    } else {
+        for (; i + 32 <= cnt; i += 32) {
+            load(B, i + 16);
+            add(A);
+            load(A, i + 32);
+            add(B);
+        }
+        if (i + 16 <= cnt) {   // A holds buf[i .. i+15]
+            add(A);
+            i += 16;
+        }
     }
     for (; i < cnt; ++i) acc = acc + buf[i];
     return acc;
@@ -581,7 +603,7 @@ __device__ __forceinline__ void rc_finish_group(const DevPtrs &P, const Dims &d,
                 if (u * 64 + lane < cnt) buf[u * 64 + lane] = v[u];
         }
         __syncthreads();
-        if (mine && lane == 0) acc = chain_sum<kRwSum>(acc, buf, cnt);
+        if (mine && lane == 0) acc = chain_sum<kRwSum, 3>(acc, buf, cnt);
         __syncthreads();
     }
     if (mine && lane == 0) {

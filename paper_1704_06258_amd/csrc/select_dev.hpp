@@ -197,18 +197,25 @@ __device__ inline void global_step(const SelState &S)
 // size up to 1024; choice: R ints of scratch.
 __device__ inline void decide_generation(const SelState &S, int32_t *__restrict__ choice)
 {
-    __shared__ double wv[16];
-    __shared__ int wi[16], wsb[16], wo[16], wcc[16], wcr[16];
+    __shared__ double wv[16], wp[16][3];
+    __shared__ int wi[16], wsb[16], wcc[16], wcr[16];
     __shared__ double sh_parts[3];
     const int tid = threadIdx.x, nt = blockDim.x, m = S.m, p = S.p;
     const int64_t g = *S.gen;
     const double best0 = S.best_cost[0];
     const bool gstep = (g + 1) % S.n1 == 0;
-    double bv = 0.0;
-    int bi = -1, bsb = -1, bo = -1, cc = 0, cr = 0;
+    int64_t st[3] = {0, 0, 0};   // counters, read ahead of the islands' loads
+    if (tid == 0)
+        for (int q = 0; q < 3; ++q) st[q] = S.stats[1 + q];
+    // the best island so far: its cost, index, child and parts (carried
+    // through the reductions, so no load waits on them)
+    double bv = 0.0, bp[3] = {0.0, 0.0, 0.0};
+    int bi = -1, bsb = -1, cc = 0, cr = 0;
     for (int r = tid; r < S.R; r += nt) {
         const int cnt = S.cand_cnt[r];
         const double fa = S.anc_cost[r];
+        double ap[3];
+        for (int q = 0; q < 3; ++q) ap[q] = S.anc_parts[3 * (size_t)r + q];
         // the first four candidates' costs, children and parts are read
         // together (valid addresses whatever cnt is), the rest in a loop
         constexpr int Q = 4;
@@ -246,7 +253,6 @@ __device__ inline void decide_generation(const SelState &S, int32_t *__restrict_
             for (int q = 0; q < 3; ++q) vp[q] = S.cand_parts[3 * o + q];
         }
         const bool take = c >= 0 && (!S.elitist || v < fa);
-        const int o = take ? r * m + c : -1;
         if (!take) sb = -1;
         const double fr = take ? v : fa;
         choice[r] = sb;
@@ -268,17 +274,19 @@ __device__ inline void decide_generation(const SelState &S, int32_t *__restrict_
             bv = fr;
             bi = r;
             bsb = sb;
-            bo = o;
+            for (int q = 0; q < 3; ++q) bp[q] = take ? vp[q] : ap[q];
         }
     }
     for (int off = 32; off > 0; off >>= 1) {
         const double ov = __shfl_xor(bv, off);
-        const int oi = __shfl_xor(bi, off), osb = __shfl_xor(bsb, off), oo = __shfl_xor(bo, off);
+        const int oi = __shfl_xor(bi, off), osb = __shfl_xor(bsb, off);
+        double op[3];
+        for (int q = 0; q < 3; ++q) op[q] = __shfl_xor(bp[q], off);
         if (oi >= 0 && better(ov, oi, bv, bi)) {
             bv = ov;
             bi = oi;
             bsb = osb;
-            bo = oo;
+            for (int q = 0; q < 3; ++q) bp[q] = op[q];
         }
         cc += __shfl_xor(cc, off);
         cr += __shfl_xor(cr, off);
@@ -287,7 +295,7 @@ __device__ inline void decide_generation(const SelState &S, int32_t *__restrict_
         wv[tid >> 6] = bv;
         wi[tid >> 6] = bi;
         wsb[tid >> 6] = bsb;
-        wo[tid >> 6] = bo;
+        for (int q = 0; q < 3; ++q) wp[tid >> 6][q] = bp[q];
         wcc[tid >> 6] = cc;
         wcr[tid >> 6] = cr;
     }
@@ -298,7 +306,7 @@ __device__ inline void decide_generation(const SelState &S, int32_t *__restrict_
                 bv = wv[w];
                 bi = wi[w];
                 bsb = wsb[w];
-                bo = wo[w];
+                for (int q = 0; q < 3; ++q) bp[q] = wp[w][q];
             }
             cc += wcc[w];
             cr += wcr[w];
@@ -306,9 +314,7 @@ __device__ inline void decide_generation(const SelState &S, int32_t *__restrict_
         wv[0] = bv;
         wi[0] = bi;
         wsb[0] = bsb;
-        wo[0] = bo;
-        for (int q = 0; q < 3; ++q)
-            sh_parts[q] = bo >= 0 ? S.cand_parts[3 * (size_t)bo + q] : S.anc_parts[3 * (size_t)bi + q];
+        for (int q = 0; q < 3; ++q) sh_parts[q] = bp[q];
     }
     __syncthreads();
     const int rs = wi[0], sbs = wsb[0];
@@ -338,9 +344,9 @@ __device__ inline void decide_generation(const SelState &S, int32_t *__restrict_
     if (tid == 0) {
         *S.gen = g + 1;
         S.stats[0] = g + 1;
-        S.stats[1] += cc;
-        S.stats[2] += cr;
-        S.stats[3] += S.S;
+        S.stats[1] = st[0] + cc;
+        S.stats[2] = st[1] + cr;
+        S.stats[3] = st[2] + S.S;
     }
     __syncthreads();
 }
