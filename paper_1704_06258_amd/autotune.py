@@ -1,10 +1,14 @@
 """Tile autotuner for the batched split-bf16 evaluation kernel.
 
-For a live context it times every tile configuration of the batched kernel
-(ga_tile_config_count / ga_set_tile_config) on the context's own current
-population, with HIP events around each launch, keeps the fastest, and caches
-the choice in a JSON file keyed by (architecture, n bucket, p, population).
-Timing re-evaluates the population through ga_evaluate_dev, so the GA state
+For a live context it searches the tile configurations of the batched kernel
+(ga_tile_config_count / ga_set_tile_config: workgroup rows x columns, K tile,
+pipeline depth, each a compiled kernel) on the context's own current
+population, with HIP events around each launch, by successive halving: every
+configuration is timed briefly, the fastest third again with more launches,
+the best few once more, and the fastest of the last round wins.  The choice
+is cached in a JSON file keyed by (architecture, n bucket, p, population),
+with every configuration's (rows, cols, K tile) and time.  Timing
+re-evaluates the population through ga_evaluate_dev, so the GA state
 (ancestors, best, generation) is left untouched.
 """
 from __future__ import annotations
@@ -45,6 +49,26 @@ def time_config(solver, cfg, d_hubs, reps=5):
     return ms / max(k, 1)
 
 
+def successive_halving(candidates, time_fn, reps=(1, 3, 10), keep=(1 / 3, 3)):
+    """Fastest of `candidates` under `time_fn(c, r)` (mean ms over r launches):
+    round t times the survivors with reps[t] launches; after round t the best
+    keep[t] survive (a fraction of those timed, or a count; at least one).
+    Returns (best, {c: ms of its last round}, [survivors after each round])."""
+    alive = list(candidates)
+    times, rounds = {}, []
+    for t, r in enumerate(reps):
+        for c in alive:
+            times[c] = time_fn(c, r)
+        alive = sorted(alive, key=lambda c: (times[c], c))
+        if t < len(keep):
+            k = keep[t]
+            alive = alive[:max(1, int(round(k * len(alive))) if isinstance(k, float) else k)]
+        else:
+            alive = alive[:1]
+        rounds.append(list(alive))
+    return alive[0], times, rounds
+
+
 def autotune(solver, cache_path=DEFAULT_CACHE, force=False, reps=5):
     """Pick (and apply) the fastest tile configuration for this context.
     Returns {"config": c, "ms": {c: ms}, "cached": bool}."""
@@ -66,12 +90,12 @@ def autotune(solver, cache_path=DEFAULT_CACHE, force=False, reps=5):
         anc, _ = solver.ancestors()
         hubs = np.repeat(anc, solver.S // anc.shape[0], axis=0)
     d_hubs = torch.from_numpy(np.ascontiguousarray(hubs)).to(solver.device)
-    times = {}
-    for cfg in candidates:
-        times[cfg] = time_config(solver, cfg, d_hubs, reps)
-    best = min(times, key=times.get)
+    best, times, rounds = successive_halving(candidates, lambda c, r: time_config(solver, c, d_hubs, r),
+                                             reps=(1, 3, max(1, reps)))
     solver.set_tile_config(best)
-    cache[key] = {"config": best, "ms": times, "time": time.time()}
+    shapes = hubga.tile_configs()
+    cache[key] = {"config": best, "ms": times, "rounds": rounds, "shapes": {c: list(shapes[c]) for c in times},
+                  "time": time.time()}
     try:
         os.makedirs(os.path.dirname(cache_path), exist_ok=True)
         tmp = cache_path + ".tmp%d" % os.getpid()
@@ -80,4 +104,4 @@ def autotune(solver, cache_path=DEFAULT_CACHE, force=False, reps=5):
         os.replace(tmp, cache_path)
     except OSError:
         pass
-    return {"config": best, "ms": times, "cached": False}
+    return {"config": best, "ms": times, "rounds": rounds, "cached": False}
