@@ -205,7 +205,7 @@ __global__ __launch_bounds__(256, OCC) void k_eval_mfma(const uint16_t *__restri
                     const int i = M0 + a * 32 + 8 * (v >> 2) + 4 * half + (v & 3);
                     if (i < n) {
                         const int k = kr[i];
-                        sum += (double)acc[a][b][v] * (double)ch[k * p];
+                        sum = __builtin_fma((double)acc[a][b][v], (double)ch[k * p], sum);
                     }
                 }
             }
@@ -315,7 +315,9 @@ __device__ __forceinline__ void epi_stage_issue(const MfmaJob &J, int mt, int nt
 }
 
 // Epilogue of a pipelined tile: sum_i G[i][(s,l)] * C[h_k(i)][h_l] over the
-// tile's rows in binary64, one partial per column in slot `slot`.  The
+// tile's rows in binary64, one partial per column in slot `slot`.  Both
+// factors are FP32, so their product is exact in binary64 and a fused
+// multiply-add rounds exactly as the product-then-sum does.  The
 // operands are staged in LDS so the gathers hit LDS: at pre when the K loop
 // already issued them there, else into the ring (ring_chunks 16-byte chunks,
 // free once every wave has left the K loop) if they fit, else the gathers go
@@ -374,10 +376,10 @@ __device__ __forceinline__ void pipe_epilogue(const MfmaJob &J, f32x16 (&acc)[RO
                         const uint2 k4 = *(const uint2 *)(lk + kb + a * 32 + 8 * j);
                         const int k0 = (int)(k4.x & 0xFFFFu), k1 = (int)(k4.x >> 16);
                         const int k2 = (int)(k4.y & 0xFFFFu), k3 = (int)(k4.y >> 16);
-                        part[0] += (double)acc[a][b][4 * j + 0] * (double)lch[cb + k0 * p];
-                        part[1] += (double)acc[a][b][4 * j + 1] * (double)lch[cb + k1 * p];
-                        part[2] += (double)acc[a][b][4 * j + 2] * (double)lch[cb + k2 * p];
-                        part[3] += (double)acc[a][b][4 * j + 3] * (double)lch[cb + k3 * p];
+                        part[0] = __builtin_fma((double)acc[a][b][4 * j + 0], (double)lch[cb + k0 * p], part[0]);
+                        part[1] = __builtin_fma((double)acc[a][b][4 * j + 1], (double)lch[cb + k1 * p], part[1]);
+                        part[2] = __builtin_fma((double)acc[a][b][4 * j + 2], (double)lch[cb + k2 * p], part[2]);
+                        part[3] = __builtin_fma((double)acc[a][b][4 * j + 3], (double)lch[cb + k3 * p], part[3]);
                     }
                 }
             } else {
@@ -388,7 +390,7 @@ __device__ __forceinline__ void pipe_epilogue(const MfmaJob &J, f32x16 (&acc)[RO
 #pragma unroll
                     for (int v = 0; v < 16; ++v) {
                         const int i = M0 + a * 32 + 8 * (v >> 2) + 4 * half + (v & 3);
-                        if (i < n) part[v & 3] += (double)acc[a][b][v] * (double)ch[kr[i] * p];
+                        if (i < n) part[v & 3] = __builtin_fma((double)acc[a][b][v], (double)ch[kr[i] * p], part[v & 3]);
                     }
                 }
             }
