@@ -236,6 +236,11 @@ __device__ __forceinline__ u32x4 ds_read16(uint32_t addr)
     return v;
 }
 __device__ __forceinline__ void pin(u32x4 &v) { asm volatile("" : "+v"(v)); }
+// An FP32 read from LDS byte address addr.
+__device__ __forceinline__ float lds_f32(uint32_t addr)
+{
+    return *(const __attribute__((address_space(3))) float *)(uintptr_t)addr;
+}
 
 // One context's operands for the batched kernel (also one entry of a grouped
 // launch over several contexts).
@@ -349,6 +354,7 @@ __device__ __forceinline__ void pipe_epilogue(const MfmaJob &J, f32x16 (&acc)[RO
     // negative intermediate would leave the LDS aperture of a flat address.
     uint16_t *lk = (uint16_t *)sd;                       // [ind][row - M0]
     float *lch = (float *)(sd + nind * (MT / 8));        // [ind][k][l]
+    const uint32_t lch_addr = staged ? (uint32_t)(uintptr_t)(lds_void *)lch : 0u, p4 = 4u * (uint32_t)p;
     if (staged) {
         vm_wait<0>();
         wg_barrier();   // every wave's copies have landed
@@ -367,20 +373,26 @@ __device__ __forceinline__ void pipe_epilogue(const MfmaJob &J, f32x16 (&acc)[RO
         if (col[b] < NS) {
             const int s = col[b] / p;
             if (staged) {
-                // rows a*32 + 8j + 4*half + t (t = 0..3) are 4 consecutive positions
-                const int kb = (s - s_lo) * MT + 4 * half, cb = (s - s_lo) * p * p + (int)lq[b];
+                // rows a*32 + 8j + 4*half + t (t = 0..3) are 4 consecutive
+                // positions; the factor C[h_k][h_l] is at LDS byte address
+                // k*4p + cb, one full-rate 24-bit multiply-add (k*4p < 2^24)
+                const int kb = (s - s_lo) * MT + 4 * half;
+                const uint32_t cb = lch_addr + 4u * (uint32_t)((s - s_lo) * p * p + (int)lq[b]);
 #pragma unroll
                 for (int a = 0; a < ROWB; ++a) {
+                    // the row block's 16 factors are all read before its products
+                    float f[16];
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
                         const uint2 k4 = *(const uint2 *)(lk + kb + a * 32 + 8 * j);
-                        const int k0 = (int)(k4.x & 0xFFFFu), k1 = (int)(k4.x >> 16);
-                        const int k2 = (int)(k4.y & 0xFFFFu), k3 = (int)(k4.y >> 16);
-                        part[0] = __builtin_fma((double)acc[a][b][4 * j + 0], (double)lch[cb + k0 * p], part[0]);
-                        part[1] = __builtin_fma((double)acc[a][b][4 * j + 1], (double)lch[cb + k1 * p], part[1]);
-                        part[2] = __builtin_fma((double)acc[a][b][4 * j + 2], (double)lch[cb + k2 * p], part[2]);
-                        part[3] = __builtin_fma((double)acc[a][b][4 * j + 3], (double)lch[cb + k3 * p], part[3]);
+                        f[4 * j + 0] = lds_f32(__umul24(k4.x & 0xFFFFu, p4) + cb);
+                        f[4 * j + 1] = lds_f32(__umul24(k4.x >> 16, p4) + cb);
+                        f[4 * j + 2] = lds_f32(__umul24(k4.y & 0xFFFFu, p4) + cb);
+                        f[4 * j + 3] = lds_f32(__umul24(k4.y >> 16, p4) + cb);
                     }
+#pragma unroll
+                    for (int v = 0; v < 16; ++v)
+                        part[v & 3] = __builtin_fma((double)acc[a][b][v], (double)f[v], part[v & 3]);
                 }
             } else {
                 const uint16_t *kr = kidx + (size_t)s * n_pad;
