@@ -27,25 +27,14 @@ __device__ inline void compact_candidates(const int32_t *__restrict__ cand, cons
                                           int32_t *__restrict__ extra_r, int32_t *__restrict__ extra_c,
                                           int32_t *__restrict__ nextra)
 {
-    __shared__ int part[1024], part2[1024];
     const int tid = threadIdx.x, nt = blockDim.x;
     const int chunk = (R + nt - 1) / nt;
     const int r0 = min(R, tid * chunk), r1 = min(R, r0 + chunk);
     int sum = 0;
     for (int r = r0; r < r1; ++r) sum += cand_cnt[r];
-    part[tid] = sum;
-    __syncthreads();
-    if (tid == 0) {
-        int acc = 0;
-        for (int t = 0; t < nt; ++t) {
-            const int v = part[t];
-            part[t] = acc;
-            acc += v;
-        }
-        *total = min(acc, tot);
-    }
-    __syncthreads();
-    int off = part[tid], ex = 0;
+    int acc;
+    int off = block_exclusive_scan(sum, &acc), ex = 0;
+    if (tid == 0) *total = min(acc, tot);
     for (int r = r0; r < r1; ++r) {
         const int cnt = cand_cnt[r];
         const int h = max(0, min(cnt, tot - off));
@@ -58,19 +47,8 @@ __device__ inline void compact_candidates(const int32_t *__restrict__ cand, cons
         off += cnt;
         ex += cnt - h;
     }
-    part2[tid] = ex;
-    __syncthreads();
-    if (tid == 0) {
-        int acc = 0;
-        for (int t = 0; t < nt; ++t) {
-            const int v = part2[t];
-            part2[t] = acc;
-            acc += v;
-        }
-        *nextra = acc;
-    }
-    __syncthreads();
-    int eo = part2[tid];
+    int eo = block_exclusive_scan(ex, &acc);
+    if (tid == 0) *nextra = acc;
     for (int r = r0; r < r1; ++r)
         for (int c = handled[r]; c < cand_cnt[r]; ++c) {
             extra_r[eo] = r;
@@ -122,21 +100,11 @@ __device__ __forceinline__ void select1_body(const SelState &S, const double *__
         if (same_as_anc) lb = ub = fa;
     }
     // (min ub, index) over the island; exact mode: (min f, lowest j)
-    ArgminScratch &sc = argmin_scratch();
-    sc.v[tid] = ub;
-    sc.i[tid] = live ? tid : -1;
-    __syncthreads();
-    for (int w = nt / 2; w > 0; w >>= 1) {
-        if (tid < w && sc.i[tid + w] >= 0 && better(sc.v[tid + w], sc.i[tid + w], sc.v[tid], sc.i[tid])) {
-            sc.v[tid] = sc.v[tid + w];
-            sc.i[tid] = sc.i[tid + w];
-        }
-        __syncthreads();
-    }
-    const double U = sc.v[0];
+    double U;
+    const int jbest = block_argmin_entries(ub, live ? tid : -1, &U);
     if (S.exact) {
         if (tid == 0) {
-            const int j = sc.i[0];
+            const int j = jbest;
             sh_best = (!S.elitist || U < fa) ? j : -1;
             cand_cnt[r] = 0;
         }

@@ -36,36 +36,16 @@ __device__ inline bool last_block(int *counter, int nblocks)
     return is_last != 0;
 }
 
-// LDS of the island reduction of the first selection stage.
-struct ArgminScratch {
-    double v[1024];
-    int i[1024];
-};
-__device__ inline ArgminScratch &argmin_scratch()
-{
-    __shared__ ArgminScratch s;
-    return s;
-}
-
-// Block-wide (value, index) argmin over v[0..count) read through f(i);
-// returns the index (-1 if count == 0).  Ties go to the lower index; any
-// workgroup size up to 1024.  (value, index) pairs are totally ordered, so the
-// order of the lane and wave merges does not change the result.
-template <typename F>
-__device__ inline int block_argmin(int count, F f, double *out_value)
+// Block-wide (value, index) argmin of one entry per thread (index < 0: no
+// entry); returns the index (-1 if no thread has one).  Ties go to the lower
+// index; any workgroup size up to 1024.  (value, index) pairs are totally
+// ordered, so the order of the lane and wave merges does not change the
+// result.
+__device__ inline int block_argmin_entries(double bv, int bi, double *out_value)
 {
     __shared__ double wv[16];
     __shared__ int wi[16];
     const int tid = threadIdx.x, nt = blockDim.x;
-    double bv = 0.0;
-    int bi = -1;
-    for (int i = tid; i < count; i += nt) {
-        const double v = f(i);
-        if (better(v, i, bv, bi)) {
-            bv = v;
-            bi = i;
-        }
-    }
     for (int off = 32; off > 0; off >>= 1) {
         const double ov = __shfl_xor(bv, off);
         const int oi = __shfl_xor(bi, off);
@@ -94,6 +74,48 @@ __device__ inline int block_argmin(int count, F f, double *out_value)
     if (out_value) *out_value = wv[0];
     __syncthreads();
     return r;
+}
+
+// Block-wide (value, index) argmin over v[0..count) read through f(i);
+// returns the index (-1 if count == 0).
+template <typename F>
+__device__ inline int block_argmin(int count, F f, double *out_value)
+{
+    const int tid = threadIdx.x, nt = blockDim.x;
+    double bv = 0.0;
+    int bi = -1;
+    for (int i = tid; i < count; i += nt) {
+        const double v = f(i);
+        if (better(v, i, bv, bi)) {
+            bv = v;
+            bi = i;
+        }
+    }
+    return block_argmin_entries(bv, bi, out_value);
+}
+
+// Exclusive prefix sum of one value per thread in thread order; *sum gets
+// the workgroup's total.  Any workgroup size up to 1024.
+__device__ inline int block_exclusive_scan(int v, int *sum)
+{
+    __shared__ int ws[16];
+    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6;
+    int x = v;   // inclusive scan within the wave
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    __syncthreads();   // ws free from a previous call
+    if (lane == 63 || tid == nt - 1) ws[wave] = x;
+    __syncthreads();
+    int base = 0, tot = 0;
+    for (int w = 0; w < (nt + 63) / 64; ++w) {
+        const int t = ws[w];
+        base += w < wave ? t : 0;
+        tot += t;
+    }
+    *sum = tot;
+    return base + x - v;
 }
 
 struct SelState {
