@@ -830,7 +830,21 @@ __device__ __forceinline__ void finalize_body(const double *__restrict__ partial
     const size_t NS = (size_t)count * p;
     const double *ps = partial + (size_t)s * p;
     double v = 0.0;
-    for (int e = lane; e < len; e += 64) v += ps[(size_t)(e / p) * NS + e % p];
+    constexpr int MAXIT = 8;
+    if (len <= 64 * MAXIT) {
+        // every load of the lane issued before its sum (the same sum)
+        double x[MAXIT];
+#pragma unroll
+        for (int it = 0; it < MAXIT; ++it) {
+            const int e = lane + 64 * it;
+            x[it] = e < len ? ps[(size_t)(e / p) * NS + e % p] : 0.0;
+        }
+#pragma unroll
+        for (int it = 0; it < MAXIT; ++it)
+            if (lane + 64 * it < len) v += x[it];
+    } else {
+        for (int e = lane; e < len; e += 64) v += ps[(size_t)(e / p) * NS + e % p];
+    }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
     if (lane == 0) {
