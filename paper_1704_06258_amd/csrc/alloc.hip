@@ -14,6 +14,7 @@
 // Ch32[s][k][l] = C[h_k][h_l] used by the batched kernel's epilogue (the
 // shortest-path distance Ctr[h_k][h_l] instead under multi-hop routing).
 #include "kernels.hpp"
+#include "ga_ops_dev.hpp"
 
 namespace hubga {
 
@@ -38,10 +39,12 @@ struct AllocLds {
     int cnt[kMaxP];
     __align__(4) uint8_t pos[kMaxN];   // position of node i in the hub list, 0xFF for spokes
     double red_c[4], red_d[4];
+    int lists[3][128];   // the child built here (ops): its parents, then the child
 };
 
 template <typename CT, int V>
-__device__ __forceinline__ void alloc_body(AllocLds &L, const int32_t *__restrict__ hubs, int count, int n, int n_pad, int p,
+__device__ __forceinline__ void alloc_body(AllocLds &L, const AllocOps &ops, const int32_t *hubs, int count, int n,
+                                           int n_pad, int p,
                                            const CT *__restrict__ Ct, const float *__restrict__ Ct32,
                                            const double *__restrict__ O, const double *__restrict__ D,
                                            uint16_t *__restrict__ kidx, double *__restrict__ parts,
@@ -64,11 +67,16 @@ __device__ __forceinline__ void alloc_body(AllocLds &L, const int32_t *__restric
     const int s = (blk & 7) * per + (blk >> 3);
     if (s >= count) return;
     const int tid = threadIdx.x;
-    const int32_t *__restrict__ hrow = hubs + (size_t)s * p;
-    const int hk = tid < p ? hrow[tid] : n;   // in flight while LDS is cleared
+    const bool build = ops.anc != nullptr;
+    // the hub list: loaded (in flight while LDS is cleared), or first built
+    // here by wave 0 (the generation's operators for child s)
+    int hk = !build && tid < p ? hubs[(size_t)s * p + tid] : n;
+    if (build && tid < 64)
+        ga_child_wave(ops.anc, ops.children, (uint64_t)*ops.gen, n, p, ops.m, ops.seed, s, &L.lists[0][0]);
     for (int e = tid; e < (n + 3) / 4; e += 256) ((uint32_t *)sh_pos)[e] = 0xFFFFFFFFu;
     if (tid < kMaxP) sh_cnt[tid] = 0;
     __syncthreads();
+    if (build && tid < p) hk = L.lists[2][tid];
     if (tid < p) {
         sh_h[tid] = hk;
         sh_pos[hk] = (uint8_t)tid;
@@ -174,9 +182,9 @@ __device__ __forceinline__ void alloc_body(AllocLds &L, const int32_t *__restric
                 c32[t] = Ct32[(size_t)i * n + i];
             } else if (at_min[t] > 1) {
                 int b = 0;
-                CT be = Ct[(size_t)hrow[0] * n + i];
+                CT be = Ct[(size_t)sh_h[0] * n + i];
                 for (int k = 1; k < p; ++k) {
-                    const CT v = Ct[(size_t)hrow[k] * n + i];
+                    const CT v = Ct[(size_t)sh_h[k] * n + i];
                     if (v < be) {
                         be = v;
                         b = k;
@@ -312,7 +320,7 @@ hipError_t launch_copy_clamp(const int32_t *src, int32_t *dst, int total, int n,
 }
 
 template <typename CT, int V>
-__global__ __launch_bounds__(256, 8) void k_alloc(const int32_t *__restrict__ hubs, int count, int n, int n_pad, int p,
+__global__ __launch_bounds__(256, 8) void k_alloc(AllocOps ops, const int32_t *hubs, int count, int n, int n_pad, int p,
                                                const CT *__restrict__ Ct, const float *__restrict__ Ct32,
                                                const double *__restrict__ O, const double *__restrict__ D,
                                                uint16_t *__restrict__ kidx, double *__restrict__ parts,
@@ -320,7 +328,7 @@ __global__ __launch_bounds__(256, 8) void k_alloc(const int32_t *__restrict__ hu
                                                const double *__restrict__ Ctr)
 {
     __shared__ AllocLds L;
-    alloc_body<CT, V>(L, hubs, count, n, n_pad, p, Ct, Ct32, O, D, kidx, parts, cmax, Ch32, want_sums, Ctr, blockIdx.x);
+    alloc_body<CT, V>(L, ops, hubs, count, n, n_pad, p, Ct, Ct32, O, D, kidx, parts, cmax, Ch32, want_sums, Ctr, blockIdx.x);
 }
 
 // Grouped: the children of every context, with their sums and hub tables
@@ -337,17 +345,17 @@ __global__ __launch_bounds__(256, 8) void k_alloc_group(const GroupHdr *__restri
     __shared__ AllocLds L;
     if (d.c_f32) {
         if (v4)
-            alloc_body<float, 4>(L, P.hubs, d.S, d.n, d.n_pad, d.p, (const float *)P.Ct, P.Ct32, P.O, P.D, P.kidx,
+            alloc_body<float, 4>(L, AllocOps{}, P.hubs, d.S, d.n, d.n_pad, d.p, (const float *)P.Ct, P.Ct32, P.O, P.D, P.kidx,
                                  P.parts, P.cmax, P.Ch32, 1, P.Ctr, blk);
         else
-            alloc_body<float, 1>(L, P.hubs, d.S, d.n, d.n_pad, d.p, (const float *)P.Ct, P.Ct32, P.O, P.D, P.kidx,
+            alloc_body<float, 1>(L, AllocOps{}, P.hubs, d.S, d.n, d.n_pad, d.p, (const float *)P.Ct, P.Ct32, P.O, P.D, P.kidx,
                                  P.parts, P.cmax, P.Ch32, 1, P.Ctr, blk);
     } else {
         if (v4)
-            alloc_body<double, 4>(L, P.hubs, d.S, d.n, d.n_pad, d.p, (const double *)P.Ct, P.Ct32, P.O, P.D, P.kidx,
+            alloc_body<double, 4>(L, AllocOps{}, P.hubs, d.S, d.n, d.n_pad, d.p, (const double *)P.Ct, P.Ct32, P.O, P.D, P.kidx,
                                   P.parts, P.cmax, P.Ch32, 1, P.Ctr, blk);
         else
-            alloc_body<double, 1>(L, P.hubs, d.S, d.n, d.n_pad, d.p, (const double *)P.Ct, P.Ct32, P.O, P.D, P.kidx,
+            alloc_body<double, 1>(L, AllocOps{}, P.hubs, d.S, d.n, d.n_pad, d.p, (const double *)P.Ct, P.Ct32, P.O, P.D, P.kidx,
                                   P.parts, P.cmax, P.Ch32, 1, P.Ctr, blk);
     }
 }
@@ -355,14 +363,14 @@ __global__ __launch_bounds__(256, 8) void k_alloc_group(const GroupHdr *__restri
 int alloc_blocks(int count) { return ((count + 7) / 8) * 8; }
 
 hipError_t launch_alloc(const DevPtrs &P, const Dims &d, const int32_t *hubs, int count, uint16_t *kidx,
-                        int want_sums, int want_ch, hipStream_t st)
+                        int want_sums, int want_ch, hipStream_t st, const AllocOps &ops)
 {
     if (count <= 0) return hipSuccess;
     float *ch = want_ch ? P.Ch32 : nullptr;
     const unsigned grid = (unsigned)alloc_blocks(count);
     const bool v4 = alloc_vec4(d.n, P.Ct32, P.O, P.D, kidx);
 #define HUBGA_ALLOC(CT, V)                                                                                      \
-    k_alloc<CT, V><<<grid, 256, 0, st>>>(hubs, count, d.n, d.n_pad, d.p, (const CT *)P.Ct, P.Ct32, P.O, P.D, kidx, \
+    k_alloc<CT, V><<<grid, 256, 0, st>>>(ops, hubs, count, d.n, d.n_pad, d.p, (const CT *)P.Ct, P.Ct32, P.O, P.D, kidx, \
                                          P.parts, P.cmax, ch, want_sums, P.Ctr)
     if (d.c_f32) {
         if (v4) HUBGA_ALLOC(float, 4);

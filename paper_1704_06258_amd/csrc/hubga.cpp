@@ -305,28 +305,30 @@ ga_status ensure_w_layout(ga_ctx *ctx, int cfg)
 }
 
 // Evaluate `count` sorted hub sets at `hubs` (device) into P.cost / P.parts /
-// P.eps, hub positions into `kidx`, on stream s.
-ga_status run_eval(ga_ctx *ctx, const int32_t *hubs, int count, uint16_t *kidx, hipStream_t s)
+// P.eps, hub positions into `kidx`, on stream s; with ops.anc set, the
+// allocation kernel first builds the sets (the generation's operators).
+ga_status run_eval(ga_ctx *ctx, const int32_t *hubs, int count, uint16_t *kidx, hipStream_t s,
+                   const AllocOps &ops = AllocOps{})
 {
     const Dims &d = ctx->d;
     const DevPtrs &P = ctx->P;
     hipEvent_t a, b;
     prof_events(ctx, &a, &b);
     if (d.prec == kFP64) {
-        HIPCHK(launch_alloc(P, d, hubs, count, kidx, 0, 0, s));
+        HIPCHK(launch_alloc(P, d, hubs, count, kidx, 0, 0, s, ops));
         if (a) HIPCHK(hipEventRecord(a, s));
         HIPCHK(launch_eval_exact(P, d, hubs, kidx, count, P.cost, P.parts, P.eps, s));
         if (b) HIPCHK(hipEventRecord(b, s));
     } else if (d.prec == kFP32 && d.kern == GA_KERN_BATCHED) {
-        HIPCHK(launch_alloc(P, d, hubs, count, kidx, 1, 1, s));
+        HIPCHK(launch_alloc(P, d, hubs, count, kidx, 1, 1, s, ops));
         HIPCHK(launch_eval_vec(P, d, kidx, count, s, a, b));
     } else if (d.prec == kFP32) {
-        HIPCHK(launch_alloc(P, d, hubs, count, kidx, 1, 0, s));
+        HIPCHK(launch_alloc(P, d, hubs, count, kidx, 1, 0, s, ops));
         if (a) HIPCHK(hipEventRecord(a, s));
         HIPCHK(launch_eval_fp32(P, d, hubs, kidx, count, s));
         if (b) HIPCHK(hipEventRecord(b, s));
     } else {
-        HIPCHK(launch_alloc(P, d, hubs, count, kidx, 1, 1, s));
+        HIPCHK(launch_alloc(P, d, hubs, count, kidx, 1, 1, s, ops));
         HIPCHK(launch_eval_split(P, d, kidx, count, s, a, b));
     }
     return GA_OK;
@@ -337,13 +339,19 @@ ga_status run_eval(ga_ctx *ctx, const int32_t *hubs, int count, uint16_t *kidx)
     return run_eval(ctx, hubs, count, kidx, ctx->st);
 }
 
-// One generation on stream s: operators, evaluation, selection.
+// One generation on stream s: operators (in the allocation kernel, one
+// child per workgroup), evaluation, selection.
 ga_status run_generation(ga_ctx *ctx, hipStream_t s)
 {
     const Dims &d = ctx->d;
     const DevPtrs &P = ctx->P;
-    HIPCHK(launch_ga_ops(P, d, s));
-    ga_status st = run_eval(ctx, P.hubs, d.S, P.kidx, s);
+    AllocOps ops;
+    ops.anc = P.anc;
+    ops.children = P.hubs;
+    ops.gen = P.gen;
+    ops.seed = d.seed;
+    ops.m = d.m;
+    ga_status st = run_eval(ctx, P.hubs, d.S, P.kidx, s, ops);
     if (st != GA_OK) return st;
     HIPCHK(launch_select(P, d, d.prec == kFP64, s));
     return GA_OK;

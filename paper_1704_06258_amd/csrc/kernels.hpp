@@ -11,9 +11,18 @@ hipError_t launch_w_layout(const DevPtrs &P, const Dims &d, int layout, hipStrea
 hipError_t launch_shortest_paths(const DevPtrs &P, const Dims &d, hipStream_t st);
 hipError_t launch_middle_nodes(const DevPtrs &P, const Dims &d, int32_t *hubs_out, uint8_t *scratch, hipStream_t st);
 
-// nearest-hub allocation (alloc.hip)
+// nearest-hub allocation (alloc.hip); with ops.anc set, each workgroup first
+// builds its child (the generation's operators) into ops.children and
+// allocates that
+struct AllocOps {
+    const int32_t *anc = nullptr;
+    int32_t *children = nullptr;
+    const int64_t *gen = nullptr;
+    uint64_t seed = 0;
+    int m = 0;
+};
 hipError_t launch_alloc(const DevPtrs &P, const Dims &d, const int32_t *hubs, int count, uint16_t *kidx,
-                        int want_sums, int want_ch, hipStream_t st);
+                        int want_sums, int want_ch, hipStream_t st, const AllocOps &ops = AllocOps{});
 hipError_t launch_copy_clamp(const int32_t *src, int32_t *dst, int total, int n, hipStream_t st);
 int alloc_blocks(int count);
 hipError_t launch_alloc_group(const GroupHdr *hdr, const TickJob *jobs, int njobs, int blocks, hipStream_t st);
@@ -71,7 +80,6 @@ hipError_t launch_enum_select(const DevPtrs &P, const Dims &d, int64_t first, in
 hipError_t prepare_enum_kernels(int max_lds);
 
 // GA (ga_ops.hip, select.hip)
-hipError_t launch_ga_ops(const DevPtrs &P, const Dims &d, hipStream_t st);
 int ga_ops_blocks(const Dims &d);
 hipError_t launch_ga_ops_group(const GroupHdr *hdr, const TickJob *jobs, int njobs, int blocks, hipStream_t st);
 int select_threads(int m);
