@@ -21,16 +21,6 @@ namespace hubga {
 constexpr int kScanHubs = 4;    // hubs per scan chunk
 constexpr int kScanNodes = 4;   // nodes per lane scanned together
 
-// Workgroup blk (of a grid of alloc_blocks(count)) of one context: individual
-// s = the workgroup's place in XCD-major order.  A lane takes kScanNodes nodes
-// at once and scans the hubs in chunks of kScanHubs: the chunk's distances for
-// all its nodes are loaded together, then merged (loads past n re-read valid
-// addresses and are not used).  With V = 4 (n a multiple of 4) the lane's
-// nodes are consecutive, i = g0 + 4*tid + t, and each hub row is read with one
-// 16-byte load; with V = 1 they are i = g0 + t*256 + tid, one 4-byte load each.
-// Few registers, so many workgroups share a CU and hide each other's load
-// latency.  A node-to-position table in LDS answers "is node i a hub" with one
-// read.
 // LDS of one workgroup; the kernels declare it once, so a kernel that
 // instantiates several forms of the body still holds one copy.
 struct AllocLds {
@@ -42,6 +32,18 @@ struct AllocLds {
     int lists[3][128];   // the child built here (ops): its parents, then the child
 };
 
+// Workgroup blk (of a grid of alloc_blocks(count)) of one context: individual
+// s = the workgroup's place in XCD-major order.  A lane takes kScanNodes nodes
+// at once and scans the hubs in chunks of kScanHubs: the chunk's distances for
+// all its nodes are loaded together, then merged (loads past n re-read valid
+// addresses and are not used).  With V = 4 (n a multiple of 4) the lane's
+// nodes are consecutive, i = g0 + 4*tid + t, and each hub row is read with one
+// 16-byte load; with V = 1 they are i = g0 + t*256 + tid, one 4-byte load each.
+// Few registers, so many workgroups share a CU and hide each other's load
+// latency.  A node-to-position table in LDS answers "is node i a hub" with one
+// read.  With ops.anc set (one generation of a context), wave 0 first builds
+// child s from its island's ancestor (the operators, ga_child_wave) while the
+// other waves clear that table.
 template <typename CT, int V>
 __device__ __forceinline__ void alloc_body(AllocLds &L, const AllocOps &ops, const int32_t *hubs, int count, int n,
                                            int n_pad, int p,
