@@ -70,6 +70,10 @@ __device__ __forceinline__ void alloc_body(AllocLds &L, const AllocOps &ops, con
     if (s >= count) return;
     const int tid = threadIdx.x;
     const bool build = ops.anc != nullptr;
+    if (build && s == 0 && tid == 0 && ops.slot_counters[0]) {
+        *ops.slot_counters[0] = 0;   // candidate slots of this generation's selection
+        *ops.slot_counters[1] = 0;
+    }
     // the hub list: loaded (in flight while LDS is cleared), or first built
     // here by wave 0 (the generation's operators for child s)
     int hk = !build && tid < p ? hubs[(size_t)s * p + tid] : n;

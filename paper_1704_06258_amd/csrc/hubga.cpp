@@ -351,9 +351,11 @@ ga_status run_generation(ga_ctx *ctx, hipStream_t s)
     ops.gen = P.gen;
     ops.seed = d.seed;
     ops.m = d.m;
+    ops.slot_counters[0] = P.total;
+    ops.slot_counters[1] = P.nextra;
     ga_status st = run_eval(ctx, P.hubs, d.S, P.kidx, s, ops);
     if (st != GA_OK) return st;
-    HIPCHK(launch_select(P, d, d.prec == kFP64, s));
+    HIPCHK(launch_select(P, d, d.prec == kFP64, s, 1));
     return GA_OK;
 }
 

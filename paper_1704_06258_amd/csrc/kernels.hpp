@@ -20,6 +20,7 @@ struct AllocOps {
     const int64_t *gen = nullptr;
     uint64_t seed = 0;
     int m = 0;
+    int32_t *slot_counters[2] = {nullptr, nullptr};   // zeroed by the workgroup of individual 0
 };
 hipError_t launch_alloc(const DevPtrs &P, const Dims &d, const int32_t *hubs, int count, uint16_t *kidx,
                         int want_sums, int want_ch, hipStream_t st, const AllocOps &ops = AllocOps{});
@@ -85,7 +86,7 @@ hipError_t launch_ga_ops_group(const GroupHdr *hdr, const TickJob *jobs, int njo
 int select_threads(int m);
 hipError_t launch_select1_group(const GroupHdr *hdr, const TickJob *jobs, int njobs, int blocks, int threads,
                                 hipStream_t st);
-hipError_t launch_select(const DevPtrs &P, const Dims &d, int exact, hipStream_t st);
+hipError_t launch_select(const DevPtrs &P, const Dims &d, int exact, hipStream_t st, int reserve = 0);
 hipError_t launch_init_state(const DevPtrs &P, const Dims &d, hipStream_t st);
 
 }  // namespace hubga

@@ -804,7 +804,7 @@ template <typename CT, typename WT, bool WIDE>
 __device__ __forceinline__ void rc_body(const DevPtrs &P, const Dims &d, const RcView &V, char *smem, int blk, int nblk)
 {
     __shared__ int sh_h[kMaxP];
-    const int total = *P.total, nextra = *P.nextra, units = total + nextra;
+    const int total = min(*P.total, d.tot), nextra = *P.nextra, units = total + nextra;
     if (rc_wide(total, d.p) != WIDE) return;
     if (units == 0) {
         if (blk == 0 && V.decide) decide_generation(make_sel_state(P, d), P.choice);
@@ -917,7 +917,7 @@ __device__ inline int rc_wide_columns(int n, int total)
 template <bool WIDE>
 __device__ inline int rc_items(const TickJob &J)
 {
-    const int total = *J.P.total;
+    const int total = min(*J.P.total, J.d.tot);
     if (rc_wide(total, J.d.p) != WIDE) return 0;
     const int u = (WIDE ? rc_wide_columns(J.d.n, total) + total : total * rc_slot_items(J.d.n, false)) + *J.P.nextra;
     return u > 0 ? u : 1;
@@ -929,7 +929,7 @@ __device__ __forceinline__ void rc_group_item(const TickJob &J, int item, char *
     const DevPtrs &P = J.P;
     const Dims &d = J.d;
     const RcView V = rc_generation_view(P, d);
-    const int total = *P.total, units = total + *P.nextra;
+    const int total = min(*P.total, d.tot), units = total + *P.nextra;
     const int slot_items = WIDE ? rc_wide_columns(d.n, total) + total : total * rc_slot_items(d.n, false);
     if (units == 0) {
         decide_generation(make_sel_state(P, d), P.choice);

@@ -66,10 +66,11 @@ __device__ __forceinline__ void select1_body(const SelState &S, const double *__
                                              int32_t *__restrict__ slot_s,
                                              int32_t *__restrict__ handled, int32_t *__restrict__ total,
                                              int32_t *__restrict__ extra_r, int32_t *__restrict__ extra_c,
-                                             int32_t *__restrict__ nextra, int *__restrict__ sync, int blk, int nblk)
+                                             int32_t *__restrict__ nextra, int *__restrict__ sync, int blk, int nblk,
+                                             bool reserve = false)
 {
     __shared__ int wave_cnt[16];
-    __shared__ int sh_best;
+    __shared__ int sh_best, sh_res[3];
     const int m = S.m, p = S.p;
     const int r = blk, tid = threadIdx.x, nt = blockDim.x;
     const int s = r * m + tid;
@@ -133,6 +134,33 @@ __device__ __forceinline__ void select1_body(const SelState &S, const double *__
             int tt = 0;
             for (int w = 0; w < (nt + 63) / 64; ++w) tt += wave_cnt[w];
             cand_cnt[r] = tt;
+            if (reserve) {
+                // the island's slots [o, o + tt) from the shared counter (zeroed
+                // at the start of the generation); past tot they are extras
+                const int o = tt > 0 ? atomicAdd(total, tt) : 0;
+                const int h = max(0, min(tt, tot - o));
+                handled[r] = h;
+                sh_res[0] = o;
+                sh_res[1] = h;
+                sh_res[2] = tt > h ? atomicAdd(nextra, tt - h) : 0;
+            }
+        }
+        if (reserve) {
+            // slots in any island order: each candidate's exact cost is its
+            // own, so which slot or extra computes it changes no result
+            __syncthreads();
+            if (is_cand) {
+                const int c = off + below, o = sh_res[0], h = sh_res[1];
+                if (c < h) {
+                    slot_r[o + c] = r;
+                    slot_c[o + c] = c;
+                    slot_s[o + c] = s;
+                } else {
+                    extra_r[sh_res[2] + c - h] = r;
+                    extra_c[sh_res[2] + c - h] = c;
+                }
+            }
+            return;
         }
     }
     if (!last_block(sync, nblk)) return;
@@ -150,10 +178,10 @@ __global__ __launch_bounds__(1024) void k_select1(SelState S, const double *__re
                                                   int32_t *__restrict__ slot_s,
                                                   int32_t *__restrict__ handled, int32_t *__restrict__ total,
                                                   int32_t *__restrict__ extra_r, int32_t *__restrict__ extra_c,
-                                                  int32_t *__restrict__ nextra, int *__restrict__ sync)
+                                                  int32_t *__restrict__ nextra, int *__restrict__ sync, int reserve)
 {
     select1_body(S, cost, eps, parts, cand, cand_cnt, tot, slot_r, slot_c, slot_s, handled, total, extra_r, extra_c,
-                 nextra, sync, blockIdx.x, gridDim.x);
+                 nextra, sync, blockIdx.x, gridDim.x, reserve != 0);
 }
 
 __global__ __launch_bounds__(1024) void k_select1_group(const GroupHdr *__restrict__ hdr,
@@ -209,13 +237,16 @@ int select_threads(int m)
 
 // Selection and the end of the generation: k_select1 (with the global step
 // for exact costs), else k_select1 -> k_recheck (exact re-evaluation of the
-// candidates, island decisions, global step).
-hipError_t launch_select(const DevPtrs &P, const Dims &d, int exact, hipStream_t st)
+// candidates, island decisions, global step).  reserve: the candidates take
+// their slots from the counters P.total and P.nextra, which the generation's
+// allocation kernel zeroed, instead of from the last workgroup's compaction.
+hipError_t launch_select(const DevPtrs &P, const Dims &d, int exact, hipStream_t st, int reserve)
 {
     const int bt = select_threads(d.m);
     const SelState S = make_sel_state(P, d);
     k_select1<<<d.R, bt, 0, st>>>(S, P.cost, P.eps, P.parts, P.cand, P.cand_cnt, d.tot, P.slot_r, P.slot_c,
-                                  P.slot_s, P.handled, P.total, P.extra_r, P.extra_c, P.nextra, P.sync);
+                                  P.slot_s, P.handled, P.total, P.extra_r, P.extra_c, P.nextra, P.sync,
+                                  exact ? 0 : reserve);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || exact) return e;
     return launch_recheck(P, d, st);
